@@ -1,0 +1,215 @@
+/*
+ * skipm — sketch-preconditioned infeasible interior-point LP solver for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Solves  min c^T x  s.t.  A x = b, x >= 0   (primal, eq. "primal" of Sec. 1)
+ * and     max b^T y  s.t.  A^T y + s = c, s >= 0   (dual, eq. "dual")
+ * for short-and-fat A (m << n) with the infeasible long-step path-following
+ * IPM of Alg. 2 (Sec. 4).  Every iteration solves the normal equations
+ * A D^2 A^T dy = p (eq. "normal", p of eq. "pdef", D^2 = X S^{-1}) by conjugate
+ * gradients preconditioned with Q = (A D W)(A D W)^T (eq. "pdprecond"), where W
+ * is a sparse embedding (Sec. 2), then applies the correction vector v of eq.
+ * "compv" so that the residuals stay on the segment between r^0 and 0
+ * (eq. "addl", Lemma 3), and takes the step of Alg. 2 steps (e)-(g).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SKIPM_OK (0) or a negative SKIPM_E* code; nothing throws.
+ *    skipm_last_error() returns a message for the last failing call on the
+ *    calling thread.
+ *  - Array arguments are DEVICE pointers (HIP device memory of the current
+ *    device) unless the comment says "host".  The library never frees caller
+ *    memory.
+ *  - Work is ordered on the given stream (NULL = the default stream).  Calls
+ *    that return host info (ipm_step, lp_solve, pcg_solve) synchronise that
+ *    stream before returning.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - All floating-point state of the IPM (x, y, s, residuals, p, v, the step)
+ *    is FP64.  SKIPM_PREC_MIXED runs only the preconditioner build and the CG
+ *    matrix-vector products in reduced precision (FP32 accumulate).
+ */
+#ifndef SKIPM_H
+#define SKIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SKIPM_OK        0
+#define SKIPM_EINVAL   (-1)  /* bad argument (sizes, null pointers, parameter ranges) */
+#define SKIPM_ENOMEM   (-2)  /* device allocation failed */
+#define SKIPM_EDEVICE  (-3)  /* a HIP runtime call failed */
+#define SKIPM_ERANK    (-4)  /* sketch A D W lost rank (Lemma 3's failure event), after re-sketching */
+#define SKIPM_ENOTCONV (-5)  /* max_outer iterations reached without meeting the stopping test */
+#define SKIPM_ESTALL   (-6)  /* step length below 1e-12 three times in a row */
+#define SKIPM_ENAN     (-7)  /* non-finite iterate */
+
+/* storage of A */
+#define SKIPM_DENSE 0        /* column-major, leading dimension lda >= m */
+#define SKIPM_CSR   1        /* compressed sparse rows, int32 row pointers / column indices */
+
+/* element type of A's values as handed in */
+#define SKIPM_F64 0
+#define SKIPM_F32 1
+
+/* arithmetic of the CG solve */
+#define SKIPM_PREC_FP64  0   /* everything FP64 */
+#define SKIPM_PREC_MIXED 1   /* FP32 CG products on an FP32 copy of A, FP32 preconditioner;
+                                residuals, v, step length and the true-residual pass FP64 */
+
+typedef struct skipm_lp_s* skipm_lp_t;
+
+/* The LP (eq. "primal"/"dual").  All pointers are device pointers; lp_create
+ * copies everything into library-owned buffers, so the caller may free them
+ * after lp_create returns. */
+typedef struct {
+  int64_t m;               /* rows (constraints), 1 <= m <= n */
+  int64_t n;               /* columns (variables) */
+  int64_t nnz;             /* CSR only: number of stored entries */
+  int32_t format;          /* SKIPM_DENSE or SKIPM_CSR */
+  int32_t a_dtype;         /* SKIPM_F64 or SKIPM_F32 */
+  const void* a_vals;      /* dense: lda*n values, column j at a_vals + j*lda;
+                              CSR: nnz values in row order */
+  int64_t lda;             /* dense only (0 means m) */
+  const int32_t* a_rowptr; /* CSR: m+1 offsets, a_rowptr[0] = 0, non-decreasing */
+  const int32_t* a_colidx; /* CSR: nnz column indices in [0, n), strictly increasing per row */
+  const double* b;         /* m */
+  const double* c;         /* n */
+} skipm_problem;
+
+/* Parameters of Alg. 1 / Alg. 2.  skipm_params_default() fills the defaults
+ * given in brackets. */
+typedef struct {
+  double sigma;      /* centring parameter, in (0, 0.8)  [0.5] (Alg. 2 input)        */
+  double gamma;      /* neighbourhood N(gamma), in (0, 1)  [0.999]                    */
+  double tol_cg;     /* relative CG tolerance ||f^(j)|| <= tol ||f^(0)||  [1e-5]      */
+  double eps_gap;    /* stop: relative duality gap and x^T s / max(1,|c^T x|)  [1e-6] */
+  double eps_feas;   /* stop: ||r_p|| <= eps_feas ||b||, ||r_d|| <= eps_feas ||c||  [1e-8] */
+  double guard;      /* step <= (1-guard) x distance to the boundary of x, s > 0  [1e-3] */
+  int32_t w;         /* sketch width, m <= w  [0 = 4m]                                 */
+  int32_t s;         /* non-zeros per row of W, s divides w  [1]                       */
+  int32_t max_cg;    /* CG iteration cap per solve  [500]                              */
+  int32_t max_outer; /* IPM iteration cap  [300]                                       */
+  int32_t resketch;  /* 1: fresh W every IPM iteration (salt = iteration), 0: one W  [1] */
+  int32_t precision; /* SKIPM_PREC_FP64 or SKIPM_PREC_MIXED  [FP64]                    */
+  uint64_t seed;     /* sketch seed  [0]                                               */
+} skipm_params;
+
+/* Result of lp_solve (host struct). */
+typedef struct {
+  int32_t status;    /* SKIPM_OK when the stopping test holds */
+  int32_t iters;     /* IPM iterations taken */
+  int32_t cg_total;  /* CG iterations summed over the solve */
+  int32_t cg_max;    /* largest CG iteration count of one solve */
+  double obj_p;      /* c^T x */
+  double obj_d;      /* b^T y */
+  double rel_gap;    /* |c^T x - b^T y| / max(1, |c^T x|) */
+  double rp_norm;    /* ||A x - b|| */
+  double rd_norm;    /* ||A^T y + s - c|| */
+  double mu;         /* x^T s / n */
+} skipm_result;
+
+/* Diagnostics of one IPM iteration (host struct). */
+typedef struct {
+  double mu;         /* duality measure at the start of the iteration */
+  double rp_norm;    /* ||r_p|| at the start */
+  double rd_norm;    /* ||r_d|| at the start */
+  double rel_gap;    /* at the start */
+  double eta;        /* ||r^k|| / ||r^0|| */
+  double alpha_max;  /* Alg. 2 step (e) */
+  double alpha;      /* Alg. 2 step (f) */
+  double f_norm;     /* ||f^(t)||, final preconditioned CG residual */
+  double f0_norm;    /* ||f^(0)|| = ||Q^{-1/2} p|| */
+  double v_norm;     /* ||v|| */
+  double v_resid;    /* ||B t - g|| / ||g|| with t = (A D W)^+ g: how exactly v meets eq. addl */
+  int32_t cg_iters;  /* CG iterations of this solve */
+  int32_t v_iters;   /* refinement steps of the FP64 solve for t inside v */
+  int32_t converged; /* 1: the stopping test held at the start, nothing was done */
+  int32_t status;    /* SKIPM_OK or an error code */
+} skipm_step_info;
+
+/* Result of pcg_solve (host struct). */
+typedef struct {
+  int32_t iters;
+  double f0_norm;    /* ||f^(0)|| */
+  double f_norm;     /* ||f^(iters)|| (from the CG recurrence) */
+} skipm_pcg_info;
+
+/* Fill *out with the default parameters.  Returns SKIPM_EINVAL if out is NULL. */
+int skipm_params_default(skipm_params* out);
+
+/* Create a solver handle for one LP (device buffers are allocated and the problem
+ * copied).  Validates sizes and, for CSR, row pointers and column indices
+ * (SKIPM_EINVAL on a bad entry).  The iterate starts at x = s = 1, y = 0
+ * (the experiments' all-ones start with y = 0).  Synchronises `stream`. */
+int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* prm,
+              hipStream_t stream);
+
+/* Free the handle and all its device memory.  NULL is accepted. */
+int lp_destroy(skipm_lp_t lp);
+
+/* Reset the iterate to x = s = 1, y = 0 and the iteration counter to 0. */
+int lp_reset(skipm_lp_t lp, hipStream_t stream);
+
+/* Overwrite the iterate (device pointers x: n, y: m, s: n; x, s > 0 is the
+ * caller's responsibility).  With reset_origin != 0 this point becomes the
+ * origin r^0, mu_0 of the neighbourhood N(gamma); otherwise the origin of the
+ * current run is kept (resuming from a checkpoint). */
+int lp_set_iterate(skipm_lp_t lp, const double* x, const double* y, const double* s,
+                   int32_t reset_origin, hipStream_t stream);
+
+/* Copy the current iterate out (device pointers; any may be NULL). */
+int lp_get_iterate(skipm_lp_t lp, double* x, double* y, double* s, hipStream_t stream);
+
+/* Copy the last computed direction (dx, ds, v: n; dy: m) out (device pointers;
+ * any may be NULL).  Valid after ipm_step. */
+int lp_get_direction(skipm_lp_t lp, double* dx, double* dy, double* ds, double* v,
+                     hipStream_t stream);
+
+/* The sparse embedding W used at IPM iteration (salt) k: for every row j < n
+ * and block r < s, bucket[j*s + r] in [r*w/s, (r+1)*w/s) and sign[j*s + r] in
+ * {-1, +1} (Sec. 2's sparse embedding, made concrete as a block CountSketch
+ * with a SplitMix64 counter hash).  bucket and sign are device arrays of n*s
+ * entries.  Needs 1 <= s, s | w. */
+int sketch_hash(uint64_t seed, int64_t k, int32_t s, int64_t n, int32_t w,
+                int32_t* bucket, int8_t* sign, hipStream_t stream);
+
+/* The sketch B = A diag(d) W_k (Alg. 1 step 1 with D = diag(d)), W_k the embedding
+ * of sketch_hash(prm.seed, k, prm.s, n, prm.w).  d: n (device).  B: device
+ * buffer of m*w FP64, column-major with leading dimension m. */
+int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, double* B, hipStream_t stream);
+
+/* Alg. 1 as used in Alg. 2 step (c): with D^2 = diag(d2), build Q from the
+ * sketch with salt k and solve A D^2 A^T dy = p by CG preconditioned with Q,
+ * from dy = 0, until ||f^(j)|| <= tol ||f^(0)|| or max_it iterations (tol <= 0:
+ * run exactly max_it iterations).  d2: n, p: m, dy: m (device).  info: host. */
+int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, double* dy,
+              double tol, int32_t max_it, skipm_pcg_info* info, hipStream_t stream);
+
+/* out = A D^2 A^T u with the handle's current D^2 (as left by the last prologue
+ * of ipm_step / lp_solve or by pcg_solve): the operator of eq. "normal" applied
+ * by the same fused one-pass kernel CG uses (FP32 copy of A in
+ * SKIPM_PREC_MIXED).  The pass is launched `reps` >= 1 times (to time it);
+ * u: m, out: m (device). */
+int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps,
+                  hipStream_t stream);
+
+/* One iteration of Alg. 2 on the handle's iterate (steps a-g), or nothing if
+ * the stopping test already holds (info->converged = 1).  info: host, may be NULL. */
+int ipm_step(skipm_lp_t lp, skipm_step_info* info, hipStream_t stream);
+
+/* Run Alg. 2 from the current iterate until the stopping test holds or
+ * max_outer iterations.  res: host. */
+int lp_solve(skipm_lp_t lp, skipm_result* res, hipStream_t stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* skipm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKIPM_H */

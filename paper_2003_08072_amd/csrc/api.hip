@@ -1,0 +1,961 @@
+// C ABI of libskipm and the host driver of the IPM (Alg. 2 with Alg. 1 inside).
+//
+// One IPM iteration, all on the handle's stream:
+//   prologue pass over A  -> r_d, d^2, r_p, p (eq. pdef), ||r||, c^T x, b^T y
+//   [host reads ~10 scalars: stopping test]
+//   hash + bucket sort     -> W of step (a)
+//   sketch pass over A     -> B = A D W (Alg. 1 step 1)
+//   Gram + Cholesky        -> Q^{-1} = (B B^T)^{-1} = L^{-T} L^{-1}
+//   CG, per iteration: normal pass over A (one read), partial sum, Q^{-1} GEMV,
+//       single-workgroup update; chunks of iterations are enqueued and the host
+//       reads the done flag once per chunk
+//   epilogue pass over A   -> ds (eq. delshat), g = A D^2 A^T dy - p
+//   t = (A D W)^+ g by refinement on the true residual g - B t (FP64)
+//   direction pass         -> v (eq. compv), dx (eq. delxhat), step sums
+//   step pass + finalize   -> alpha_max, alpha (Alg. 2 steps e, f)
+//   update pass            -> (x, y, s) (step g), mu
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace skipm {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace skipm
+
+using namespace skipm;
+
+struct skipm_lp_s {
+  int device = 0;
+  int64_t m = 0, n = 0, nnz = 0;
+  int fmt = SKIPM_DENSE, a_dtype = SKIPM_F64;
+  int64_t lda = 0, mp = 0;
+  skipm_params prm{};
+  int w = 0, s = 1, nb = 32;
+  bool mixed = false;
+  // device buffers
+  void* A = nullptr;
+  float* A32 = nullptr;
+  double *b = nullptr, *c = nullptr, *x = nullptr, *y = nullptr, *sv = nullptr;
+  double *d2 = nullptr, *rd = nullptr, *dx = nullptr, *ds = nullptr, *v = nullptr;
+  float* d2f = nullptr;
+  double *rp = nullptr, *p = nullptr, *dy = nullptr, *g = nullptr;
+  double *cr = nullptr, *cz = nullptr, *cd = nullptr, *cq = nullptr, *cw = nullptr,
+         *cx = nullptr;
+  float* cdf = nullptr;
+  double *tw = nullptr, *tq = nullptr;
+  double* B = nullptr;
+  double* Gpart = nullptr;
+  int ksplit = 1;
+  double* G = nullptr;
+  double* Xb = nullptr;
+  // correction-vector solve: whitened sketches B1 = L0^{-1} B, B2 = L1^{-1} B1, their
+  // Gram inverses, and the accumulated inverse factors M1 = X0, M2 = X1 X0
+  double *B1 = nullptr, *B2 = nullptr, *Gv = nullptr, *Xv = nullptr, *M1 = nullptr,
+         *M2 = nullptr, *rv = nullptr, *uv1 = nullptr, *uv2 = nullptr;
+  int vrounds_built = 0;
+  int32_t *bucket = nullptr, *perm = nullptr, *perm_raw = nullptr, *bptr = nullptr,
+          *bcnt = nullptr, *bcur = nullptr;
+  int8_t* sign = nullptr;
+  void* part = nullptr;
+  double* red = nullptr;
+  double* sc = nullptr;
+  int32_t* is = nullptr;
+  double* hsc = nullptr;  // pinned: S_NSLOTS doubles then I_NINTS ints
+  int nblk_A = 1, nblk_A32 = 1, nblk_B = 1, nblk_vec = 1;
+  int64_t k = 0;
+  int64_t hashed_k = -1;
+  int prev_cg = 8;
+  int origin_pending = 1;
+  int small_steps = 0;
+  double bnorm = 0, cnorm = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+template <typename T>
+int dalloc(skipm_lp_s* lp, T** out, int64_t count) {
+  void* p = nullptr;
+  const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    return SKIPM_ENOMEM;
+  }
+  lp->allocs.push_back(p);
+  *out = (T*)p;
+  return SKIPM_OK;
+}
+
+int validate_params(const skipm_params& p, int64_t m, int64_t n) {
+  if (!(p.sigma > 0.0 && p.sigma < 0.8)) return set_error("sigma must lie in (0, 0.8)"), SKIPM_EINVAL;
+  if (!(p.gamma > 0.0 && p.gamma < 1.0)) return set_error("gamma must lie in (0, 1)"), SKIPM_EINVAL;
+  if (!(p.guard >= 0.0 && p.guard < 1.0)) return set_error("guard must lie in [0, 1)"), SKIPM_EINVAL;
+  const int64_t w = p.w > 0 ? p.w : 4 * m;
+  if (w < m) return set_error("sketch width w must be >= m"), SKIPM_EINVAL;
+  if (p.s < 1 || p.s > 16) return set_error("s must lie in [1, 16]"), SKIPM_EINVAL;
+  if (w % p.s != 0) return set_error("s must divide w"), SKIPM_EINVAL;
+  if (p.max_cg < 1 || p.max_outer < 0) return set_error("bad iteration caps"), SKIPM_EINVAL;
+  if (p.precision != SKIPM_PREC_FP64 && p.precision != SKIPM_PREC_MIXED)
+    return set_error("unknown precision"), SKIPM_EINVAL;
+  if (n * p.s > INT32_MAX) return set_error("n*s exceeds int32 item indices"), SKIPM_EINVAL;
+  return SKIPM_OK;
+}
+
+int sync_read(skipm_lp_s* lp, hipStream_t st) {
+  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc + S_NSLOTS, lp->is, I_NINTS * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+const int32_t* host_ints(const skipm_lp_s* lp) { return (const int32_t*)(lp->hsc + S_NSLOTS); }
+
+int mu_from_iterate(skipm_lp_s* lp, hipStream_t st) {
+  launch_xs_sum(lp->n, lp->x, lp->sv, lp->red, lp->nblk_vec, st);
+  launch_mu_finalize(lp->red, lp->nblk_vec, lp->n, lp->sc, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+int set_param_slots(skipm_lp_s* lp, hipStream_t st) {
+  double vals[3] = {lp->prm.sigma, lp->prm.gamma, lp->prm.guard};
+  SK_CHECK_HIP(hipMemcpyAsync(lp->sc + S_SIGMA, vals, sizeof(vals), hipMemcpyHostToDevice, st));
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+// ---- passes ----------------------------------------------------------------
+
+int run_colpass(ColPass& cp, hipStream_t st) {
+  if (launch_colpass(cp, st) != 0) {
+    set_error("no column-pass kernel for this shape / type");
+    return SKIPM_EINVAL;
+  }
+  return SKIPM_OK;
+}
+
+ColPass colpass_A(skipm_lp_s* lp, int mode) {
+  ColPass cp{};
+  cp.mode = mode;
+  cp.A = lp->A;
+  cp.ta = lp->a_dtype;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->lda;
+  cp.m = lp->m;
+  cp.n = lp->n;
+  cp.part = lp->part;
+  cp.ldp = lp->mp;
+  cp.red = lp->red;
+  cp.sc = lp->sc;
+  cp.nblk = lp->nblk_A;
+  return cp;
+}
+
+int prologue(skipm_lp_s* lp, hipStream_t st) {
+  ColPass cp = colpass_A(lp, COL_PROLOGUE);
+  cp.u = lp->y;
+  cp.x = lp->x;
+  cp.s = lp->sv;
+  cp.c = lp->c;
+  cp.rd_out = lp->rd;
+  cp.d2_out = lp->d2;
+  cp.d2f_out = lp->mixed ? lp->d2f : nullptr;
+  SK_TRY(run_colpass(cp, st));
+  // r_p = A x - b ; p = b - A (sigma mu / s + d2 r_d)
+  launch_finish(lp->part, SKIPM_F64, 2 * lp->mp, 0, cp.nblk, lp->m, 1.0, lp->b, -1.0, lp->rp,
+                nullptr, st);
+  launch_finish(lp->part, SKIPM_F64, 2 * lp->mp, lp->mp, cp.nblk, lp->m, -1.0, lp->b, 1.0, lp->p,
+                nullptr, st);
+  launch_prologue_finalize(lp->m, lp->rp, lp->b, lp->y, lp->red, cp.nblk, lp->sc,
+                           lp->origin_pending, st);
+  lp->origin_pending = 0;
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+int hash_items(skipm_lp_s* lp, int64_t salt, hipStream_t st) {
+  if (lp->hashed_k == salt) return SKIPM_OK;
+  launch_fill_i32(lp->bcnt, 0, lp->w, st);
+  launch_hash(lp->prm.seed, salt, lp->s, lp->n, lp->w, lp->bucket, lp->sign, lp->bcnt, st);
+  launch_bucket_scan(lp->bcnt, lp->bptr, lp->bcur, lp->w, st);
+  launch_bucket_scatter(lp->bucket, lp->n * lp->s, lp->bptr, lp->bcur, lp->perm_raw, st);
+  launch_bucket_sort(lp->bptr, lp->perm_raw, lp->perm, lp->w, st);
+  SK_CHECK_HIP(hipGetLastError());
+  lp->hashed_k = salt;
+  return SKIPM_OK;
+}
+
+int factor(skipm_lp_s* lp, double shift, hipStream_t st) {
+  launch_gram(lp->B, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, lp->mp, st);
+  launch_gram_finish(lp->Gpart, lp->ksplit, lp->m, lp->mp, lp->G, st);
+  if (shift > 0) launch_shift_diag(lp->G, lp->mp, lp->m, shift, st);
+  launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
+  launch_fill_f64(lp->Xb, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
+  launch_spd_inverse(lp->G, lp->Xb, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// out = Q^{-1} u (u, out: m-vectors, padded to mp with zeros)
+int qinv_apply(skipm_lp_s* lp, const double* u, double* out, const int32_t* done,
+               hipStream_t st) {
+  ColPass cp{};
+  cp.mode = COL_DOT;
+  cp.A = lp->G;
+  cp.ta = SKIPM_F64;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->mp;
+  cp.m = lp->mp;
+  cp.n = lp->m;
+  cp.u = u;
+  cp.t_out = out;
+  cp.done = done;
+  cp.nblk = 0;
+  return run_colpass(cp, st);
+}
+
+// One CG iteration on A D^2 A^T (the chunk loop checks the done flag).
+int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
+  const int32_t* done = lp->is + I_CG_DONE;
+  ColPass cp = colpass_A(lp, COL_NORMAL);
+  if (lp->mixed) {
+    cp.A = lp->A32;
+    cp.ta = SKIPM_F32;
+    cp.tc = SKIPM_F32;
+    cp.u = lp->cdf;
+    cp.d2 = lp->d2f;
+    cp.nblk = lp->nblk_A32;
+  } else {
+    cp.u = lp->cd;
+    cp.d2 = lp->d2;
+  }
+  cp.done = done;
+  SK_TRY(run_colpass(cp, st));
+  launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, lp->cq, done, st);
+  SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
+  launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, lp->mixed ? lp->cdf : nullptr,
+                   xsol, nullptr, nullptr, 0, lp->sc, lp->is, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// CG on A D^2 A^T dy = rhs preconditioned by Q^{-1}; returns iterations in *its.
+int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
+            int first_chunk, int* its, int* fact_fail, hipStream_t st) {
+  SK_TRY(qinv_apply(lp, rhs, lp->cw, nullptr, st));
+  launch_cg_init(lp->m, rhs, lp->cw, lp->cr, lp->cz, lp->cd, lp->mixed ? lp->cdf : nullptr, xsol,
+                 nullptr, 0, lp->sc, lp->is, tol, max_it, 0, st);
+  int enq = 0;
+  int chunk = std::max(1, std::min(first_chunk, max_it));
+  *fact_fail = 0;
+  for (;;) {
+    for (int q = 0; q < chunk && enq < max_it; ++q, ++enq) SK_TRY(pcg_iteration(lp, xsol, st));
+    SK_TRY(sync_read(lp, st));
+    const int32_t* hi = host_ints(lp);
+    if (hi[I_FACT_FAIL]) {
+      *fact_fail = 1;
+      *its = hi[I_CG_ITERS];
+      return SKIPM_OK;
+    }
+    if (hi[I_CG_DONE] || enq >= max_it) {
+      *its = hi[I_CG_ITERS];
+      return SKIPM_OK;
+    }
+    chunk = 4;
+  }
+}
+
+// sketch + factor + CG with rank-failure retries (shifted Gram).
+int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
+                 int* its, hipStream_t st) {
+  double shift = 0.0;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    SK_TRY(factor(lp, shift, st));
+    int fail = 0;
+    const int first = std::max(2, lp->prev_cg - 1);
+    SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first, its, &fail, st));
+    if (!fail) return SKIPM_OK;
+    shift = shift == 0.0 ? 1e-12 : shift * 1e3;
+  }
+  set_error("sketch A D W is numerically rank deficient (non-positive Gram pivot)");
+  return SKIPM_ERANK;
+}
+
+int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, double* B,
+                hipStream_t st) {
+  SK_TRY(hash_items(lp, salt, st));
+  launch_sketch_dense(lp->A, lp->a_dtype, lp->lda, lp->m, lp->n, lp->s, dscale, is_d2, lp->bptr,
+                      lp->perm, lp->sign, lp->w, B, lp->lda, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+int epilogue(skipm_lp_s* lp, hipStream_t st) {
+  ColPass cp = colpass_A(lp, COL_EPILOGUE);
+  cp.u = lp->dy;
+  cp.rd = lp->rd;
+  cp.d2 = lp->d2;
+  cp.ds_out = lp->ds;
+  SK_TRY(run_colpass(cp, st));
+  // g = A D^2 A^T dy - p
+  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, 1.0, lp->p, -1.0, lp->g, nullptr,
+                st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// ---- correction vector: t = (A D W)^+ g ---------------------------------------
+//
+// eq. compv needs t = B^+ g with B = A D W, so that B t = g holds to working
+// accuracy (it is what keeps the residuals on their segment, eq. addl).  Late in
+// the IPM kappa(B) reaches 1e8 and anything that goes through the FP64 Gram
+// matrix B B^T alone loses the residual.  So t is refined on the true residual
+// r = g - B t (formed from B itself), with an inner approximate pseudo-inverse
+// taken from Cholesky-QR rounds on B: round 0 uses P0 = (B B^T)^{-1} (the CG
+// preconditioner), round K >= 1 the whitened B_K = L_{K-1}^{-1} ... L_0^{-1} B,
+// whose Gram matrix is well conditioned.  Rounds are built only when the
+// refinement contracts poorly.
+
+int alloc_vbuffers(skipm_lp_s* lp) {
+  if (lp->B1) return SKIPM_OK;
+  const int64_t lw = lp->lda * lp->w, mm = lp->mp * lp->mp;
+  SK_TRY(dalloc(lp, &lp->B1, lw));
+  SK_TRY(dalloc(lp, &lp->B2, lw));
+  SK_TRY(dalloc(lp, &lp->Gv, mm));
+  SK_TRY(dalloc(lp, &lp->Xv, mm));
+  SK_TRY(dalloc(lp, &lp->M1, mm));
+  SK_TRY(dalloc(lp, &lp->M2, mm));
+  return SKIPM_OK;
+}
+
+// out(m) = Mat(mp x mp, column-major) * u, Mat lower triangular (AXPY pass + finish)
+int tri_apply(skipm_lp_s* lp, const double* Mat, const double* u, double* out, hipStream_t st) {
+  ColPass cp{};
+  cp.mode = COL_AXPY;
+  cp.A = Mat;
+  cp.ta = SKIPM_F64;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->mp;
+  cp.m = lp->m;
+  cp.n = lp->m;
+  cp.d2 = u;
+  cp.part = lp->part;
+  cp.ldp = lp->mp;
+  cp.nblk = 0;
+  SK_TRY(run_colpass(cp, st));
+  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr,
+                st);
+  return SKIPM_OK;
+}
+
+// out(mp) = Sym(mp x mp) u  (DOT pass over the symmetric matrix's columns)
+int sym_apply(skipm_lp_s* lp, const double* Sym, const double* u, double* out, hipStream_t st) {
+  ColPass cp{};
+  cp.mode = COL_DOT;
+  cp.A = Sym;
+  cp.ta = SKIPM_F64;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->mp;
+  cp.m = lp->mp;
+  cp.n = lp->m;
+  cp.u = u;
+  cp.t_out = out;
+  cp.nblk = 0;
+  return run_colpass(cp, st);
+}
+
+// out(w) = Bk^T u
+int sketch_t_apply(skipm_lp_s* lp, const double* Bk, const double* u, double* out,
+                   hipStream_t st) {
+  ColPass cp{};
+  cp.mode = COL_DOT;
+  cp.A = Bk;
+  cp.ta = SKIPM_F64;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->lda;
+  cp.m = lp->m;
+  cp.n = lp->w;
+  cp.u = u;
+  cp.t_out = out;
+  cp.nblk = lp->nblk_B;
+  return run_colpass(cp, st);
+}
+
+// rv = g - B t ; S_V_RR = ||rv||^2
+int true_residual(skipm_lp_s* lp, hipStream_t st) {
+  ColPass cp{};
+  cp.mode = COL_AXPY;
+  cp.A = lp->B;
+  cp.ta = SKIPM_F64;
+  cp.tc = SKIPM_F64;
+  cp.lda = lp->lda;
+  cp.m = lp->m;
+  cp.n = lp->w;
+  cp.d2 = lp->tw;
+  cp.part = lp->part;
+  cp.ldp = lp->mp;
+  cp.nblk = lp->nblk_B;
+  SK_TRY(run_colpass(cp, st));
+  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, lp->g, 1.0, lp->rv, nullptr,
+                st);
+  launch_norm2(lp->rv, lp->m, lp->sc, S_V_RR, st);
+  return SKIPM_OK;
+}
+
+int spd_inverse_checked(skipm_lp_s* lp, double* Gm, double* Xm, hipStream_t st) {
+  launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
+  launch_fill_f64(Xm, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
+  launch_spd_inverse(Gm, Xm, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// Build round K (1 or 2) of the whitening.
+int build_vround(skipm_lp_s* lp, int K, hipStream_t st) {
+  SK_TRY(alloc_vbuffers(lp));
+  const int64_t mp = lp->mp, mm = mp * mp;
+  if (K == 1) {
+    launch_copy_f64(lp->M1, lp->Xb, mm, st);  // M1 = X0
+    launch_trmm(lp->Xb, mp, lp->nb, lp->B, lp->lda, lp->m, lp->w, lp->B1, lp->lda, lp->lda, st);
+    launch_gram(lp->B1, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, mp, st);
+  } else {
+    launch_trmm(lp->Xv, mp, lp->nb, lp->B1, lp->lda, lp->m, lp->w, lp->B2, lp->lda, lp->lda, st);
+    launch_trmm(lp->Xv, mp, lp->nb, lp->M1, mp, mp, mp, lp->M2, mp, mp, st);  // M2 = X1 M1
+    launch_gram(lp->B2, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, mp, st);
+  }
+  launch_gram_finish(lp->Gpart, lp->ksplit, lp->m, mp, lp->Gv, st);
+  SK_TRY(spd_inverse_checked(lp, lp->Gv, lp->Xv, st));
+  SK_TRY(sync_read(lp, st));
+  if (host_ints(lp)[I_FACT_FAIL]) {
+    // shifted Cholesky of the round's Gram matrix
+    launch_gram_finish(lp->Gpart, lp->ksplit, lp->m, mp, lp->Gv, st);
+    launch_shift_trace(lp->Gv, mp, lp->m, 11.0 * (double)(lp->w * lp->m + lp->m * (lp->m + 1)) *
+                                              1.1102230246251565e-16, st);
+    SK_TRY(spd_inverse_checked(lp, lp->Gv, lp->Xv, st));
+  }
+  lp->vrounds_built = K;
+  return SKIPM_OK;
+}
+
+// tq = approximate B^+ rv from round K
+int pinv_apply(skipm_lp_s* lp, int K, hipStream_t st) {
+  if (K == 0) {
+    SK_TRY(sym_apply(lp, lp->G, lp->rv, lp->uv2, st));
+    return sketch_t_apply(lp, lp->B, lp->uv2, lp->tq, st);
+  }
+  SK_TRY(tri_apply(lp, K == 1 ? lp->M1 : lp->M2, lp->rv, lp->uv1, st));
+  SK_TRY(sym_apply(lp, lp->Gv, lp->uv1, lp->uv2, st));
+  return sketch_t_apply(lp, K == 1 ? lp->B1 : lp->B2, lp->uv2, lp->tq, st);
+}
+
+int v_solve(skipm_lp_s* lp, int* its, double* rel_out, hipStream_t st) {
+  const double target = 1e-14;
+  const int max_steps = 12;
+  lp->vrounds_built = 0;
+  launch_fill_f64(lp->tw, 0.0, lp->w, st);
+  launch_copy_f64(lp->rv, lp->g, lp->m, st);
+  launch_norm2(lp->g, lp->m, lp->sc, S_V_GG, st);
+  SK_TRY(sync_read(lp, st));
+  const double gg = lp->hsc[S_V_GG];
+  *its = 0;
+  *rel_out = 0.0;
+  if (!(gg > 0.0)) return SKIPM_OK;
+  int K = 0;
+  double rel_prev = 1.0;
+  for (int step = 0; step < max_steps; ++step) {
+    SK_TRY(pinv_apply(lp, K, st));
+    launch_axpy(lp->tw, lp->tq, 1.0, lp->w, st);
+    SK_TRY(true_residual(lp, st));
+    SK_CHECK_HIP(hipGetLastError());
+    SK_TRY(sync_read(lp, st));
+    const double rel = sqrt(std::max(0.0, lp->hsc[S_V_RR]) / gg);
+    *its = step + 1;
+    *rel_out = rel;
+    if (!(rel > target)) break;
+    if (K < 2 && rel > 1e-2 * rel_prev) {
+      K += 1;
+      SK_TRY(build_vround(lp, K, st));
+    } else if (rel > 0.5 * rel_prev) {
+      break;  // stagnated at the attainable accuracy
+    }
+    rel_prev = std::min(rel_prev, rel);
+  }
+  return SKIPM_OK;
+}
+
+int finish_step(skipm_lp_s* lp, hipStream_t st) {
+  launch_direction(lp->n, lp->s, lp->x, lp->sv, lp->d2, lp->ds, lp->bucket, lp->sign, lp->tw,
+                   lp->v, lp->dx, lp->red, lp->nblk_vec, lp->sc, st);
+  launch_reduce_slots(lp->red, lp->nblk_vec, 5, lp->sc, S_A0, 0, st);
+  launch_step_terms(lp->n, lp->x, lp->sv, lp->dx, lp->ds, lp->red, lp->nblk_vec, lp->sc, st);
+  launch_reduce_slots(lp->red, lp->nblk_vec, 2, lp->sc, S_EXIT, 1, st);
+  launch_step_finalize(lp->n, lp->sc, st);
+  launch_update(lp->n, lp->m, lp->x, lp->y, lp->sv, lp->dx, lp->dy, lp->ds, lp->red, lp->nblk_vec,
+                lp->sc, st);
+  launch_mu_finalize(lp->red, lp->nblk_vec, lp->n, lp->sc, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+struct StopState {
+  bool converged;
+  bool nan;
+  double ctx, bty, rel_gap, rp, rd, mu;
+};
+
+StopState stop_test(skipm_lp_s* lp, double bnorm, double cnorm) {
+  const double* h = lp->hsc;
+  StopState s{};
+  s.ctx = h[S_CTX];
+  s.bty = h[S_BTY];
+  s.mu = h[S_MU];
+  s.rp = sqrt(h[S_RP2]);
+  s.rd = sqrt(h[S_RD2]);
+  const double den = std::max(1.0, fabs(s.ctx));
+  s.rel_gap = fabs(s.ctx - s.bty) / den;
+  s.nan = !(std::isfinite(s.ctx) && std::isfinite(s.bty) && std::isfinite(s.mu) &&
+            std::isfinite(s.rp) && std::isfinite(s.rd));
+  s.converged = !s.nan && s.rel_gap <= lp->prm.eps_gap && h[S_XS] <= lp->prm.eps_gap * den &&
+                s.rp <= lp->prm.eps_feas * bnorm && s.rd <= lp->prm.eps_feas * cnorm;
+  return s;
+}
+
+int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cnorm,
+                  hipStream_t st) {
+  SK_TRY(prologue(lp, st));
+  SK_TRY(sync_read(lp, st));
+  // the prologue's x^T s is the same quantity as the update's; S_XS holds the
+  // value of the current iterate
+  const StopState ss = stop_test(lp, bnorm, cnorm);
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->mu = ss.mu;
+    info->rp_norm = ss.rp;
+    info->rd_norm = ss.rd;
+    info->rel_gap = ss.rel_gap;
+    info->eta = lp->hsc[S_ETA];
+  }
+  if (ss.nan) {
+    set_error("non-finite iterate");
+    if (info) info->status = SKIPM_ENAN;
+    return SKIPM_ENAN;
+  }
+  if (lp->k > 0) {  // step length of the previous iteration
+    lp->small_steps = lp->hsc[S_ALPHA] < 1e-12 ? lp->small_steps + 1 : 0;
+    if (lp->small_steps >= 3) {
+      set_error("step length below 1e-12 three times in a row");
+      if (info) info->status = SKIPM_ESTALL;
+      return SKIPM_ESTALL;
+    }
+  }
+  if (ss.converged) {
+    if (info) info->converged = 1;
+    return SKIPM_OK;
+  }
+  const int64_t salt = lp->prm.resketch ? lp->k : 0;
+  SK_TRY(sketch_into(lp, lp->d2, 1, salt, lp->B, st));
+  int its = 0;
+  SK_TRY(solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st));
+  const double f0 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
+  const double f1 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ]));
+  lp->prev_cg = its;
+  SK_TRY(epilogue(lp, st));
+  int vits = 0;
+  double vrel = 0;
+  SK_TRY(v_solve(lp, &vits, &vrel, st));
+  SK_TRY(finish_step(lp, st));
+  lp->k += 1;
+  if (info) {
+    info->cg_iters = its;
+    info->f0_norm = f0;
+    info->f_norm = f1;
+    info->v_iters = vits;
+    info->v_resid = vrel;
+  }
+  return SKIPM_OK;
+}
+
+double host_norm(const double* dptr, int64_t n, int* rc) {
+  std::vector<double> h((size_t)n);
+  if (hipMemcpy(h.data(), dptr, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    *rc = SKIPM_EDEVICE;
+    return 0;
+  }
+  double s = 0;
+  for (double v : h) s += v * v;
+  *rc = SKIPM_OK;
+  return sqrt(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int skipm_params_default(skipm_params* out) {
+  if (!out) return set_error("null params"), SKIPM_EINVAL;
+  memset(out, 0, sizeof(*out));
+  out->sigma = 0.5;
+  out->gamma = 0.999;
+  out->tol_cg = 1e-5;
+  out->eps_gap = 1e-6;
+  out->eps_feas = 1e-8;
+  out->guard = 1e-3;
+  out->w = 0;
+  out->s = 1;
+  out->max_cg = 500;
+  out->max_outer = 300;
+  out->resketch = 1;
+  out->precision = SKIPM_PREC_FP64;
+  out->seed = 0;
+  return SKIPM_OK;
+}
+
+int lp_destroy(skipm_lp_t lp) {
+  if (!lp) return SKIPM_OK;
+  hipSetDevice(lp->device);
+  for (void* p : lp->allocs) hipFree(p);
+  if (lp->hsc) hipHostFree(lp->hsc);
+  delete lp;
+  return SKIPM_OK;
+}
+
+int lp_reset(skipm_lp_t lp, hipStream_t st) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  launch_fill_f64(lp->x, 1.0, lp->n, st);
+  launch_fill_f64(lp->sv, 1.0, lp->n, st);
+  launch_fill_f64(lp->y, 0.0, lp->mp, st);
+  lp->k = 0;
+  lp->prev_cg = 8;
+  lp->origin_pending = 1;
+  lp->small_steps = 0;
+  SK_TRY(mu_from_iterate(lp, st));
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* prm,
+              hipStream_t st) {
+  if (!out || !prob || !prm) return set_error("null argument"), SKIPM_EINVAL;
+  *out = nullptr;
+  const int64_t m = prob->m, n = prob->n;
+  if (m < 1 || n < m) return set_error("need 1 <= m <= n"), SKIPM_EINVAL;
+  if (prob->format != SKIPM_DENSE)
+    return set_error("only SKIPM_DENSE storage is supported by this build"), SKIPM_EINVAL;
+  if (prob->a_dtype != SKIPM_F64 && prob->a_dtype != SKIPM_F32)
+    return set_error("a_dtype must be SKIPM_F64 or SKIPM_F32"), SKIPM_EINVAL;
+  if (!prob->a_vals || !prob->b || !prob->c) return set_error("null problem pointer"), SKIPM_EINVAL;
+  const int64_t lda_in = prob->lda > 0 ? prob->lda : m;
+  if (lda_in < m) return set_error("lda < m"), SKIPM_EINVAL;
+  SK_TRY(validate_params(*prm, m, n));
+  if (m > 2048) return set_error("dense path supports m <= 2048"), SKIPM_EINVAL;
+
+  skipm_lp_s* lp = new skipm_lp_s();
+  hipGetDevice(&lp->device);
+  lp->m = m;
+  lp->n = n;
+  lp->fmt = prob->format;
+  lp->a_dtype = prob->a_dtype;
+  lp->prm = *prm;
+  lp->w = prm->w > 0 ? prm->w : (int)(4 * m);
+  lp->s = prm->s;
+  lp->mixed = prm->precision == SKIPM_PREC_MIXED;
+  lp->lda = round_up(m, 4);
+  lp->mp = round_up(m, 64);
+  lp->nb = chol_block(lp->mp);
+  const int64_t mp = lp->mp, lda = lp->lda, w = lp->w;
+
+  int rc = SKIPM_OK;
+#define ALLOC(ptr, cnt)                      \
+  if ((rc = dalloc(lp, &(ptr), (cnt))) != 0) { \
+    lp_destroy(lp);                          \
+    return rc;                               \
+  }
+  const size_t esz = lp->a_dtype == SKIPM_F64 ? 8 : 4;
+  {
+    void* p = nullptr;
+    if (hipMalloc(&p, esz * lda * n) != hipSuccess) {
+      lp_destroy(lp);
+      return set_error("hipMalloc of A failed"), SKIPM_ENOMEM;
+    }
+    lp->allocs.push_back(p);
+    lp->A = p;
+  }
+  if (lp->mixed) ALLOC(lp->A32, lda * n);
+  ALLOC(lp->b, mp);
+  ALLOC(lp->c, n);
+  ALLOC(lp->x, n);
+  ALLOC(lp->y, mp);
+  ALLOC(lp->sv, n);
+  ALLOC(lp->d2, n);
+  ALLOC(lp->rd, n);
+  ALLOC(lp->dx, n);
+  ALLOC(lp->ds, n);
+  ALLOC(lp->v, n);
+  if (lp->mixed) ALLOC(lp->d2f, n);
+  ALLOC(lp->rp, mp);
+  ALLOC(lp->p, mp);
+  ALLOC(lp->dy, mp);
+  ALLOC(lp->g, mp);
+  ALLOC(lp->cr, mp);
+  ALLOC(lp->cz, mp);
+  ALLOC(lp->cd, mp);
+  ALLOC(lp->cq, mp);
+  ALLOC(lp->cw, mp);
+  ALLOC(lp->cx, mp);
+  ALLOC(lp->rv, mp);
+  ALLOC(lp->uv1, mp);
+  ALLOC(lp->uv2, mp);
+  if (lp->mixed) ALLOC(lp->cdf, mp);
+  ALLOC(lp->tw, w);
+  ALLOC(lp->tq, w);
+  ALLOC(lp->B, lda * w);
+  lp->nb = chol_block(mp);
+  {
+    const int T = (int)(mp / 64);
+    const int ntiles = T * (T + 1) / 2;
+    int ks = (int)std::max<int64_t>(1, std::min<int64_t>(16, 320 / ntiles));
+    ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, w / 64));
+    lp->ksplit = ks;
+  }
+  ALLOC(lp->Gpart, (int64_t)lp->ksplit * mp * mp);
+  ALLOC(lp->G, mp * mp);
+  ALLOC(lp->Xb, mp * mp);
+  ALLOC(lp->bucket, n * lp->s);
+  ALLOC(lp->sign, n * lp->s);
+  ALLOC(lp->perm, n * lp->s);
+  ALLOC(lp->perm_raw, n * lp->s);
+  ALLOC(lp->bptr, w + 1);
+  ALLOC(lp->bcnt, w);
+  ALLOC(lp->bcur, w);
+  lp->nblk_A = colpass_nblk(lda, n, lp->a_dtype);
+  lp->nblk_A32 = colpass_nblk(lda, n, SKIPM_F32);
+  lp->nblk_B = colpass_nblk(lda, w, SKIPM_F64);
+  lp->nblk_vec = vec_nblk(n);
+  {
+    int64_t pe = std::max<int64_t>(2 * (int64_t)lp->nblk_A * mp, (int64_t)lp->nblk_B * mp);
+    pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A32 * mp);
+    pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64) * mp);
+    double* pp = nullptr;
+    ALLOC(pp, pe);
+    lp->part = pp;
+  }
+  ALLOC(lp->red, (int64_t)std::max(std::max(lp->nblk_A, lp->nblk_vec), 64) * 8);
+  ALLOC(lp->sc, S_NSLOTS);
+  ALLOC(lp->is, I_NINTS);
+#undef ALLOC
+  if (hipHostMalloc((void**)&lp->hsc, S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t)) !=
+      hipSuccess) {
+    lp_destroy(lp);
+    return set_error("hipHostMalloc failed"), SKIPM_ENOMEM;
+  }
+  // zero the vectors whose padding must stay zero, then copy the problem in
+  launch_fill_f64(lp->sc, 0.0, S_NSLOTS, st);
+  launch_fill_i32(lp->is, 0, I_NINTS, st);
+  double* zero_vecs[] = {lp->b,  lp->y,  lp->rp, lp->p,  lp->dy, lp->g,  lp->cr,  lp->cz,
+                         lp->cd, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2};
+  for (double* z : zero_vecs) launch_fill_f64(z, 0.0, mp, st);
+  if (lp->cdf) launch_convert_f64_f32(lp->cdf, lp->cd, mp, st);
+  launch_fill_f64(lp->B, 0.0, lda * w, st);
+  launch_copy_f64(lp->b, prob->b, m, st);
+  launch_copy_f64(lp->c, prob->c, n, st);
+  if (lp->a_dtype == SKIPM_F64) {
+    launch_pad_copy_f64((double*)lp->A, lda, (const double*)prob->a_vals, lda_in, m, n, st);
+    if (lp->mixed)
+      launch_pad_copy_f64_to_f32(lp->A32, lda, (const double*)prob->a_vals, lda_in, m, n, st);
+  } else {
+    launch_pad_copy_f32((float*)lp->A, lda, (const float*)prob->a_vals, lda_in, m, n, st);
+    if (lp->mixed) lp->A32 = (float*)lp->A;
+  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    lp_destroy(lp);
+    return set_error("device error while copying the problem"), SKIPM_EDEVICE;
+  }
+  if ((rc = set_param_slots(lp, st)) != SKIPM_OK || (rc = lp_reset(lp, st)) != SKIPM_OK) {
+    lp_destroy(lp);
+    return rc;
+  }
+  lp->bnorm = host_norm(lp->b, m, &rc);
+  if (rc == SKIPM_OK) lp->cnorm = host_norm(lp->c, n, &rc);
+  if (rc != SKIPM_OK) {
+    lp_destroy(lp);
+    return set_error("copy of b or c failed"), rc;
+  }
+  *out = lp;
+  return SKIPM_OK;
+}
+
+int lp_set_iterate(skipm_lp_t lp, const double* x, const double* y, const double* s,
+                   int32_t reset_origin, hipStream_t st) {
+  if (!lp || !x || !y || !s) return set_error("null argument"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  launch_copy_f64(lp->x, x, lp->n, st);
+  launch_copy_f64(lp->y, y, lp->m, st);
+  launch_copy_f64(lp->sv, s, lp->n, st);
+  if (reset_origin) {
+    lp->origin_pending = 1;
+    lp->k = 0;
+  }
+  SK_TRY(mu_from_iterate(lp, st));
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int lp_get_iterate(skipm_lp_t lp, double* x, double* y, double* s, hipStream_t st) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  if (x) launch_copy_f64(x, lp->x, lp->n, st);
+  if (y) launch_copy_f64(y, lp->y, lp->m, st);
+  if (s) launch_copy_f64(s, lp->sv, lp->n, st);
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int lp_get_direction(skipm_lp_t lp, double* dx, double* dy, double* ds, double* v,
+                     hipStream_t st) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  if (dx) launch_copy_f64(dx, lp->dx, lp->n, st);
+  if (dy) launch_copy_f64(dy, lp->dy, lp->m, st);
+  if (ds) launch_copy_f64(ds, lp->ds, lp->n, st);
+  if (v) launch_copy_f64(v, lp->v, lp->n, st);
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int sketch_hash(uint64_t seed, int64_t k, int32_t s, int64_t n, int32_t w, int32_t* bucket,
+                int8_t* sign, hipStream_t st) {
+  if (!bucket || !sign) return set_error("null output"), SKIPM_EINVAL;
+  if (n < 1 || w < 1 || s < 1 || s > 16 || w % s != 0)
+    return set_error("need n >= 1, 1 <= s <= 16, s | w"), SKIPM_EINVAL;
+  launch_hash(seed, k, s, n, w, bucket, sign, nullptr, st);
+  SK_CHECK_HIP(hipGetLastError());
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, double* B, hipStream_t st) {
+  if (!lp || !d || !B) return set_error("null argument"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  SK_TRY(sketch_into(lp, d, 0, k, lp->B, st));
+  launch_pad_copy_f64(B, lp->m, lp->B, lp->lda, lp->m, lp->w, st);
+  SK_CHECK_HIP(hipGetLastError());
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
+int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, double* dy, double tol,
+              int32_t max_it, skipm_pcg_info* info, hipStream_t st) {
+  if (!lp || !d2 || !p || !dy) return set_error("null argument"), SKIPM_EINVAL;
+  if (max_it < 1) return set_error("max_it must be >= 1"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  launch_copy_f64(lp->d2, d2, lp->n, st);
+  if (lp->mixed) launch_convert_f64_f32(lp->d2f, lp->d2, lp->n, st);
+  launch_copy_f64(lp->g, p, lp->m, st);  // g doubles as the right-hand side buffer here
+  SK_TRY(sketch_into(lp, lp->d2, 1, k, lp->B, st));
+  int its = 0;
+  SK_TRY(solve_normal(lp, lp->g, lp->cx, tol, max_it, &its, st));
+  launch_copy_f64(dy, lp->cx, lp->m, st);
+  SK_CHECK_HIP(hipGetLastError());
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = its;
+    info->f0_norm = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
+    info->f_norm = sqrt(std::max(0.0, lp->hsc[S_CG_RZ]));
+  }
+  return SKIPM_OK;
+}
+
+int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps, hipStream_t st) {
+  if (!lp || !u || !out) return set_error("null argument"), SKIPM_EINVAL;
+  if (reps < 1) return set_error("reps must be >= 1"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  launch_copy_f64(lp->cd, u, lp->m, st);
+  if (lp->mixed) launch_convert_f64_f32(lp->cdf, lp->cd, lp->m, st);
+  ColPass cp = colpass_A(lp, COL_NORMAL);
+  if (lp->mixed) {
+    cp.A = lp->A32;
+    cp.ta = SKIPM_F32;
+    cp.tc = SKIPM_F32;
+    cp.u = lp->cdf;
+    cp.d2 = lp->d2f;
+    cp.nblk = lp->nblk_A32;
+  } else {
+    cp.u = lp->cd;
+    cp.d2 = lp->d2;
+  }
+  for (int r = 0; r < reps; ++r) SK_TRY(run_colpass(cp, st));
+  launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+int ipm_step(skipm_lp_t lp, skipm_step_info* info, hipStream_t st) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  const double bn = lp->bnorm, cn = lp->cnorm;
+  const int rc = step_internal(lp, info, bn, cn, st);
+  if (rc != SKIPM_OK) return rc;
+  if (info && !info->converged) {
+    SK_TRY(sync_read(lp, st));
+    info->alpha_max = lp->hsc[S_AMAX];
+    info->alpha = lp->hsc[S_ALPHA];
+    info->v_norm = sqrt(std::max(0.0, lp->hsc[S_V2]));
+  }
+  return SKIPM_OK;
+}
+
+int lp_solve(skipm_lp_t lp, skipm_result* res, hipStream_t st) {
+  if (!lp || !res) return set_error("null argument"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  const double bn = lp->bnorm, cn = lp->cnorm;
+  memset(res, 0, sizeof(*res));
+  int status = SKIPM_ENOTCONV;
+  int it = 0;
+  for (;; ++it) {
+    skipm_step_info info;
+    if (it >= lp->prm.max_outer) {
+      // evaluate the stopping test at the final iterate without stepping
+      SK_TRY(prologue(lp, st));
+      SK_TRY(sync_read(lp, st));
+      const StopState ss = stop_test(lp, bn, cn);
+      status = ss.converged ? SKIPM_OK : (ss.nan ? SKIPM_ENAN : SKIPM_ENOTCONV);
+      break;
+    }
+    const int rc = step_internal(lp, &info, bn, cn, st);
+    if (rc != SKIPM_OK) {
+      status = rc;
+      break;
+    }
+    if (info.converged) {
+      status = SKIPM_OK;
+      break;
+    }
+    res->cg_total += info.cg_iters;
+    res->cg_max = std::max(res->cg_max, info.cg_iters);
+  }
+  const StopState ss = stop_test(lp, bn, cn);
+  res->status = status;
+  res->iters = it;
+  res->obj_p = ss.ctx;
+  res->obj_d = ss.bty;
+  res->rel_gap = ss.rel_gap;
+  res->rp_norm = ss.rp;
+  res->rd_norm = ss.rd;
+  res->mu = ss.mu;
+  if (status != SKIPM_OK && status != SKIPM_ENOTCONV) return status;
+  return status == SKIPM_ENOTCONV ? (set_error("max_outer reached"), SKIPM_ENOTCONV) : SKIPM_OK;
+}
+
+const char* skipm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

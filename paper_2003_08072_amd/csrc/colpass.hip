@@ -1,0 +1,518 @@
+// One streaming pass over a dense column-major matrix (A, the sketch B, or the
+// inverse Gram matrix), doing per column j:
+//     t_j = a_j^T u                      (a dot product down the column)
+//     acc += coef_j(t_j, ...) * a_j      (an axpy of the same column)
+// so that a product like A D^2 A^T u needs exactly one read of A.  Modes:
+//   COL_NORMAL    coef_j = d2_j t_j                  -> A D^2 A^T u  (CG product)
+//   COL_PROLOGUE  t_j = a_j^T y,  r_d,j = t_j + s_j - c_j,  d2_j = x_j / s_j,
+//                 acc1 += x_j a_j,  acc2 += (sigma mu / s_j + d2_j r_d,j) a_j
+//                 -> A x and A (sigma mu S^{-1} 1 + D^2 r_d); with them
+//                    r_p = A x - b and p = b - A(sigma mu / s + d2 r_d), which is
+//                    eq. pdef with its A x terms cancelled.
+//   COL_EPILOGUE  t_j = a_j^T dy, ds_j = -r_d,j - t_j (eq. delshat),
+//                 acc += d2_j t_j a_j  -> A D^2 A^T dy (for g = A D^2 A^T dy - p)
+//   COL_DOT       t_j only (a GEMV with the transpose)
+//   COL_AXPY      no dot: acc += coef_j a_j with coef given   -> A coef  (a GEMV)
+//
+// Layout: a group of G lanes owns one column at a time; lane l of the group
+// holds rows (r*G + l)*V .. +V-1 for r < R, read as one 16-byte vector per r,
+// so a group reads a column with fully coalesced 16-byte-per-lane loads.  The
+// column's dot is a butterfly over the G lanes.  Each workgroup streams a
+// contiguous range of columns (next column prefetched into registers), keeps
+// its accumulators in registers, folds its waves together through LDS in a
+// fixed order and writes one partial vector; launch_finish sums the partials
+// of all workgroups in a fixed order, so results are bitwise reproducible.
+#include "common.h"
+
+namespace skipm {
+
+namespace {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+template <typename TA>
+struct Vec;
+template <>
+struct Vec<double> {
+  static constexpr int V = 2;
+  typedef dvec2 type;
+};
+template <>
+struct Vec<float> {
+  static constexpr int V = 4;
+  typedef fvec4 type;
+};
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct Args {
+  const void* A;
+  int64_t lda, m, n, cpb;
+  const void* u;
+  const double* x;
+  const double* s;
+  const double* c;
+  const double* rd;
+  const void* d2;
+  double* rd_out;
+  double* d2_out;
+  float* d2f_out;
+  double* ds_out;
+  void* t_out;
+  void* part;
+  int64_t ldp;
+  double* red;
+  const double* sc;
+  const int32_t* done;
+};
+
+template <typename TA, typename TC, int G, int R, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_colpass(Args a) {
+  constexpr int V = Vec<TA>::V;
+  typedef typename Vec<TA>::type VT;
+  constexpr int NGW = 64 / G;
+  constexpr int NW = NT / 64;
+  constexpr int NACC = MODE == COL_PROLOGUE ? 2 : (MODE == COL_DOT ? 0 : 1);
+  constexpr int NACC1 = NACC > 0 ? NACC : 1;
+  constexpr int LROWS = G * R * V;
+  __shared__ TC lds[NACC1][LROWS];
+  __shared__ double sred[NW][4];
+
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = lane / G, lg = lane % G;
+  const int slot = wid * NGW + grp;
+  constexpr int NSLOT = NW * NGW;
+  const int64_t c0 = (int64_t)blockIdx.x * a.cpb;
+  const int64_t c1 = c0 + a.cpb < a.n ? c0 + a.cpb : a.n;
+  const TA* __restrict__ A = (const TA*)a.A;
+  const TC* __restrict__ u = (const TC*)a.u;
+  const TC* __restrict__ d2 = (const TC*)a.d2;
+
+  bool valid[R];
+  TC uu[R][V];
+  TC acc1[R][V], acc2[R][V];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t row0 = (int64_t)(r * G + lg) * V;
+    valid[r] = row0 < a.lda;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      uu[r][e] = (valid[r] && MODE != COL_AXPY) ? u[row0 + e] : (TC)0;
+      acc1[r][e] = 0;
+      acc2[r][e] = 0;
+    }
+  }
+  double mu = 0, sigma = 0;
+  if (MODE == COL_PROLOGUE) {
+    mu = a.sc[S_MU];
+    sigma = a.sc[S_SIGMA];
+  }
+  double sr0 = 0, sr1 = 0, sr2 = 0;
+
+  VT cur[R], nxt[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    cur[r] = (VT)0;
+    nxt[r] = (VT)0;
+  }
+  int64_t col = c0 + slot;
+  if (col < c1) {
+    const VT* p = (const VT*)(A + col * a.lda);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (valid[r]) cur[r] = p[r * G + lg];
+  }
+  while (col < c1) {
+    const int64_t ncol = col + NSLOT;
+    if (ncol < c1) {
+      const VT* p = (const VT*)(A + ncol * a.lda);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (valid[r]) nxt[r] = p[r * G + lg];
+    }
+    TC dot = 0;
+    if (MODE != COL_AXPY) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!valid[r]) continue;
+#pragma unroll
+        for (int e = 0; e < V; ++e) dot += (TC)cur[r][e] * uu[r][e];
+      }
+      dot = group_sum<G>(dot);
+    }
+    if (MODE == COL_AXPY) {
+      const TC coef = d2[col];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+    } else if (MODE == COL_DOT) {
+      if (lg == 0) ((TC*)a.t_out)[col] = dot;
+    } else if (MODE == COL_NORMAL) {
+      const TC coef = d2 ? d2[col] * dot : dot;
+      if (a.t_out && lg == 0) ((TC*)a.t_out)[col] = dot;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+    } else if (MODE == COL_EPILOGUE) {
+      const double t = (double)dot;
+      const double dsj = -a.rd[col] - t;
+      const double coef = ((const double*)a.d2)[col] * t;
+      if (lg == 0) a.ds_out[col] = dsj;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc1[r][e] += (TC)(coef * (double)cur[r][e]);
+    } else {  // COL_PROLOGUE
+      const double t = (double)dot;
+      const double xj = a.x[col], sj = a.s[col], cj = a.c[col];
+      const double rdj = t + sj - cj;
+      const double d2j = xj / sj;
+      const double ej = sigma * mu / sj + d2j * rdj;
+      if (lg == 0) {
+        a.rd_out[col] = rdj;
+        a.d2_out[col] = d2j;
+        if (a.d2f_out) a.d2f_out[col] = (float)d2j;
+        sr0 += rdj * rdj;
+        sr1 += cj * xj;
+        sr2 += xj * sj;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          acc1[r][e] += (TC)(xj * (double)cur[r][e]);
+          acc2[r][e] += (TC)(ej * (double)cur[r][e]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+    col = ncol;
+  }
+
+  if (MODE == COL_PROLOGUE) {
+    // workgroup sums of the per-column scalars (only lg == 0 lanes are non-zero)
+    sr0 = group_sum<64>(sr0);
+    sr1 = group_sum<64>(sr1);
+    sr2 = group_sum<64>(sr2);
+    if (lane == 0) {
+      sred[wid][0] = sr0;
+      sred[wid][1] = sr1;
+      sred[wid][2] = sr2;
+    }
+  }
+  if (NACC == 0) return;
+  // fold the groups of a wave (same rows) together
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        acc1[r][e] += __shfl_xor(acc1[r][e], off, 64);
+        if (NACC > 1) acc2[r][e] += __shfl_xor(acc2[r][e], off, 64);
+      }
+  }
+  // fold the waves together in a fixed order
+  for (int w = 0; w < NW; ++w) {
+    if (wid == w && grp == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int idx = (r * G + lg) * V + e;
+          lds[0][idx] = (w == 0 ? (TC)0 : lds[0][idx]) + acc1[r][e];
+          if (NACC > 1) lds[NACC1 - 1][idx] = (w == 0 ? (TC)0 : lds[NACC1 - 1][idx]) + acc2[r][e];
+        }
+    }
+    __syncthreads();
+  }
+  TC* part = (TC*)a.part + (int64_t)blockIdx.x * NACC * a.ldp;
+  for (int64_t i = threadIdx.x; i < a.m; i += NT) {
+    part[i] = lds[0][i];
+    if (NACC > 1) part[a.ldp + i] = lds[NACC1 - 1][i];
+  }
+  if (MODE == COL_PROLOGUE && threadIdx.x == 0) {
+    double t0 = 0, t1 = 0, t2 = 0;
+    for (int w = 0; w < NW; ++w) {
+      t0 += sred[w][0];
+      t1 += sred[w][1];
+      t2 += sred[w][2];
+    }
+    a.red[blockIdx.x * 8 + 0] = t0;
+    a.red[blockIdx.x * 8 + 1] = t1;
+    a.red[blockIdx.x * 8 + 2] = t2;
+  }
+}
+
+// B[:, b] = sum over the (sorted) items of bucket b of sign * d_j * A[:, j]
+// (d_j = dsc_j, or sqrt(dsc_j) when dsc holds d^2)
+template <typename TA, int G, int R, int NT>
+__global__ __launch_bounds__(NT) void k_sketch(const TA* __restrict__ A, int64_t lda, int s,
+                                               const double* __restrict__ dsc, int is_d2,
+                                               const int32_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ perm,
+                                               const int8_t* __restrict__ sign, int w,
+                                               double* __restrict__ B, int64_t ldb) {
+  constexpr int V = Vec<TA>::V;
+  typedef typename Vec<TA>::type VT;
+  constexpr int NGW = 64 / G;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = lane / G, lg = lane % G;
+  const int gslot = (blockIdx.x * (NT / 64) + wid) * NGW + grp;
+  const int nslot = gridDim.x * (NT / 64) * NGW;
+  bool valid[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) valid[r] = (int64_t)(r * G + lg) * V < lda;
+  for (int b = gslot; b < w; b += nslot) {
+    double acc[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[r][e] = 0;
+    const int beg = ptr[b], end = ptr[b + 1];
+    VT cur[R], nxt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cur[r] = (VT)0;
+      nxt[r] = (VT)0;
+    }
+    int it = beg;
+    int64_t j = 0;
+    if (it < end) {
+      j = perm[it] / s;
+      const VT* p = (const VT*)(A + j * lda);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (valid[r]) cur[r] = p[r * G + lg];
+    }
+    while (it < end) {
+      const int item = perm[it];
+      const double dj = dsc[item / s];
+      const double coef = (double)sign[item] * (is_d2 ? sqrt(dj) : dj);
+      const int nit = it + 1;
+      if (nit < end) {
+        const int64_t nj = perm[nit] / s;
+        const VT* p = (const VT*)(A + nj * lda);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (valid[r]) nxt[r] = p[r * G + lg];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (valid[r])
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cur[r][e];
+#pragma unroll
+      for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+      it = nit;
+    }
+    double* out = B + (int64_t)b * ldb;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (valid[r]) {
+        const int64_t row0 = (int64_t)(r * G + lg) * V;
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (row0 + e < ldb) out[row0 + e] = acc[r][e];
+      }
+  }
+}
+
+// Partials are summed over the block axis by 16 block-lanes x 16 rows per
+// workgroup, then the 16 block-lane sums are added in a fixed tree order.
+template <typename TP>
+__global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int64_t ldp,
+                                                int64_t off, int nblk, int64_t m, double scale,
+                                                const double* __restrict__ add, double beta,
+                                                double* __restrict__ out,
+                                                const int32_t* __restrict__ done) {
+  __shared__ double tile[16][17];
+  if (done && *done) return;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + tx;
+  double acc = 0;
+  if (i < m)
+    for (int b = ty; b < nblk; b += 16) acc += (double)part[(int64_t)b * ldp + off + i];
+  tile[ty][tx] = acc;
+  __syncthreads();
+  for (int h = 8; h > 0; h >>= 1) {
+    if (ty < h) tile[ty][tx] += tile[ty + h][tx];
+    __syncthreads();
+  }
+  if (ty == 0 && i < m) {
+    double v = scale * tile[0][tx];
+    if (add) v += beta * add[i];
+    out[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+struct Shape {
+  int G, R;
+};
+
+Shape pick_shape(int64_t lda, int V) {
+  if (lda <= 16 * V) return {16, 1};
+  if (lda <= 32 * V) return {16, 2};
+  const int64_t per = 64 * V;
+  const int64_t R = (lda + per - 1) / per;
+  static const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  for (int o : opts)
+    if (o >= R) return {64, o};
+  return {0, 0};
+}
+
+template <int R>
+constexpr int threads_for() {
+  return R <= 4 ? 1024 : (R <= 8 ? 512 : 256);
+}
+
+template <typename TA, typename TC, int MODE, int G, int R>
+void launch_one(const Args& a, int nblk, hipStream_t st) {
+  constexpr int NT = threads_for<R>();
+  hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, a);
+}
+
+template <typename TA, typename TC, int MODE>
+int dispatch(const Args& a, int nblk, hipStream_t st) {
+  const Shape sh = pick_shape(a.lda, Vec<TA>::V);
+#define SK_CASE(GG, RR) \
+  if (sh.G == GG && sh.R == RR) { launch_one<TA, TC, MODE, GG, RR>(a, nblk, st); return 0; }
+  SK_CASE(16, 1) SK_CASE(16, 2)
+  SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
+  SK_CASE(64, 6) SK_CASE(64, 8) SK_CASE(64, 12) SK_CASE(64, 16)
+#undef SK_CASE
+  return -1;
+}
+
+template <typename TA, int G, int R>
+void launch_sketch_one(const TA* A, int64_t lda, int s, const double* d2, int is_d2,
+                       const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
+                       double* B, int64_t ldb, hipStream_t st) {
+  constexpr int NT = threads_for<R>() < 512 ? threads_for<R>() : 256;
+  const int per_block = (NT / 64) * (64 / G);
+  int blocks = (w + per_block - 1) / per_block;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_sketch<TA, G, R, NT>), dim3(blocks), dim3(NT), 0, st, A, lda, s, d2,
+                     is_d2, ptr, perm, sign, w, B, ldb);
+}
+
+template <typename TA>
+void sketch_dispatch(const TA* A, int64_t lda, int s, const double* d2, int is_d2,
+                     const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
+                     double* B, int64_t ldb, hipStream_t st) {
+  const Shape sh = pick_shape(lda, Vec<TA>::V);
+#define SK_CASE(GG, RR)                                                              \
+  if (sh.G == GG && sh.R == RR) {                                                    \
+    launch_sketch_one<TA, GG, RR>(A, lda, s, d2, is_d2, ptr, perm, sign, w, B, ldb, st); \
+    return;                                                                          \
+  }
+  SK_CASE(16, 1) SK_CASE(16, 2)
+  SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
+  SK_CASE(64, 6) SK_CASE(64, 8) SK_CASE(64, 12) SK_CASE(64, 16)
+#undef SK_CASE
+}
+
+}  // namespace
+
+int colpass_nblk(int64_t lda, int64_t n, int ta) {
+  const int V = ta == SKIPM_F64 ? 2 : 4;
+  const Shape sh = pick_shape(lda, V);
+  if (sh.G == 0) return 1;
+  const int nt = sh.R <= 4 ? 1024 : (sh.R <= 8 ? 512 : 256);
+  const int64_t slots = (int64_t)(nt / 64) * (64 / sh.G);
+  const int target = nt == 256 ? 512 : 256;
+  int64_t nb = (n + slots * 4 - 1) / (slots * 4);  // at least ~4 columns per slot
+  if (nb > target) nb = target;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+int launch_colpass(ColPass& c, hipStream_t st) {
+  Args a;
+  a.A = c.A;
+  a.lda = c.lda;
+  a.m = c.m;
+  a.n = c.n;
+  a.u = c.u;
+  a.x = c.x;
+  a.s = c.s;
+  a.c = c.c;
+  a.rd = c.rd;
+  a.d2 = c.d2;
+  a.rd_out = c.rd_out;
+  a.d2_out = c.d2_out;
+  a.d2f_out = c.d2f_out;
+  a.ds_out = c.ds_out;
+  a.t_out = c.t_out;
+  a.part = c.part;
+  a.ldp = c.ldp;
+  a.red = c.red;
+  a.sc = c.sc;
+  a.done = c.done;
+  if (c.nblk <= 0) c.nblk = colpass_nblk(c.lda, c.n, c.ta);
+  a.cpb = (c.n + c.nblk - 1) / c.nblk;
+  const int nblk = c.nblk;
+  int rc = -1;
+  if (c.ta == SKIPM_F64 && c.tc == SKIPM_F64) {
+    switch (c.mode) {
+      case COL_NORMAL: rc = dispatch<double, double, COL_NORMAL>(a, nblk, st); break;
+      case COL_PROLOGUE: rc = dispatch<double, double, COL_PROLOGUE>(a, nblk, st); break;
+      case COL_EPILOGUE: rc = dispatch<double, double, COL_EPILOGUE>(a, nblk, st); break;
+      case COL_DOT: rc = dispatch<double, double, COL_DOT>(a, nblk, st); break;
+      case COL_AXPY: rc = dispatch<double, double, COL_AXPY>(a, nblk, st); break;
+    }
+  } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F64) {
+    switch (c.mode) {
+      case COL_NORMAL: rc = dispatch<float, double, COL_NORMAL>(a, nblk, st); break;
+      case COL_PROLOGUE: rc = dispatch<float, double, COL_PROLOGUE>(a, nblk, st); break;
+      case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, st); break;
+      case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, st); break;
+    }
+  } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F32) {
+    switch (c.mode) {
+      case COL_NORMAL: rc = dispatch<float, float, COL_NORMAL>(a, nblk, st); break;
+      case COL_DOT: rc = dispatch<float, float, COL_DOT>(a, nblk, st); break;
+    }
+  }
+  return rc;
+}
+
+void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t n, int s,
+                         const double* dscale, int is_d2, const int32_t* ptr,
+                         const int32_t* perm, const int8_t* sign, int w, double* B,
+                         int64_t ldb, hipStream_t st) {
+  (void)m;
+  (void)n;
+  if (ta == SKIPM_F64)
+    sketch_dispatch<double>((const double*)A, lda, s, dscale, is_d2, ptr, perm, sign, w, B, ldb,
+                            st);
+  else
+    sketch_dispatch<float>((const float*)A, lda, s, dscale, is_d2, ptr, perm, sign, w, B, ldb,
+                           st);
+}
+
+void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,
+                   double scale, const double* add, double beta, double* out,
+                   const int32_t* done, hipStream_t st) {
+  const unsigned blocks = (unsigned)((m + 15) / 16);
+  if (tc == SKIPM_F64)
+    hipLaunchKernelGGL(k_finish<double>, dim3(blocks), dim3(256), 0, st, (const double*)part,
+                       ldp, off, nblk, m, scale, add, beta, out, done);
+  else
+    hipLaunchKernelGGL(k_finish<float>, dim3(blocks), dim3(256), 0, st, (const float*)part, ldp,
+                       off, nblk, m, scale, add, beta, out, done);
+}
+
+}  // namespace skipm

@@ -1,0 +1,186 @@
+// Internal declarations shared by the HIP translation units of libskipm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/skipm.h"
+
+namespace skipm {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define SK_CHECK_HIP(expr)                                                         \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::skipm::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return SKIPM_EDEVICE;                                                        \
+    }                                                                              \
+  } while (0)
+
+#define SK_TRY(expr)                  \
+  do {                                \
+    int rc_ = (expr);                 \
+    if (rc_ != SKIPM_OK) return rc_;  \
+  } while (0)
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// device scalar slots (one FP64 array per handle)
+// ---------------------------------------------------------------------------
+enum Slot : int {
+  S_MU = 0,      // x^T s / n of the current iterate
+  S_XS,          // x^T s
+  S_CTX,         // c^T x
+  S_BTY,         // b^T y
+  S_RP2,         // ||r_p||^2
+  S_RD2,         // ||r_d||^2
+  S_A0, S_A1, S_A2,  // step sums x^T s, x^T ds + s^T dx, dx^T ds
+  S_VSUM, S_V2,  // 1^T v, ||v||^2
+  S_AMAX, S_ALPHA,
+  S_ETA,         // ||r^k|| / ||r^0||
+  S_MU0,         // mu of the origin
+  S_R0,          // ||r^0||
+  S_SIGMA, S_GAMMA, S_GUARD,
+  S_EXIT,        // min first-exit over the per-entry conditions
+  S_BOUND,       // distance to the boundary of x, s > 0
+  // CG state
+  S_CG_RZ, S_CG_RZ0, S_CG_TOL2, S_CG_PQ,
+  S_V_RR, S_V_GG, // v-solve: ||r||^2, ||g||^2
+  S_NSLOTS = 40
+};
+
+enum IntSlot : int {
+  I_CG_ITERS = 0,   // iterations performed by the running CG
+  I_CG_DONE,        // 1: converged (or broke down); later CG kernels return at once
+  I_CG_MAX,         // iteration cap of the running CG
+  I_FACT_FAIL,      // non-positive pivot met while inverting the Gram matrix
+  I_CG_RESID,       // 1: stop on the residual r^T r, 0: on r^T z
+  I_NINTS = 8
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each defined in the .hip file that owns the kernel)
+// ---------------------------------------------------------------------------
+
+// fill / copy helpers
+void launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void launch_copy_f64(double* dst, const double* src, int64_t n, hipStream_t st);
+void launch_convert_f64_f32(float* dst, const double* src, int64_t n, hipStream_t st);
+void launch_pad_copy_f64(double* dst, int64_t ldd, const double* src, int64_t lds,
+                         int64_t m, int64_t n, hipStream_t st);
+void launch_pad_copy_f32(float* dst, int64_t ldd, const float* src, int64_t lds,
+                         int64_t m, int64_t n, hipStream_t st);
+void launch_pad_copy_f64_to_f32(float* dst, int64_t ldd, const double* src, int64_t lds,
+                                int64_t m, int64_t n, hipStream_t st);
+
+// hash + counting sort of (row, block) items by bucket
+void launch_hash(uint64_t seed, int64_t k, int s, int64_t n, int w, int32_t* bucket,
+                 int8_t* sign, int32_t* count, hipStream_t st);
+void launch_bucket_scan(const int32_t* count, int32_t* ptr, int32_t* cursor, int w,
+                        hipStream_t st);
+void launch_bucket_scatter(const int32_t* bucket, int64_t nitems, const int32_t* ptr,
+                           int32_t* cursor, int32_t* perm, hipStream_t st);
+void launch_bucket_sort(const int32_t* ptr, const int32_t* raw, int32_t* perm, int w,
+                        hipStream_t st);
+
+// dense column passes
+struct ColPass {
+  int mode;                 // see COL_* below
+  const void* A;            // column-major, element type ta
+  int ta;                   // SKIPM_F64 / SKIPM_F32
+  int tc;                   // accumulate in SKIPM_F64 / SKIPM_F32
+  int64_t lda, m, n;
+  const void* u;            // m-vector (type tc) for the column dots
+  const double* x;          // per-column inputs (FP64)
+  const double* s;
+  const double* c;
+  const double* rd;
+  const void* d2;           // column scale (type tc), NULL = 1; COL_AXPY: the coefficients
+  double* rd_out;
+  double* d2_out;
+  float* d2f_out;
+  double* ds_out;
+  void* t_out;              // per-column dot a_j^T u (type tc)
+  void* part;               // [nblk][nacc*ldp] partial sums (type tc)
+  int64_t ldp;
+  double* red;              // [nblk][8] partial scalars (prologue)
+  const double* sc;         // device scalar slots
+  const int32_t* done;      // optional early-exit flag
+  int nblk;                 // filled by the launcher
+};
+enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
+int launch_colpass(ColPass& a, hipStream_t st);
+int colpass_nblk(int64_t lda, int64_t n, int ta);
+
+// bucket-ordered sketch B[:, b] = sum over items in bucket b of sign * d_j * A[:, j]
+// (dscale holds d, or d^2 when is_d2 != 0)
+void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t n, int s,
+                         const double* dscale, int is_d2, const int32_t* ptr,
+                         const int32_t* perm, const int8_t* sign, int w, double* B,
+                         int64_t ldb, hipStream_t st);
+
+// sum of partials along the block axis: out[i] = scale*sum_b part[b][off+i] + beta*add[i]
+void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,
+                   double scale, const double* add, double beta, double* out,
+                   const int32_t* done, hipStream_t st);
+
+// Gram matrix and its inverse (blocked Cholesky, triangular inverse, X^T X)
+void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart,
+                 int ksplit, int64_t mp, hipStream_t st);
+void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, double* G,
+                        hipStream_t st);
+int chol_block(int64_t mp);
+// G (mp x mp, SPD) -> G^{-1} in place via Cholesky; Xb: mp x mp scratch (holds L^{-1})
+void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail,
+                        hipStream_t st);
+void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t st);
+// Out = X In, X block-lower-triangular mp x mp
+void launch_trmm(const double* X, int64_t mp, int nb, const double* In, int64_t ldin,
+                 int64_t nrows, int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out,
+                 hipStream_t st);
+void launch_shift_trace(double* G, int64_t mp, int64_t m, double c, hipStream_t st);
+// sc[slot] = ||u||^2 over m entries (single workgroup)
+void launch_norm2(const double* u, int64_t m, double* sc, int slot, hipStream_t st);
+void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+
+// single-workgroup CG kernels
+void launch_cg_init(int64_t m, const double* p, const double* z, double* r, double* zz,
+                    double* d, float* df, double* x, double* tw, int64_t nw, double* sc,
+                    int32_t* is, double tol, int max_it, int resid_test, hipStream_t st);
+void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
+                      double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
+                      double* sc, int32_t* is, hipStream_t st);
+
+// n-vector kernels of the IPM iteration
+void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,
+                              const double* red, int nblk, double* sc, int set_origin,
+                              hipStream_t st);
+void launch_mu_finalize(const double* red, int nblk, int64_t n, double* sc, hipStream_t st);
+void launch_direction(int64_t n, int s, const double* x, const double* sv, const double* d2,
+                      const double* ds, const int32_t* bucket, const int8_t* sign,
+                      const double* tw, double* v, double* dx, double* red, int nblk,
+                      const double* sc, hipStream_t st);
+void launch_reduce_slots(const double* red, int nblk, int nq, double* sc, int slot0,
+                         int op, hipStream_t st);
+void launch_step_terms(int64_t n, const double* x, const double* s, const double* dx,
+                       const double* ds, double* red, int nblk, const double* sc,
+                       hipStream_t st);
+void launch_step_finalize(int64_t n, double* sc, hipStream_t st);
+void launch_update(int64_t n, int64_t m, double* x, double* y, double* s, const double* dx,
+                   const double* dy, const double* ds, double* red, int nblk,
+                   const double* sc, hipStream_t st);
+void launch_xs_sum(int64_t n, const double* x, const double* s, double* red, int nblk,
+                   hipStream_t st);
+void launch_sqrt_vec(int64_t n, const double* in, double* out, hipStream_t st);
+int vec_nblk(int64_t n);
+
+}  // namespace skipm

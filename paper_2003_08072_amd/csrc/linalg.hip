@@ -1,0 +1,498 @@
+// Preconditioner build: the Gram matrix Q = B B^T of the sketch B = A D W
+// (eq. pdprecond) and its inverse Q^{-1}, applied inside CG as a dense GEMV.
+//
+// Q^{-1} instead of Q^{-1/2}: CG on the split system of eq. precond_alt and CG
+// preconditioned with M = Q on eq. precond produce the same iterates dy
+// (Q^{-1/2} z_j = dy_j), so the square root never has to be formed.  The
+// inverse is formed as X^T X with X = L^{-1} from a blocked Cholesky factor
+// L of Q (two launches per block column), then a blocked triangular inverse
+// (one launch per block row) and one launch for X^T X.
+#include "common.h"
+
+namespace skipm {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, 64x64 tiles of the lower
+// triangle, mirrored to the upper triangle.  G is mp x mp, column-major.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int64_t ldb,
+                                              int64_t m, int64_t w, double* __restrict__ Gpart,
+                                              int64_t mp, int64_t cols_per_split) {
+  __shared__ double Ai[16][64 + 1];
+  __shared__ double Ak[16][64 + 1];
+  // decode the lower-triangle tile pair (ti >= tk)
+  int t = blockIdx.x, ti = 0;
+  while (t > ti) {
+    t -= ti + 1;
+    ++ti;
+  }
+  const int tk = t;
+  const int ks = blockIdx.y;
+  const int64_t i0 = (int64_t)ti * 64, k0 = (int64_t)tk * 64;
+  const int64_t cb = (int64_t)ks * cols_per_split;
+  const int64_t ce = cb + cols_per_split < w ? cb + cols_per_split : w;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  for (int64_t c = cb; c < ce; c += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int cc = idx >> 6, rr = idx & 63;
+      const int64_t col = c + cc;
+      double vi = 0, vk = 0;
+      if (col < ce) {
+        if (i0 + rr < m) vi = B[col * ldb + i0 + rr];
+        if (k0 + rr < m) vk = B[col * ldb + k0 + rr];
+      }
+      Ai[cc][rr] = vi;
+      Ak[cc][rr] = vk;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Ai[cc][ty * 4 + q];
+        b[q] = Ak[cc][tx * 4 + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    }
+    __syncthreads();
+  }
+  double* G = Gpart + (int64_t)ks * mp * mp;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + ty * 4 + p, k = k0 + tx * 4 + q;
+      G[i + k * mp] = acc[p][q];
+      G[k + i * mp] = acc[p][q];
+    }
+}
+
+// G = sum of the split partials on the m x m block; identity on the padding.
+__global__ __launch_bounds__(256) void k_gram_finish(const double* __restrict__ Gpart, int ksplit,
+                                                     int64_t m, int64_t mp,
+                                                     double* __restrict__ G) {
+  const int64_t total = mp * mp;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e % mp, k = e / mp;
+    double v;
+    if (i < m && k < m) {
+      v = 0;
+      for (int q = 0; q < ksplit; ++q) v += Gpart[(int64_t)q * total + e];
+    } else {
+      v = (i == k) ? 1.0 : 0.0;
+    }
+    G[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_shift_diag(double* __restrict__ G, int64_t mp, int64_t m,
+                                                    double rel) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) G[i + i * mp] *= (1.0 + rel);
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Cholesky G = L L^T (lower, in place), explicit X = L^{-1} (block lower
+// triangular, stored in Xb) and P = X^T X = G^{-1} (written over G).
+// P is applied by one GEMV per CG iteration.  Because L is a backward-stable
+// factor and X has a small residual, X^T X G has eigenvalues within u*kappa(G)
+// of one, unlike a Gauss-Jordan inverse of G.
+// ---------------------------------------------------------------------------
+
+// Unblocked Cholesky of the NB x NB tile T (LDS, lower part), then the inverse
+// of the factor into Xt (lower, zero above the diagonal).
+template <int NB>
+__device__ void lds_potrf_trinv(double (*T)[NB + 1], double (*Xt)[NB + 1], int32_t* fail) {
+  for (int p = 0; p < NB; ++p) {
+    if (threadIdx.x == 0) {
+      double d = T[p][p];
+      if (!(d > 0.0)) {
+        atomicOr(fail, 1);
+        d = 1e-300;
+      }
+      T[p][p] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = T[p][p];
+    for (int i = p + 1 + threadIdx.x; i < NB; i += blockDim.x) T[i][p] /= piv;
+    __syncthreads();
+    const int rem = NB - p - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int i = p + 1 + e / rem, j = p + 1 + e % rem;
+      if (j <= i) T[i][j] -= T[i][p] * T[j][p];
+    }
+    __syncthreads();
+  }
+  // zero the strict upper part of the factor
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    if (j > i) T[i][j] = 0.0;
+  }
+  __syncthreads();
+  // column c of L^{-1} by forward substitution (one thread per column)
+  for (int c = threadIdx.x; c < NB; c += blockDim.x) {
+    for (int i = 0; i < c; ++i) Xt[i][c] = 0.0;
+    Xt[c][c] = 1.0 / T[c][c];
+    for (int i = c + 1; i < NB; ++i) {
+      double acc = 0.0;
+      for (int j = c; j < i; ++j) acc += T[i][j] * Xt[j][c];
+      Xt[i][c] = -acc / T[i][i];
+    }
+  }
+  __syncthreads();
+}
+
+// Panel step k.  Every block factors G_kk in LDS; block 0 stores X_kk = L_kk^{-1}
+// in Xb, block b > 0 overwrites row block i = k + b with L_ik = G_ik X_kk^T.
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ G, double* __restrict__ Xb,
+                                                    int64_t mp, int k,
+                                                    int32_t* __restrict__ fail) {
+  __shared__ double T[NB][NB + 1];
+  __shared__ double Xt[NB][NB + 1];
+  const int64_t K0 = (int64_t)k * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    T[r][c] = G[(K0 + r) + (K0 + c) * mp];
+  }
+  __syncthreads();
+  lds_potrf_trinv<NB>(T, Xt, fail);
+  if (blockIdx.x == 0) {
+    // L_kk itself is not needed later (only X_kk and the off-diagonal L_ik are),
+    // and G_kk must stay intact while the other blocks of this launch read it.
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+      const int r = e % NB, c = e / NB;
+      Xb[(K0 + r) + (K0 + c) * mp] = Xt[r][c];
+    }
+    return;
+  }
+  // reuse T for the row block G_ik
+  __syncthreads();
+  const int64_t I0 = K0 + (int64_t)blockIdx.x * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    T[r][c] = G[(I0 + r) + (K0 + c) * mp];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    double acc = 0.0;
+    for (int q = 0; q <= c; ++q) acc += T[r][q] * Xt[c][q];  // (G_ik X_kk^T)_rc
+    G[(I0 + r) + (K0 + c) * mp] = acc;
+  }
+}
+
+// C[I, J] (+)= sign * sum_q A[I, q-block] B[J, q-block]^T over a range of q
+// blocks, with NB x NB tiles staged through LDS (16 x 16 threads, TW x TW each).
+template <int NB>
+struct TileAcc {
+  static constexpr int TW = NB / 16;
+  double acc[TW][TW];
+  __device__ void zero() {
+#pragma unroll
+    for (int p = 0; p < TW; ++p)
+#pragma unroll
+      for (int o = 0; o < TW; ++o) acc[p][o] = 0.0;
+  }
+  // acc += At * Bt^T   (At, Bt: NB x NB tiles in LDS, row index first)
+  __device__ void mma_nt(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int q = 0; q < NB; ++q) {
+      double a[TW], b[TW];
+#pragma unroll
+      for (int p = 0; p < TW; ++p) {
+        a[p] = At[ty * TW + p][q];
+        b[p] = Bt[tx * TW + p][q];
+      }
+#pragma unroll
+      for (int p = 0; p < TW; ++p)
+#pragma unroll
+        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
+    }
+  }
+  // acc += At^T * Bt
+  __device__ void mma_tn(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int q = 0; q < NB; ++q) {
+      double a[TW], b[TW];
+#pragma unroll
+      for (int p = 0; p < TW; ++p) {
+        a[p] = At[q][ty * TW + p];
+        b[p] = Bt[q][tx * TW + p];
+      }
+#pragma unroll
+      for (int p = 0; p < TW; ++p)
+#pragma unroll
+        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
+    }
+  }
+  // acc += At * Bt
+  __device__ void mma_nn(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int q = 0; q < NB; ++q) {
+      double a[TW], b[TW];
+#pragma unroll
+      for (int p = 0; p < TW; ++p) {
+        a[p] = At[ty * TW + p][q];
+        b[p] = Bt[q][tx * TW + p];
+      }
+#pragma unroll
+      for (int p = 0; p < TW; ++p)
+#pragma unroll
+        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
+    }
+  }
+};
+
+template <int NB>
+__device__ void load_tile(double (*Tt)[NB + 1], const double* __restrict__ M, int64_t ld,
+                          int64_t r0, int64_t c0) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    Tt[r][c] = M[(r0 + r) + (c0 + c) * ld];
+  }
+}
+
+// Trailing update of step k: G_ij -= L_ik L_jk^T for k < j <= i (lower triangle).
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int64_t mp, int k) {
+  __shared__ double Ai[NB][NB + 1];
+  __shared__ double Aj[NB][NB + 1];
+  int t = blockIdx.x, di = 0;  // decode (di >= dj) over the trailing blocks
+  while (t > di) {
+    t -= di + 1;
+    ++di;
+  }
+  const int bi = k + 1 + di, bj = k + 1 + t;
+  const int64_t K0 = (int64_t)k * NB, I0 = (int64_t)bi * NB, J0 = (int64_t)bj * NB;
+  load_tile<NB>(Ai, G, mp, I0, K0);
+  load_tile<NB>(Aj, G, mp, J0, K0);
+  __syncthreads();
+  TileAcc<NB> ta;
+  ta.zero();
+  ta.mma_nt(Ai, Aj);
+  constexpr int TW = NB / 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int p = 0; p < TW; ++p)
+#pragma unroll
+    for (int o = 0; o < TW; ++o) {
+      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
+      G[gi + gj * mp] -= ta.acc[p][o];
+    }
+}
+
+// Off-diagonal blocks of X = L^{-1}, block row i: for k < i,
+//   X_ik = -X_ii * sum_{j=k}^{i-1} L_ij X_jk      (one workgroup per k)
+template <int NB>
+__global__ __launch_bounds__(256) void k_trinv_row(const double* __restrict__ G,
+                                                   double* __restrict__ Xb, int64_t mp, int i) {
+  __shared__ double At[NB][NB + 1];
+  __shared__ double Bt[NB][NB + 1];
+  const int k = blockIdx.x;
+  const int64_t I0 = (int64_t)i * NB, K0 = (int64_t)k * NB;
+  TileAcc<NB> ta;
+  ta.zero();
+  for (int j = k; j < i; ++j) {
+    const int64_t J0 = (int64_t)j * NB;
+    __syncthreads();
+    load_tile<NB>(At, G, mp, I0, J0);   // L_ij
+    load_tile<NB>(Bt, Xb, mp, J0, K0);  // X_jk
+    __syncthreads();
+    ta.mma_nn(At, Bt);
+  }
+  // S -> LDS (Bt), then X_ik = -X_ii S
+  constexpr int TW = NB / 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < TW; ++p)
+#pragma unroll
+    for (int o = 0; o < TW; ++o) Bt[ty * TW + p][tx * TW + o] = ta.acc[p][o];
+  load_tile<NB>(At, Xb, mp, I0, I0);  // X_ii
+  __syncthreads();
+  ta.zero();
+  ta.mma_nn(At, Bt);
+#pragma unroll
+  for (int p = 0; p < TW; ++p)
+#pragma unroll
+    for (int o = 0; o < TW; ++o) {
+      const int64_t gi = I0 + ty * TW + p, gk = K0 + tx * TW + o;
+      Xb[gi + gk * mp] = -ta.acc[p][o];
+    }
+}
+
+// P = X^T X: P_ij = sum_{l >= i} X_li^T X_lj for j <= i, mirrored; written over G.
+template <int NB>
+__global__ __launch_bounds__(256) void k_xtx(const double* __restrict__ Xb, double* __restrict__ G,
+                                             int64_t mp, int T) {
+  __shared__ double At[NB][NB + 1];
+  __shared__ double Bt[NB][NB + 1];
+  int t = blockIdx.x, bi = 0;
+  while (t > bi) {
+    t -= bi + 1;
+    ++bi;
+  }
+  const int bj = t;
+  const int64_t I0 = (int64_t)bi * NB, J0 = (int64_t)bj * NB;
+  TileAcc<NB> ta;
+  ta.zero();
+  for (int l = bi; l < T; ++l) {
+    const int64_t L0 = (int64_t)l * NB;
+    __syncthreads();
+    load_tile<NB>(At, Xb, mp, L0, I0);  // X_li
+    load_tile<NB>(Bt, Xb, mp, L0, J0);  // X_lj
+    __syncthreads();
+    ta.mma_tn(At, Bt);
+  }
+  constexpr int TW = NB / 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int p = 0; p < TW; ++p)
+#pragma unroll
+    for (int o = 0; o < TW; ++o) {
+      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
+      G[gi + gj * mp] = ta.acc[p][o];
+      G[gj + gi * mp] = ta.acc[p][o];
+    }
+}
+
+// Out = X * In for X block-lower-triangular (mp x mp, ld mp; only blocks
+// k <= i are read) and In with nrows valid rows (ld ldin; rows beyond are zero)
+// and ncols columns.  Rows < nrows_out of Out are written.
+template <int NB>
+__global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ X, int64_t mp,
+                                              const double* __restrict__ In, int64_t ldin,
+                                              int64_t nrows, int64_t ncols,
+                                              double* __restrict__ Out, int64_t ldout,
+                                              int64_t nrows_out) {
+  __shared__ double At[NB][NB + 1];
+  __shared__ double Bt[NB][NB + 1];
+  const int bi = blockIdx.x;
+  const int64_t I0 = (int64_t)bi * NB, J0 = (int64_t)blockIdx.y * NB;
+  TileAcc<NB> ta;
+  ta.zero();
+  for (int kb = 0; kb <= bi; ++kb) {
+    const int64_t K0 = (int64_t)kb * NB;
+    __syncthreads();
+    load_tile<NB>(At, X, mp, I0, K0);
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+      const int r = e % NB, c = e / NB;
+      const int64_t gr = K0 + r, gc = J0 + c;
+      Bt[r][c] = (gr < nrows && gc < ncols) ? In[gr + gc * ldin] : 0.0;
+    }
+    __syncthreads();
+    ta.mma_nn(At, Bt);
+  }
+  constexpr int TW = NB / 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int p = 0; p < TW; ++p)
+#pragma unroll
+    for (int o = 0; o < TW; ++o) {
+      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
+      if (gi < nrows_out && gj < ncols) Out[gi + gj * ldout] = ta.acc[p][o];
+    }
+}
+
+// G_ii += c * trace(G) for i < m (single workgroup): the shift of shifted
+// Cholesky QR, with ||B||_2^2 bounded by ||B||_F^2 = trace(B B^T).
+__global__ __launch_bounds__(1024) void k_shift_trace(double* __restrict__ G, int64_t mp, int64_t m,
+                                                      double c) {
+  __shared__ double buf[16];
+  double tr = 0;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) tr += G[i + i * mp];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = tr;
+  __syncthreads();
+  double tot = 0;
+  for (int q = 0; q < 16; ++q) tot += buf[q];
+  for (int64_t i = threadIdx.x; i < m; i += 1024) G[i + i * mp] += c * tot;
+}
+
+}  // namespace
+
+void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart, int ksplit,
+                 int64_t mp, hipStream_t st) {
+  const int T = (int)(mp / 64);
+  const int ntiles = T * (T + 1) / 2;
+  int64_t cps = (w + ksplit - 1) / ksplit;
+  cps = (cps + 15) / 16 * 16;
+  hipLaunchKernelGGL(k_gram, dim3(ntiles, ksplit), dim3(256), 0, st, B, ldb, m, w, Gpart, mp,
+                     cps);
+}
+
+void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, double* G,
+                        hipStream_t st) {
+  int64_t blocks = (mp * mp + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)blocks), dim3(256), 0, st, Gpart, ksplit, m,
+                     mp, G);
+}
+
+int chol_block(int64_t mp) { return mp <= 256 ? 32 : 64; }  // mp is a multiple of 64
+
+void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail,
+                        hipStream_t st) {
+  const int T = (int)(mp / nb);
+  for (int k = 0; k < T; ++k) {
+    const int rest = T - k - 1;
+    if (nb == 32) {
+      hipLaunchKernelGGL(k_chol_panel<32>, dim3(rest + 1), dim3(256), 0, st, G, Xb, mp, k, fail);
+      if (rest > 0)
+        hipLaunchKernelGGL(k_chol_update<32>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
+                           mp, k);
+    } else {
+      hipLaunchKernelGGL(k_chol_panel<64>, dim3(rest + 1), dim3(256), 0, st, G, Xb, mp, k, fail);
+      if (rest > 0)
+        hipLaunchKernelGGL(k_chol_update<64>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
+                           mp, k);
+    }
+  }
+  for (int i = 1; i < T; ++i) {
+    if (nb == 32)
+      hipLaunchKernelGGL(k_trinv_row<32>, dim3(i), dim3(256), 0, st, G, Xb, mp, i);
+    else
+      hipLaunchKernelGGL(k_trinv_row<64>, dim3(i), dim3(256), 0, st, G, Xb, mp, i);
+  }
+  const int npairs = T * (T + 1) / 2;
+  if (nb == 32)
+    hipLaunchKernelGGL(k_xtx<32>, dim3(npairs), dim3(256), 0, st, Xb, G, mp, T);
+  else
+    hipLaunchKernelGGL(k_xtx<64>, dim3(npairs), dim3(256), 0, st, Xb, G, mp, T);
+}
+
+void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, G, mp, m,
+                     rel);
+}
+
+void launch_trmm(const double* X, int64_t mp, int nb, const double* In, int64_t ldin,
+                 int64_t nrows, int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out,
+                 hipStream_t st) {
+  const int T = (int)(mp / nb);
+  const unsigned gy = (unsigned)((ncols + nb - 1) / nb);
+  if (nb == 32)
+    hipLaunchKernelGGL(k_trmm<32>, dim3(T, gy), dim3(256), 0, st, X, mp, In, ldin, nrows, ncols,
+                       Out, ldout, nrows_out);
+  else
+    hipLaunchKernelGGL(k_trmm<64>, dim3(T, gy), dim3(256), 0, st, X, mp, In, ldin, nrows, ncols,
+                       Out, ldout, nrows_out);
+}
+
+void launch_shift_trace(double* G, int64_t mp, int64_t m, double c, hipStream_t st) {
+  hipLaunchKernelGGL(k_shift_trace, dim3(1), dim3(1024), 0, st, G, mp, m, c);
+}
+
+}  // namespace skipm

@@ -1,0 +1,311 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Every case prints its name before touching the GPU.  Tolerances:
+  * hash buckets and signs: bit-exact;
+  * sketch B: |B - B_ref| <= k u sum|terms| (k = largest bucket, order of sums differs);
+  * CG iterates at a fixed iteration count: relative 1e-9 (same Krylov method,
+    different rounding order); at the IPM's stopping tolerance, a tenth of the
+    iterate's own distance to the exact solve;
+  * CG to a tight tolerance vs Cholesky: relative 1e-8 on iterates with
+    kappa(A D^2 A^T) <= 1e7;
+  * invariants eq. addl / iip_3 on the GPU's own FP64 directions: 1e-12 of the
+    size of the terms that cancel in them;
+  * step length from the GPU's directions vs the oracle's rule: relative 1e-10;
+  * final objective vs the planted optimum and the exact oracle: the stopping
+    tolerance eps_gap; KKT residuals <= 1e-8 ||b||, ||c||.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from lpgen import config_lp, dense_planted
+from oracle import ipm as O
+from oracle.sketch import sketch_hash as ref_hash
+from oracle.sketch import sketch_matrix
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2003_08072_amd as _sk
+    _sk.load()
+    return _sk
+
+
+def mid_iterate(lp, iters):
+    x, y, s = np.ones(lp.n), np.zeros(lp.m), np.ones(lp.n)
+    rp0, rd0 = O.residuals(lp.A, lp.b, lp.c, x, y, s)
+    r0 = math.hypot(np.linalg.norm(rp0), np.linalg.norm(rd0))
+    for _ in range(iters):
+        d = O.exact_direction(lp.A, lp.b, lp.c, x, y, s, 0.5)
+        eta = math.hypot(np.linalg.norm(d.rp), np.linalg.norm(d.rd)) / r0
+        st = O.step_length(x, s, d.dx, d.ds, 0.999, 1.0, eta, 1e-3)
+        x, y, s = x + st.alpha * d.dx, y + st.alpha * d.dy, s + st.alpha * d.ds
+    return x, y, s
+
+
+# ---------------------------------------------------------------------------
+# a2: hash (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,k,s,n,w", [
+    (0, 0, 1, 1000, 200),
+    (0x5EED0001, 7, 1, 100_000, 2000),
+    (123, 3, 2, 1_000_000, 4000),
+    (9, 1, 4, 12345, 64),
+    (1, 0, 1, 10, 7),
+    (2**63 + 5, 2**40, 3, 3001, 33),
+])
+def test_hash_bit_exact(torch, sk, seed, k, s, n, w):
+    say(f"hash seed={seed} k={k} s={s} n={n} w={w}")
+    bucket = torch.empty(n * s, dtype=torch.int32, device="cuda")
+    sign = torch.empty(n * s, dtype=torch.int8, device="cuda")
+    sk.sketch_hash(seed, k, s, n, w, bucket, sign)
+    rb, rs = ref_hash(seed, k, s, n, w)
+    assert np.array_equal(bucket.cpu().numpy(), rb.ravel().astype(np.int32))
+    assert np.array_equal(sign.cpu().numpy(), rs.ravel())
+
+
+# ---------------------------------------------------------------------------
+# a2: sketch B = A D W
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,w,s,dtype", [
+    (37, 500, 150, 2, "f64"), (50, 1000, 200, 1, "f64"), (5, 64, 8, 1, "f64"),
+    (130, 3000, 520, 4, "f64"), (61, 2000, 244, 1, "f32"), (257, 2000, 1028, 2, "f64"),
+])
+def test_sketch_apply(torch, sk, m, n, w, s, dtype):
+    say(f"sketch m={m} n={n} w={w} s={s} {dtype}")
+    rng = np.random.default_rng(m * 7 + n)
+    lp = dense_planted(m, n, rng=rng, a_dtype=dtype)
+    d = rng.uniform(0.01, 10.0, n) * rng.choice([-1.0, 1.0], n)
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype=dtype, w=w, s=s, seed=77) as h:
+        B = h.sketch(d, 5).cpu().numpy()
+    W = sketch_matrix(77, 5, s, n, w)
+    AD = lp.A * d
+    Bref = np.asarray((W.T @ AD.T).T)
+    bound = np.asarray((abs(W).T @ abs(AD).T).T)
+    kmax = int(np.diff(W.tocsc().indptr).max())
+    assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# a3/a4: preconditioned CG
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cg_case():
+    lp = dense_planted(40, 800, rng=np.random.default_rng(8))
+    x, y, s = mid_iterate(lp, 6)
+    return lp, x, s
+
+
+@pytest.mark.parametrize("t", [1, 3, 8])
+def test_pcg_fixed_iterations_match_alg1(torch, sk, cg_case, t):
+    lp, x, s = cg_case
+    say(f"pcg fixed t={t}")
+    d2 = x / s
+    p = np.random.default_rng(t).standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, seed=31, s=2) as h:
+        dy, info = h.pcg(d2, p, 4, tol=0.0, max_it=t)
+        dy = dy.cpu().numpy()
+    assert info.iters == t
+    W = sketch_matrix(31, 4, 2, lp.n, lp.w)
+    ref = O.sketch_pcg(lp.A * np.sqrt(d2), p, W, t=t)
+    assert np.linalg.norm(dy - ref.dy) <= 1e-9 * np.linalg.norm(ref.dy)
+    assert info.f_norm == pytest.approx(ref.f_norms[-1], rel=1e-6)
+    assert info.f0_norm == pytest.approx(ref.f_norms[0], rel=1e-10)
+
+
+@pytest.mark.parametrize("iters", [2, 10])
+def test_pcg_tight_tolerance_matches_cholesky(torch, sk, cg_case, iters):
+    lp, _, _ = cg_case
+    x, y, s = mid_iterate(lp, iters)
+    say(f"pcg vs cholesky at exact-IPM iterate {iters}")
+    d2 = x / s
+    N = (lp.A * d2) @ lp.A.T
+    assert np.linalg.cond(N) <= 1e7
+    p = np.random.default_rng(1).standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, seed=3) as h:
+        dy, info = h.pcg(d2, p, 0, tol=1e-13, max_it=300)
+        dy = dy.cpu().numpy()
+    ref = np.linalg.solve(N, p)
+    assert np.linalg.norm(dy - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_pcg_signed_permutation_sketch_one_iteration(torch, sk):
+    """w = n with s = n/w... a sketch whose buckets are all distinct makes
+    Q = A D^2 A^T, so CG converges in one iteration (special case of Alg. 1)."""
+    rng = np.random.default_rng(2)
+    lp = dense_planted(12, 60, rng=rng)
+    # find a seed whose hash is injective for n = w = 60 blocks of width 1 (s = 60 is
+    # out of range), so use s = 1, w >> n and search a salt with no collision
+    w = 4096
+    for k in range(2000):
+        b, _ = ref_hash(5, k, 1, lp.n, w)
+        if len(np.unique(b)) == lp.n:
+            break
+    else:
+        pytest.skip("no injective salt found")
+    say(f"pcg injective sketch k={k}")
+    d2 = rng.uniform(0.1, 10.0, lp.n)
+    p = rng.standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, seed=5, w=w) as h:
+        dy, info = h.pcg(d2, p, k, tol=1e-10, max_it=50)
+        dy = dy.cpu().numpy()
+    assert info.iters == 1
+    ref = np.linalg.solve((lp.A * d2) @ lp.A.T, p)
+    assert np.linalg.norm(dy - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+# a1, a5-a9: one IPM step from an iterate shared with the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("iters,s_nnz", [(0, 1), (4, 1), (9, 2)])
+def test_ipm_step_parity(torch, sk, iters, s_nnz):
+    lp = dense_planted(45, 900, rng=np.random.default_rng(33))
+    x, y, s = mid_iterate(lp, iters)
+    say(f"ipm_step parity from exact-IPM iterate {iters}, s={s_nnz}")
+    with sk.LP(lp.A, lp.b, lp.c, seed=17, s=s_nnz) as h:
+        h.set_iterate(x, y, s, reset_origin=True)
+        info = h.step()
+        dx, dy, ds, v = (t.cpu().numpy() for t in h.get_direction())
+        xn, yn, sn = (t.cpu().numpy() for t in h.get_iterate())
+    assert info.converged == 0 and info.status == 0
+    A, b, c = lp.A, lp.b, lp.c
+    rp, rd = O.residuals(A, b, c, x, y, s)
+    mu = float(x @ s) / lp.n
+    assert info.mu == pytest.approx(mu, rel=1e-12)
+    # residual norms at the rounding scale of the products that form them
+    tol_rp = 64 * EPS * (np.linalg.norm(abs(A) @ abs(x)) + np.linalg.norm(b))
+    tol_rd = 64 * EPS * (np.linalg.norm(abs(A).T @ abs(y)) + np.linalg.norm(s) + np.linalg.norm(c))
+    assert info.rp_norm == pytest.approx(np.linalg.norm(rp), rel=1e-10, abs=tol_rp)
+    assert info.rd_norm == pytest.approx(np.linalg.norm(rd), rel=1e-10, abs=tol_rd)
+    p = O.normal_rhs(A, b, c, x, y, s, 0.5, mu)
+    d2 = x / s
+    g = A @ (d2 * (A.T @ dy)) - p
+    # g cancels terms of size ~||p||: compare at the rounding scale of those terms
+    scale_g = np.linalg.norm(abs(A) @ (d2 * abs(A.T @ dy))) + np.linalg.norm(p)
+    assert np.linalg.norm(v) > 0
+    # eq. addl (Lemma 3): A S^{-1} v = A D^2 A^T dy - p
+    assert np.linalg.norm(A @ (v / s) - g) <= 1e-12 * scale_g
+    # eq. iip_3
+    scale_1 = np.linalg.norm(abs(A) @ abs(dx)) + np.linalg.norm(rp) + scale_g
+    assert np.linalg.norm(A @ dx + rp) <= 1e-12 * scale_1
+    scale_2 = np.linalg.norm(rd) + np.linalg.norm(abs(A).T @ abs(dy))
+    assert np.linalg.norm(A.T @ dy + ds + rd) <= 1e-12 * scale_2
+    r3 = x * ds + s * dx + x * s - 0.5 * mu + v
+    scale_3 = (np.linalg.norm(x * ds) + np.linalg.norm(s * dx) + np.linalg.norm(x * s)
+               + np.linalg.norm(v))
+    assert np.linalg.norm(r3) <= 1e-12 * scale_3
+    # the direction against the oracle's Alg. 1 + eq. compv with the same W
+    W = sketch_matrix(17, 0, s_nnz, lp.n, lp.w)
+    ref = O.sketch_direction(A, b, c, x, y, s, 0.5, W, tol_cg=1e-5, max_cg=500)
+    assert info.cg_iters == ref.cg_iters
+    # Both are CG iterates stopped at tol_cg; they must agree far below their
+    # common distance to the exact Newton direction (the GPU inverts the Gram
+    # matrix, the oracle takes an SVD, so the rounding paths differ).
+    exact = O.exact_direction(A, b, c, x, y, s, 0.5)
+    trunc = np.linalg.norm(ref.dy - exact.dy)
+    assert np.linalg.norm(dy - ref.dy) <= 0.1 * trunc + 1e-12 * np.linalg.norm(exact.dy)
+    # Alg. 2 steps (e), (f) on the GPU's own direction (origin = this iterate)
+    st = O.step_length(x, s, dx, ds, 0.999, mu, 1.0, 1e-3)
+    assert info.alpha_max == pytest.approx(st.alpha_max, rel=1e-10)
+    assert info.alpha == pytest.approx(st.alpha, rel=1e-10)
+    # step (g)
+    assert np.allclose(xn, x + info.alpha * dx, rtol=1e-15, atol=1e-300)
+    assert np.allclose(yn, y + info.alpha * dy, rtol=1e-14, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# full solves
+# ---------------------------------------------------------------------------
+
+def check_solution(lp, res, gap):
+    assert res.status == 0, res
+    assert abs(res.obj_p - lp.opt) <= max(gap, 1e-12) * 2 * max(1.0, abs(lp.opt))
+    assert res.rel_gap <= gap
+    assert res.rp_norm <= 1e-8 * np.linalg.norm(lp.b)
+    assert res.rd_norm <= 1e-8 * np.linalg.norm(lp.c)
+
+
+def test_solve_config0_against_oracle(torch, sk):
+    lp = config_lp(0)
+    say("solve config 0 (50 x 1000, FP64, w=200, s=1, gap 1e-8)")
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
+        res = h.solve()
+    check_solution(lp, res, lp.eps_gap)
+    ref = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap))
+    assert abs(res.obj_p - ref.obj_p) <= 2e-8 * abs(ref.obj_p)
+
+
+@pytest.mark.parametrize("m,n", [(1, 10), (3, 50), (7, 300), (33, 700), (64, 1000),
+                                 (65, 1500), (130, 4000), (257, 3000)])
+def test_solve_ragged_shapes(torch, sk, m, n):
+    lp = dense_planted(m, n, rng=np.random.default_rng(m + n), eps_gap=1e-8)
+    say(f"solve ragged m={m} n={n}")
+    with sk.LP(lp.A, lp.b, lp.c, eps_gap=1e-8, seed=m, s=2) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-8)
+
+
+@pytest.mark.parametrize("s_nnz", [2, 4])
+def test_solve_config0_block_sketch(torch, sk, s_nnz):
+    lp = config_lp(0)
+    say(f"solve config 0 with s={s_nnz}")
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap, s=s_nnz) as h:
+        res = h.solve()
+    check_solution(lp, res, lp.eps_gap)
+
+
+def test_solve_f32_values(torch, sk):
+    lp = dense_planted(60, 3000, rng=np.random.default_rng(4), a_dtype="f32")
+    say("solve f32-valued 60 x 3000")
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", s=2) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-6)
+
+
+def test_solve_mixed_precision(torch, sk):
+    lp = dense_planted(80, 4000, rng=np.random.default_rng(6))
+    say("solve mixed precision 80 x 4000")
+    with sk.LP(lp.A, lp.b, lp.c, s=2, precision=sk.SKIPM_PREC_MIXED) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-6)
+
+
+def test_solve_is_deterministic_and_resettable(torch, sk):
+    lp = dense_planted(70, 2000, rng=np.random.default_rng(9))
+    say("determinism 70 x 2000")
+    with sk.LP(lp.A, lp.b, lp.c, s=2) as h:
+        r1 = h.solve()
+        h.reset()
+        r2 = h.solve()
+    assert r1.iters == r2.iters and r1.cg_total == r2.cg_total
+    assert r1.obj_p == r2.obj_p and r1.obj_d == r2.obj_d
+
+
+def test_solve_config1_full_size(torch, sk):
+    lp = config_lp(1)
+    say("solve config 1 (500 x 100000 FP64, w=2000, s=1)")
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
+        res = h.solve()
+    check_solution(lp, res, lp.eps_gap)
