@@ -38,7 +38,39 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=25.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
+    ap.add_argument("--probe", choices=["matvec", "copy"], default=None,
+                    help="profiling helpers: 'matvec' runs one IPM step then only the fused "
+                         "normal matvec; 'copy' runs a plain device copy of known size (the "
+                         "calibration for HBM byte counters)")
     return ap.parse_args()
+
+
+def run_probe(args):
+    import torch
+    if args.probe == "copy":
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.matvec_reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": args.matvec_reps}), flush=True)
+        return
+    import paper_2003_08072_amd as sk
+    from lpgen import config_lp
+    lp = config_lp(args.config)
+    prec = sk.SKIPM_PREC_MIXED if args.precision == "mixed" else sk.SKIPM_PREC_FP64
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=args.s,
+               eps_gap=lp.eps_gap, precision=prec) as h:
+        h.step()
+        u = torch.randn(lp.m, dtype=torch.float64, device="cuda")
+        h.normal_matvec(u, reps=args.matvec_reps)
+        torch.cuda.synchronize()
+    pa = 4 if (args.precision == "mixed" or lp.a_dtype == "f32") else 8
+    print(json.dumps({"probe": "matvec", "config": args.config, "precision": args.precision,
+                      "bytes_per_launch": lp.m * lp.n * pa + lp.n * pa,
+                      "launches": args.matvec_reps}), flush=True)
 
 
 def percentile(xs, q):
@@ -139,6 +171,9 @@ def main():
         print("bench.py measures one GPU only: the solver runs on a single MI355X and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.probe:
+        run_probe(args)
+        return
     import numpy as np  # noqa: F401
     import torch
 
