@@ -24,8 +24,9 @@
  *    stream before returning.
  *  - A handle is not thread-safe; distinct handles are independent.
  *  - All floating-point state of the IPM (x, y, s, residuals, p, v, the step)
- *    is FP64.  SKIPM_PREC_MIXED runs only the preconditioner build and the CG
- *    matrix-vector products in reduced precision (FP32 accumulate).
+ *    is FP64.  SKIPM_PREC_MIXED only lets the CG matrix-vector products read an
+ *    FP32 copy of A; the normal-equation residual that decides convergence is
+ *    recomputed from the FP64 A.
  */
 #ifndef SKIPM_H
 #define SKIPM_H
@@ -58,8 +59,9 @@ extern "C" {
 
 /* arithmetic of the CG solve */
 #define SKIPM_PREC_FP64  0   /* everything FP64 */
-#define SKIPM_PREC_MIXED 1   /* FP32 CG products on an FP32 copy of A, FP32 preconditioner;
-                                residuals, v, step length and the true-residual pass FP64 */
+#define SKIPM_PREC_MIXED 1   /* CG products read an FP32 copy of A (FP64 accumulation) inside
+                                an iterative refinement on FP64 residuals; residuals, v,
+                                step length and preconditioner FP64 */
 
 typedef struct skipm_lp_s* skipm_lp_t;
 
@@ -197,6 +199,12 @@ int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, doubl
  * u: m, out: m (device). */
 int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps,
                   hipStream_t stream);
+
+/* As normal_matvec, and *ms_per_pass (host) receives the mean duration of one
+ * fused pass, from HIP events recorded on `stream` immediately before the first
+ * and after the last of the `reps` back-to-back passes.  Synchronises `stream`. */
+int normal_matvec_timed(skipm_lp_t lp, const double* u, double* out, int32_t reps,
+                        float* ms_per_pass, hipStream_t stream);
 
 /* One iteration of Alg. 2 on the handle's iterate (steps a-g), or nothing if
  * the stopping test already holds (info->converged = 1).  info: host, may be NULL. */

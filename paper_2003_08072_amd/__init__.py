@@ -82,6 +82,7 @@ SIGNATURES = {
     "pcg_solve": (C.c_int, [_VP, _VP, _VP, C.c_int64, _VP, C.c_double, C.c_int32,
                             C.POINTER(PcgInfo), _VP]),
     "normal_matvec": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP]),
+    "normal_matvec_timed": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.POINTER(C.c_float), _VP]),
     "ipm_step": (C.c_int, [_VP, C.POINTER(StepInfo), _VP]),
     "lp_solve": (C.c_int, [_VP, C.POINTER(Result), _VP]),
     "skipm_last_error": (C.c_char_p, []),
@@ -284,6 +285,17 @@ class LP:
         _check(self._lib.normal_matvec(self.handle, _ptr(ut), _ptr(out), int(reps),
                                        _stream(self.stream)), "normal_matvec")
         return out
+
+    def normal_matvec_timed(self, u, reps=50):
+        """Mean duration (ms) of one fused pass, from HIP events around `reps` passes."""
+        import torch
+        ut = _as_device(u, torch.float64).contiguous()
+        out = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        ms = C.c_float()
+        _check(self._lib.normal_matvec_timed(self.handle, _ptr(ut), _ptr(out), int(reps),
+                                             C.byref(ms), _stream(self.stream)),
+               "normal_matvec_timed")
+        return float(ms.value)
 
     def step(self) -> StepInfo:
         info = StepInfo()

@@ -43,11 +43,9 @@ struct skipm_lp_s {
   float* A32 = nullptr;
   double *b = nullptr, *c = nullptr, *x = nullptr, *y = nullptr, *sv = nullptr;
   double *d2 = nullptr, *rd = nullptr, *dx = nullptr, *ds = nullptr, *v = nullptr;
-  float* d2f = nullptr;
   double *rp = nullptr, *p = nullptr, *dy = nullptr, *g = nullptr;
   double *cr = nullptr, *cz = nullptr, *cd = nullptr, *cq = nullptr, *cw = nullptr,
          *cx = nullptr;
-  float* cdf = nullptr;
   double *tw = nullptr, *tq = nullptr;
   double* B = nullptr;
   double* Gpart = nullptr;
@@ -58,6 +56,9 @@ struct skipm_lp_s {
   // Gram inverses, and the accumulated inverse factors M1 = X0, M2 = X1 X0
   double *B1 = nullptr, *B2 = nullptr, *Gv = nullptr, *Xv = nullptr, *M1 = nullptr,
          *M2 = nullptr, *rv = nullptr, *uv1 = nullptr, *uv2 = nullptr;
+  double *rt = nullptr, *dyc = nullptr;  // mixed precision: FP64 residual and correction
+  int last_outer = 0;
+  int demoted = 0;  // mixed precision switched to FP64 CG for the rest of this run
   int vrounds_built = 0;
   int32_t *bucket = nullptr, *perm = nullptr, *perm_raw = nullptr, *bptr = nullptr,
           *bcnt = nullptr, *bcur = nullptr;
@@ -67,7 +68,7 @@ struct skipm_lp_s {
   double* sc = nullptr;
   int32_t* is = nullptr;
   double* hsc = nullptr;  // pinned: S_NSLOTS doubles then I_NINTS ints
-  int nblk_A = 1, nblk_A32 = 1, nblk_B = 1, nblk_vec = 1;
+  int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_B = 1, nblk_vec = 1;
   int64_t k = 0;
   int64_t hashed_k = -1;
   int prev_cg = 8;
@@ -156,7 +157,7 @@ ColPass colpass_A(skipm_lp_s* lp, int mode) {
   cp.ldp = lp->mp;
   cp.red = lp->red;
   cp.sc = lp->sc;
-  cp.nblk = lp->nblk_A;
+  cp.nblk = mode == COL_PROLOGUE ? lp->nblk_Ap : lp->nblk_A;
   return cp;
 }
 
@@ -168,7 +169,6 @@ int prologue(skipm_lp_s* lp, hipStream_t st) {
   cp.c = lp->c;
   cp.rd_out = lp->rd;
   cp.d2_out = lp->d2;
-  cp.d2f_out = lp->mixed ? lp->d2f : nullptr;
   SK_TRY(run_colpass(cp, st));
   // r_p = A x - b ; p = b - A (sigma mu / s + d2 r_d)
   launch_finish(lp->part, SKIPM_F64, 2 * lp->mp, 0, cp.nblk, lp->m, 1.0, lp->b, -1.0, lp->rp,
@@ -227,23 +227,19 @@ int qinv_apply(skipm_lp_s* lp, const double* u, double* out, const int32_t* done
 int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
   const int32_t* done = lp->is + I_CG_DONE;
   ColPass cp = colpass_A(lp, COL_NORMAL);
-  if (lp->mixed) {
+  cp.u = lp->cd;
+  cp.d2 = lp->d2;
+  if (lp->mixed) {  // FP32 copy of A, FP64 accumulation
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
-    cp.tc = SKIPM_F32;
-    cp.u = lp->cdf;
-    cp.d2 = lp->d2f;
     cp.nblk = lp->nblk_A32;
-  } else {
-    cp.u = lp->cd;
-    cp.d2 = lp->d2;
   }
   cp.done = done;
   SK_TRY(run_colpass(cp, st));
   launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, lp->cq, done, st);
   SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
-  launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, lp->mixed ? lp->cdf : nullptr,
-                   xsol, nullptr, nullptr, 0, lp->sc, lp->is, st);
+  launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
+                   nullptr, 0, lp->sc, lp->is, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -252,8 +248,8 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
 int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
             int first_chunk, int* its, int* fact_fail, hipStream_t st) {
   SK_TRY(qinv_apply(lp, rhs, lp->cw, nullptr, st));
-  launch_cg_init(lp->m, rhs, lp->cw, lp->cr, lp->cz, lp->cd, lp->mixed ? lp->cdf : nullptr, xsol,
-                 nullptr, 0, lp->sc, lp->is, tol, max_it, 0, st);
+  launch_cg_init(lp->m, rhs, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr, 0, lp->sc,
+                 lp->is, tol, max_it, 0, st);
   int enq = 0;
   int chunk = std::max(1, std::min(first_chunk, max_it));
   *fact_fail = 0;
@@ -274,6 +270,68 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   }
 }
 
+// FP64 residual of the normal equations, rt = rhs - A D^2 A^T x (one FP64 pass
+// over A), and S_RHO2 = rt^T Q^{-1} rt.
+int normal_residual_fp64(skipm_lp_s* lp, const double* rhs, const double* x, hipStream_t st) {
+  ColPass cp = colpass_A(lp, COL_NORMAL);
+  cp.u = x;
+  cp.d2 = lp->d2;
+  SK_TRY(run_colpass(cp, st));
+  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, rhs, 1.0, lp->rt, nullptr,
+                st);
+  SK_TRY(qinv_apply(lp, lp->rt, lp->uv1, nullptr, st));
+  launch_dot(lp->rt, lp->uv1, lp->m, lp->sc, S_RHO2, st);
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+constexpr int kMixedMaxOuter = 4;
+
+// Mixed precision: iterative refinement with FP64 residuals around a CG whose
+// products use the FP32 copy of A.  Stops on the same test as the FP64 CG,
+// sqrt(r^T Q^{-1} r) <= tol sqrt(p^T Q^{-1} p), with r the FP64 residual.
+int pcg_mixed(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it, int* its,
+              int* fact_fail, hipStream_t st) {
+  launch_fill_f64(xsol, 0.0, lp->m, st);
+  launch_copy_f64(lp->rt, rhs, lp->m, st);
+  double rho0 = -1, rho = 0;
+  int total = 0;
+  *fact_fail = 0;
+  const int max_outer = 6;
+  int outer = 0;
+  for (; outer < max_outer; ++outer) {
+    // The inner CG is consistent (FP64 accumulation), so it can go straight to
+    // the target; further outer steps only correct the FP32 rounding of A.
+    const double rel_target = rho0 > 0 && rho > 0 ? tol * rho0 / rho : tol;
+    const double inner_tol = std::min(0.5, rel_target);
+    int inner = 0;
+    const int first = std::max(2, outer == 0 ? lp->prev_cg - 1 : lp->prev_cg / 3);
+    SK_TRY(pcg_run(lp, lp->rt, lp->dyc, tol > 0 ? inner_tol : 0.0, max_it, first, &inner,
+                   fact_fail, st));
+    if (*fact_fail) return SKIPM_OK;
+    // If refinement needs many outer steps, the FP32 copy of A is too coarse
+    // for this iterate (kappa(A D) too large): finish this solve, and the rest
+    // of the run, with FP64 products.
+    if (outer + 1 >= kMixedMaxOuter) {
+      lp->demoted = 1;
+      lp->mixed = false;
+    }
+    if (rho0 < 0) rho0 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
+    total += inner;
+    launch_axpy(xsol, lp->dyc, 1.0, lp->m, st);
+    SK_TRY(normal_residual_fp64(lp, rhs, xsol, st));
+    SK_TRY(sync_read(lp, st));
+    rho = sqrt(std::max(0.0, lp->hsc[S_RHO2]));
+    if (!(rho0 > 0) || rho <= tol * rho0 || tol <= 0) break;
+  }
+  lp->last_outer = outer + 1;
+  // report the FP64 residual in the CG slots
+  lp->hsc[S_CG_RZ0] = rho0 * rho0;
+  lp->hsc[S_CG_RZ] = rho * rho;
+  *its = total;
+  return SKIPM_OK;
+}
+
 // sketch + factor + CG with rank-failure retries (shifted Gram).
 int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
                  int* its, hipStream_t st) {
@@ -281,8 +339,12 @@ int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, in
   for (int attempt = 0; attempt < 4; ++attempt) {
     SK_TRY(factor(lp, shift, st));
     int fail = 0;
-    const int first = std::max(2, lp->prev_cg - 1);
-    SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first, its, &fail, st));
+    if (lp->mixed) {
+      SK_TRY(pcg_mixed(lp, rhs, xsol, tol, max_it, its, &fail, st));
+    } else {
+      const int first = std::max(2, lp->prev_cg - 1);
+      SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first, its, &fail, st));
+    }
     if (!fail) return SKIPM_OK;
     shift = shift == 0.0 ? 1e-12 : shift * 1e3;
   }
@@ -386,7 +448,7 @@ int sketch_t_apply(skipm_lp_s* lp, const double* Bk, const double* u, double* ou
   cp.n = lp->w;
   cp.u = u;
   cp.t_out = out;
-  cp.nblk = lp->nblk_B;
+  cp.nblk = 0;
   return run_colpass(cp, st);
 }
 
@@ -638,6 +700,10 @@ int lp_reset(skipm_lp_t lp, hipStream_t st) {
   lp->prev_cg = 8;
   lp->origin_pending = 1;
   lp->small_steps = 0;
+  if (lp->demoted) {
+    lp->demoted = 0;
+    lp->mixed = true;
+  }
   SK_TRY(mu_from_iterate(lp, st));
   SK_CHECK_HIP(hipStreamSynchronize(st));
   return SKIPM_OK;
@@ -701,7 +767,6 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->dx, n);
   ALLOC(lp->ds, n);
   ALLOC(lp->v, n);
-  if (lp->mixed) ALLOC(lp->d2f, n);
   ALLOC(lp->rp, mp);
   ALLOC(lp->p, mp);
   ALLOC(lp->dy, mp);
@@ -713,9 +778,10 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cw, mp);
   ALLOC(lp->cx, mp);
   ALLOC(lp->rv, mp);
+  ALLOC(lp->rt, mp);
+  ALLOC(lp->dyc, mp);
   ALLOC(lp->uv1, mp);
   ALLOC(lp->uv2, mp);
-  if (lp->mixed) ALLOC(lp->cdf, mp);
   ALLOC(lp->tw, w);
   ALLOC(lp->tq, w);
   ALLOC(lp->B, lda * w);
@@ -737,19 +803,21 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->bptr, w + 1);
   ALLOC(lp->bcnt, w);
   ALLOC(lp->bcur, w);
-  lp->nblk_A = colpass_nblk(lda, n, lp->a_dtype);
-  lp->nblk_A32 = colpass_nblk(lda, n, SKIPM_F32);
-  lp->nblk_B = colpass_nblk(lda, w, SKIPM_F64);
+  lp->nblk_A = colpass_nblk(lda, n, lp->a_dtype, SKIPM_F64, COL_NORMAL);
+  lp->nblk_Ap = colpass_nblk(lda, n, lp->a_dtype, SKIPM_F64, COL_PROLOGUE);
+  lp->nblk_A32 = colpass_nblk(lda, n, SKIPM_F32, SKIPM_F64, COL_NORMAL);
+  lp->nblk_B = colpass_nblk(lda, w, SKIPM_F64, SKIPM_F64, COL_NORMAL);
   lp->nblk_vec = vec_nblk(n);
   {
-    int64_t pe = std::max<int64_t>(2 * (int64_t)lp->nblk_A * mp, (int64_t)lp->nblk_B * mp);
+    int64_t pe = std::max<int64_t>(2 * (int64_t)lp->nblk_Ap * mp, (int64_t)lp->nblk_A * mp);
+    pe = std::max<int64_t>(pe, (int64_t)lp->nblk_B * mp);
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A32 * mp);
-    pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64) * mp);
+    pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
     double* pp = nullptr;
     ALLOC(pp, pe);
     lp->part = pp;
   }
-  ALLOC(lp->red, (int64_t)std::max(std::max(lp->nblk_A, lp->nblk_vec), 64) * 8);
+  ALLOC(lp->red, (int64_t)std::max(std::max(lp->nblk_Ap, lp->nblk_vec), 64) * 8);
   ALLOC(lp->sc, S_NSLOTS);
   ALLOC(lp->is, I_NINTS);
 #undef ALLOC
@@ -762,9 +830,9 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   launch_fill_f64(lp->sc, 0.0, S_NSLOTS, st);
   launch_fill_i32(lp->is, 0, I_NINTS, st);
   double* zero_vecs[] = {lp->b,  lp->y,  lp->rp, lp->p,  lp->dy, lp->g,  lp->cr,  lp->cz,
-                         lp->cd, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2};
+                         lp->cd, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2,
+                         lp->rt, lp->dyc};
   for (double* z : zero_vecs) launch_fill_f64(z, 0.0, mp, st);
-  if (lp->cdf) launch_convert_f64_f32(lp->cdf, lp->cd, mp, st);
   launch_fill_f64(lp->B, 0.0, lda * w, st);
   launch_copy_f64(lp->b, prob->b, m, st);
   launch_copy_f64(lp->c, prob->c, n, st);
@@ -859,7 +927,6 @@ int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, doubl
   if (max_it < 1) return set_error("max_it must be >= 1"), SKIPM_EINVAL;
   SK_CHECK_HIP(hipSetDevice(lp->device));
   launch_copy_f64(lp->d2, d2, lp->n, st);
-  if (lp->mixed) launch_convert_f64_f32(lp->d2f, lp->d2, lp->n, st);
   launch_copy_f64(lp->g, p, lp->m, st);  // g doubles as the right-hand side buffer here
   SK_TRY(sketch_into(lp, lp->d2, 1, k, lp->B, st));
   int its = 0;
@@ -875,27 +942,51 @@ int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, doubl
   return SKIPM_OK;
 }
 
+static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32_t reps,
+                              float* ms, hipStream_t st);
+
 int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps, hipStream_t st) {
+  return normal_matvec_impl(lp, u, out, reps, nullptr, st);
+}
+
+int normal_matvec_timed(skipm_lp_t lp, const double* u, double* out, int32_t reps,
+                        float* ms_per_pass, hipStream_t st) {
+  if (!ms_per_pass) return set_error("null ms_per_pass"), SKIPM_EINVAL;
+  return normal_matvec_impl(lp, u, out, reps, ms_per_pass, st);
+}
+
+static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32_t reps,
+                              float* ms, hipStream_t st) {
   if (!lp || !u || !out) return set_error("null argument"), SKIPM_EINVAL;
   if (reps < 1) return set_error("reps must be >= 1"), SKIPM_EINVAL;
   SK_CHECK_HIP(hipSetDevice(lp->device));
   launch_copy_f64(lp->cd, u, lp->m, st);
-  if (lp->mixed) launch_convert_f64_f32(lp->cdf, lp->cd, lp->m, st);
   ColPass cp = colpass_A(lp, COL_NORMAL);
+  cp.u = lp->cd;
+  cp.d2 = lp->d2;
   if (lp->mixed) {
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
-    cp.tc = SKIPM_F32;
-    cp.u = lp->cdf;
-    cp.d2 = lp->d2f;
     cp.nblk = lp->nblk_A32;
-  } else {
-    cp.u = lp->cd;
-    cp.d2 = lp->d2;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    SK_CHECK_HIP(hipEventCreate(&e0));
+    SK_CHECK_HIP(hipEventCreate(&e1));
+    SK_CHECK_HIP(hipEventRecord(e0, st));
   }
   for (int r = 0; r < reps; ++r) SK_TRY(run_colpass(cp, st));
+  if (ms) SK_CHECK_HIP(hipEventRecord(e1, st));
   launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr, st);
   SK_CHECK_HIP(hipGetLastError());
+  if (ms) {
+    float tot = 0;
+    SK_CHECK_HIP(hipEventSynchronize(e1));
+    SK_CHECK_HIP(hipEventElapsedTime(&tot, e0, e1));
+    *ms = tot / (float)reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
   return SKIPM_OK;
 }
 

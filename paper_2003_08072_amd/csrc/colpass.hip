@@ -116,86 +116,95 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   }
   double sr0 = 0, sr1 = 0, sr2 = 0;
 
-  VT cur[R], nxt[R];
+  // Per-column work on the R vectors of column `col` held by this lane.
+  auto process = [&](const VT* cur, const int64_t col) {
+      TC dot = 0;
+      if (MODE != COL_AXPY) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    cur[r] = (VT)0;
-    nxt[r] = (VT)0;
-  }
-  int64_t col = c0 + slot;
-  if (col < c1) {
+        for (int r = 0; r < R; ++r) {
+          if (!valid[r]) continue;
+#pragma unroll
+          for (int e = 0; e < V; ++e) dot += (TC)cur[r][e] * uu[r][e];
+        }
+        dot = group_sum<G>(dot);
+      }
+      if (MODE == COL_AXPY) {
+        const TC coef = d2[col];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+      } else if (MODE == COL_DOT) {
+        if (lg == 0) ((TC*)a.t_out)[col] = dot;
+      } else if (MODE == COL_NORMAL) {
+        const TC coef = d2 ? d2[col] * dot : dot;
+        if (a.t_out && lg == 0) ((TC*)a.t_out)[col] = dot;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+      } else if (MODE == COL_EPILOGUE) {
+        const double t = (double)dot;
+        const double dsj = -a.rd[col] - t;
+        const double coef = ((const double*)a.d2)[col] * t;
+        if (lg == 0) a.ds_out[col] = dsj;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc1[r][e] += (TC)(coef * (double)cur[r][e]);
+      } else {  // COL_PROLOGUE
+        const double t = (double)dot;
+        const double xj = a.x[col], sj = a.s[col], cj = a.c[col];
+        const double rdj = t + sj - cj;
+        const double d2j = xj / sj;
+        const double ej = sigma * mu / sj + d2j * rdj;
+        if (lg == 0) {
+          a.rd_out[col] = rdj;
+          a.d2_out[col] = d2j;
+          if (a.d2f_out) a.d2f_out[col] = (float)d2j;
+          sr0 += rdj * rdj;
+          sr1 += cj * xj;
+          sr2 += xj * sj;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            acc1[r][e] += (TC)(xj * (double)cur[r][e]);
+            acc2[r][e] += (TC)(ej * (double)cur[r][e]);
+          }
+      }
+  };
+  auto load_col = [&](VT* dst, const int64_t col) {
     const VT* p = (const VT*)(A + col * a.lda);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (valid[r]) cur[r] = p[r * G + lg];
+      if (valid[r]) dst[r] = p[r * G + lg];
+  };
+  // Two columns per trip, the next two prefetched while these are used, so up
+  // to four columns per lane group are in flight.
+  VT c0v[R], c1v[R], n0v[R], n1v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    c0v[r] = (VT)0;
+    c1v[r] = (VT)0;
+    n0v[r] = (VT)0;
+    n1v[r] = (VT)0;
   }
+  int64_t col = c0 + slot;
+  if (col < c1) load_col(c0v, col);
+  if (col + NSLOT < c1) load_col(c1v, col + NSLOT);
   while (col < c1) {
-    const int64_t ncol = col + NSLOT;
-    if (ncol < c1) {
-      const VT* p = (const VT*)(A + ncol * a.lda);
+    if (col + 2 * NSLOT < c1) load_col(n0v, col + 2 * NSLOT);
+    if (col + 3 * NSLOT < c1) load_col(n1v, col + 3 * NSLOT);
+    process(c0v, col);
+    if (col + NSLOT < c1) process(c1v, col + NSLOT);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (valid[r]) nxt[r] = p[r * G + lg];
+    for (int r = 0; r < R; ++r) {
+      c0v[r] = n0v[r];
+      c1v[r] = n1v[r];
     }
-    TC dot = 0;
-    if (MODE != COL_AXPY) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!valid[r]) continue;
-#pragma unroll
-        for (int e = 0; e < V; ++e) dot += (TC)cur[r][e] * uu[r][e];
-      }
-      dot = group_sum<G>(dot);
-    }
-    if (MODE == COL_AXPY) {
-      const TC coef = d2[col];
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
-    } else if (MODE == COL_DOT) {
-      if (lg == 0) ((TC*)a.t_out)[col] = dot;
-    } else if (MODE == COL_NORMAL) {
-      const TC coef = d2 ? d2[col] * dot : dot;
-      if (a.t_out && lg == 0) ((TC*)a.t_out)[col] = dot;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
-    } else if (MODE == COL_EPILOGUE) {
-      const double t = (double)dot;
-      const double dsj = -a.rd[col] - t;
-      const double coef = ((const double*)a.d2)[col] * t;
-      if (lg == 0) a.ds_out[col] = dsj;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc1[r][e] += (TC)(coef * (double)cur[r][e]);
-    } else {  // COL_PROLOGUE
-      const double t = (double)dot;
-      const double xj = a.x[col], sj = a.s[col], cj = a.c[col];
-      const double rdj = t + sj - cj;
-      const double d2j = xj / sj;
-      const double ej = sigma * mu / sj + d2j * rdj;
-      if (lg == 0) {
-        a.rd_out[col] = rdj;
-        a.d2_out[col] = d2j;
-        if (a.d2f_out) a.d2f_out[col] = (float)d2j;
-        sr0 += rdj * rdj;
-        sr1 += cj * xj;
-        sr2 += xj * sj;
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          acc1[r][e] += (TC)(xj * (double)cur[r][e]);
-          acc2[r][e] += (TC)(ej * (double)cur[r][e]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) cur[r] = nxt[r];
-    col = ncol;
+    col += 2 * NSLOT;
   }
 
   if (MODE == COL_PROLOGUE) {
@@ -340,8 +349,18 @@ __global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + tx;
   double acc = 0;
-  if (i < m)
-    for (int b = ty; b < nblk; b += 16) acc += (double)part[(int64_t)b * ldp + off + i];
+  if (i < m) {
+    // eight loads in flight per thread, added in block order
+    int b = ty;
+    for (; b + 7 * 16 < nblk; b += 8 * 16) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (double)part[(int64_t)(b + 16 * q) * ldp + off + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    for (; b < nblk; b += 16) acc += (double)part[(int64_t)b * ldp + off + i];
+  }
   tile[ty][tx] = acc;
   __syncthreads();
   for (int h = 8; h > 0; h >>= 1) {
@@ -373,14 +392,20 @@ Shape pick_shape(int64_t lda, int V) {
   return {0, 0};
 }
 
-template <int R>
-constexpr int threads_for() {
-  return R <= 4 ? 1024 : (R <= 8 ? 512 : 256);
+// Block size from an estimate of the VGPRs a lane needs (u and accumulators in
+// the compute type, four 16-byte column buffers, ~32 for addressing): 1024
+// threads need <= 128 VGPRs, 512 threads <= 256.  DOT passes write no partial
+// sums, so they use small blocks and many of them.
+constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
+  const int nacc = mode == COL_PROLOGUE ? 2 : (mode == COL_DOT ? 0 : 1);
+  const int est = (1 + nacc) * R * V * tc_bytes / 4 + 16 * R + 32;
+  if (mode == COL_DOT) return 256;
+  return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
 
 template <typename TA, typename TC, int MODE, int G, int R>
 void launch_one(const Args& a, int nblk, hipStream_t st) {
-  constexpr int NT = threads_for<R>();
+  constexpr int NT = threads_for(MODE, R, Vec<TA>::V, (int)sizeof(TC));
   hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, a);
 }
 
@@ -400,7 +425,7 @@ template <typename TA, int G, int R>
 void launch_sketch_one(const TA* A, int64_t lda, int s, const double* d2, int is_d2,
                        const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
                        double* B, int64_t ldb, hipStream_t st) {
-  constexpr int NT = threads_for<R>() < 512 ? threads_for<R>() : 256;
+  constexpr int NT = 256;
   const int per_block = (NT / 64) * (64 / G);
   int blocks = (w + per_block - 1) / per_block;
   if (blocks < 1) blocks = 1;
@@ -426,11 +451,22 @@ void sketch_dispatch(const TA* A, int64_t lda, int s, const double* d2, int is_d
 
 }  // namespace
 
-int colpass_nblk(int64_t lda, int64_t n, int ta) {
+int colpass_nblk_dot(int64_t lda, int64_t n, int ta) {
   const int V = ta == SKIPM_F64 ? 2 : 4;
   const Shape sh = pick_shape(lda, V);
   if (sh.G == 0) return 1;
-  const int nt = sh.R <= 4 ? 1024 : (sh.R <= 8 ? 512 : 256);
+  const int64_t slots = (256 / 64) * (64 / sh.G);
+  int64_t nb = (n + slots - 1) / slots;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode) {
+  const int V = ta == SKIPM_F64 ? 2 : 4;
+  const Shape sh = pick_shape(lda, V);
+  if (sh.G == 0) return 1;
+  const int nt = threads_for(mode, sh.R, V, tc == SKIPM_F64 ? 8 : 4);
   const int64_t slots = (int64_t)(nt / 64) * (64 / sh.G);
   const int target = nt == 256 ? 512 : 256;
   int64_t nb = (n + slots * 4 - 1) / (slots * 4);  // at least ~4 columns per slot
@@ -461,7 +497,9 @@ int launch_colpass(ColPass& c, hipStream_t st) {
   a.red = c.red;
   a.sc = c.sc;
   a.done = c.done;
-  if (c.nblk <= 0) c.nblk = colpass_nblk(c.lda, c.n, c.ta);
+  if (c.nblk <= 0)
+    c.nblk = c.mode == COL_DOT ? colpass_nblk_dot(c.lda, c.n, c.ta)
+                               : colpass_nblk(c.lda, c.n, c.ta, c.tc, c.mode);
   a.cpb = (c.n + c.nblk - 1) / c.nblk;
   const int nblk = c.nblk;
   int rc = -1;

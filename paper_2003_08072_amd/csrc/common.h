@@ -54,6 +54,7 @@ enum Slot : int {
   // CG state
   S_CG_RZ, S_CG_RZ0, S_CG_TOL2, S_CG_PQ,
   S_V_RR, S_V_GG, // v-solve: ||r||^2, ||g||^2
+  S_RHO2,         // mixed precision: r^T Q^{-1} r of the FP64 normal-equation residual
   S_NSLOTS = 40
 };
 
@@ -119,7 +120,8 @@ struct ColPass {
 };
 enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
 int launch_colpass(ColPass& a, hipStream_t st);
-int colpass_nblk(int64_t lda, int64_t n, int ta);
+// workgroups of a pass (each writes one partial of nacc * m entries)
+int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode);
 
 // bucket-ordered sketch B[:, b] = sum over items in bucket b of sign * d_j * A[:, j]
 // (dscale holds d, or d^2 when is_d2 != 0)
@@ -151,6 +153,9 @@ void launch_shift_trace(double* G, int64_t mp, int64_t m, double c, hipStream_t 
 // sc[slot] = ||u||^2 over m entries (single workgroup)
 void launch_norm2(const double* u, int64_t m, double* sc, int slot, hipStream_t st);
 void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+// sc[slot] = a^T b over m entries (single workgroup)
+void launch_dot(const double* a, const double* b, int64_t m, double* sc, int slot,
+                hipStream_t st);
 
 // single-workgroup CG kernels
 void launch_cg_init(int64_t m, const double* p, const double* z, double* r, double* zz,

@@ -109,87 +109,82 @@ __global__ __launch_bounds__(256) void k_shift_diag(double* __restrict__ G, int6
 // of one, unlike a Gauss-Jordan inverse of G.
 // ---------------------------------------------------------------------------
 
-// Unblocked Cholesky of the NB x NB tile T (LDS, lower part), then the inverse
-// of the factor into Xt (lower, zero above the diagonal).
-template <int NB>
-__device__ void lds_potrf_trinv(double (*T)[NB + 1], double (*Xt)[NB + 1], int32_t* fail) {
-  for (int p = 0; p < NB; ++p) {
-    if (threadIdx.x == 0) {
-      double d = T[p][p];
-      if (!(d > 0.0)) {
-        atomicOr(fail, 1);
-        d = 1e-300;
-      }
-      T[p][p] = sqrt(d);
-    }
-    __syncthreads();
-    const double piv = T[p][p];
-    for (int i = p + 1 + threadIdx.x; i < NB; i += blockDim.x) T[i][p] /= piv;
-    __syncthreads();
-    const int rem = NB - p - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-      const int i = p + 1 + e / rem, j = p + 1 + e % rem;
-      if (j <= i) T[i][j] -= T[i][p] * T[j][p];
-    }
-    __syncthreads();
-  }
-  // zero the strict upper part of the factor
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    if (j > i) T[i][j] = 0.0;
-  }
-  __syncthreads();
-  // column c of L^{-1} by forward substitution (one thread per column)
-  for (int c = threadIdx.x; c < NB; c += blockDim.x) {
-    for (int i = 0; i < c; ++i) Xt[i][c] = 0.0;
-    Xt[c][c] = 1.0 / T[c][c];
-    for (int i = c + 1; i < NB; ++i) {
-      double acc = 0.0;
-      for (int j = c; j < i; ++j) acc += T[i][j] * Xt[j][c];
-      Xt[i][c] = -acc / T[i][i];
-    }
-  }
-  __syncthreads();
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// Panel step k.  Every block factors G_kk in LDS; block 0 stores X_kk = L_kk^{-1}
-// in Xb, block b > 0 overwrites row block i = k + b with L_ik = G_ik X_kk^T.
+// Panel step k, one wave of NB lanes per block.  Every block factors G_kk with
+// lane i holding row i in registers (left-looking: column p needs row p's
+// finished entries, taken from lane p by readlane), then keeps L_kk in LDS.
+// Block 0 forms X_kk = L_kk^{-1} (lane c solves column c by forward
+// substitution, reading L_kk by LDS broadcast) and stores it in Xb; block
+// b > 0 solves L_kk y = G_ik[r, :]^T for its rows r (lane r), i.e.
+// L_ik = G_ik L_kk^{-T}, in place.
 template <int NB>
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ G, double* __restrict__ Xb,
-                                                    int64_t mp, int k,
-                                                    int32_t* __restrict__ fail) {
-  __shared__ double T[NB][NB + 1];
-  __shared__ double Xt[NB][NB + 1];
+__global__ __launch_bounds__(NB) void k_chol_panel(double* __restrict__ G, double* __restrict__ Xb,
+                                                   int64_t mp, int k,
+                                                   int32_t* __restrict__ fail) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double rdiag[NB];
+  const int lane = threadIdx.x;
   const int64_t K0 = (int64_t)k * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int r = e % NB, c = e / NB;
-    T[r][c] = G[(K0 + r) + (K0 + c) * mp];
-  }
-  __syncthreads();
-  lds_potrf_trinv<NB>(T, Xt, fail);
-  if (blockIdx.x == 0) {
-    // L_kk itself is not needed later (only X_kk and the off-diagonal L_ik are),
-    // and G_kk must stay intact while the other blocks of this launch read it.
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-      const int r = e % NB, c = e / NB;
-      Xb[(K0 + r) + (K0 + c) * mp] = Xt[r][c];
+  double a[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) a[j] = G[(K0 + lane) + (K0 + j) * mp];
+  bool bad = false;
+#pragma unroll
+  for (int p = 0; p < NB; ++p) {
+    double s = a[p];
+#pragma unroll
+    for (int q = 0; q < p; ++q) s -= a[q] * readlane_d(a[q], p);
+    double d = readlane_d(s, p);
+    if (!(d > 0.0)) {
+      bad = true;
+      d = 1e-300;
     }
+    const double lpp = sqrt(d);
+    a[p] = lane > p ? s / lpp : (lane == p ? lpp : 0.0);
+  }
+  if (bad && lane == 0) atomicOr(fail, 1);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) Ls[lane][j] = a[j];
+  __syncthreads();
+  rdiag[lane] = 1.0 / Ls[lane][lane];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    // column `lane` of L_kk^{-1}
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < i; ++q) s -= Ls[i][q] * x[q];
+      x[i] = s * rdiag[i];
+    }
+    __syncthreads();
+    // stage through LDS (transpose) for coalesced stores of the column-major tile
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Ls[i][lane] = x[i];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Xb[(K0 + lane) + (K0 + c) * mp] = Ls[lane][c];
     return;
   }
-  // reuse T for the row block G_ik
-  __syncthreads();
   const int64_t I0 = K0 + (int64_t)blockIdx.x * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int r = e % NB, c = e / NB;
-    T[r][c] = G[(I0 + r) + (K0 + c) * mp];
+  double y[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) y[c] = G[(I0 + lane) + (K0 + c) * mp];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    double s = y[c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) s -= Ls[c][q] * y[q];
+    y[c] = s * rdiag[c];
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int r = e % NB, c = e / NB;
-    double acc = 0.0;
-    for (int q = 0; q <= c; ++q) acc += T[r][q] * Xt[c][q];  // (G_ik X_kk^T)_rc
-    G[(I0 + r) + (K0 + c) * mp] = acc;
-  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) G[(I0 + lane) + (K0 + c) * mp] = y[c];
 }
 
 // C[I, J] (+)= sign * sum_q A[I, q-block] B[J, q-block]^T over a range of q
@@ -441,7 +436,7 @@ void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, 
                      mp, G);
 }
 
-int chol_block(int64_t mp) { return mp <= 256 ? 32 : 64; }  // mp is a multiple of 64
+int chol_block(int64_t mp) { return mp > 0 ? 32 : 32; }  // mp is a multiple of 64
 
 void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail,
                         hipStream_t st) {
@@ -449,12 +444,12 @@ void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail
   for (int k = 0; k < T; ++k) {
     const int rest = T - k - 1;
     if (nb == 32) {
-      hipLaunchKernelGGL(k_chol_panel<32>, dim3(rest + 1), dim3(256), 0, st, G, Xb, mp, k, fail);
+      hipLaunchKernelGGL(k_chol_panel<32>, dim3(rest + 1), dim3(32), 0, st, G, Xb, mp, k, fail);
       if (rest > 0)
         hipLaunchKernelGGL(k_chol_update<32>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
                            mp, k);
     } else {
-      hipLaunchKernelGGL(k_chol_panel<64>, dim3(rest + 1), dim3(256), 0, st, G, Xb, mp, k, fail);
+      hipLaunchKernelGGL(k_chol_panel<64>, dim3(rest + 1), dim3(64), 0, st, G, Xb, mp, k, fail);
       if (rest > 0)
         hipLaunchKernelGGL(k_chol_update<64>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
                            mp, k);

@@ -442,6 +442,16 @@ __global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ u, in
   if (threadIdx.x == 0) sc[slot] = v;
 }
 
+__global__ __launch_bounds__(1024) void k_dot(const double* __restrict__ a,
+                                              const double* __restrict__ b, int64_t m,
+                                              double* __restrict__ sc, int slot) {
+  __shared__ double buf[16];
+  double v = 0;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) v += a[i] * b[i];
+  v = block_sum<1024>(v, buf);
+  if (threadIdx.x == 0) sc[slot] = v;
+}
+
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -452,6 +462,11 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
 
 void launch_norm2(const double* u, int64_t m, double* sc, int slot, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, u, m, sc, slot);
+}
+
+void launch_dot(const double* a, const double* b, int64_t m, double* sc, int slot,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(1024), 0, st, a, b, m, sc, slot);
 }
 
 void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st) {
