@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--s", type=int, default=1,
                     help="non-zeros per row of the sketch for the headline (1: CountSketch)")
@@ -70,10 +70,24 @@ def run_probe(args):
         u = torch.randn(lp.m, dtype=torch.float64, device="cuda")
         h.normal_matvec(u, reps=args.matvec_reps)
         torch.cuda.synchronize()
-    pa = 4 if (args.precision == "mixed" or lp.a_dtype == "f32") else 8
     print(json.dumps({"probe": "matvec", "config": args.config, "precision": args.precision,
-                      "bytes_per_launch": lp.m * lp.n * pa + lp.n * pa,
+                      "bytes_per_launch": matvec_bytes(lp, args.precision),
                       "launches": args.matvec_reps}), flush=True)
+
+
+def matvec_bytes(lp, precision):
+    """Algorithmic HBM bytes of one normal product A D^2 A^T u.
+
+    Dense: A once (m n values) and D^2 once (n values, stored in A's precision
+    inside the pass).  CSR: the column pass reads the CSC copy (row indices,
+    values, column pointers) and D^2 and writes one coefficient per column; the
+    row pass reads the CSR copy (column indices, values, row pointers) and the
+    coefficients once."""
+    pa = 4 if (precision == "mixed" or lp.a_dtype == "f32") else 8
+    if lp.fmt == "dense":
+        return lp.m * lp.n * pa + lp.n * pa
+    nnz = int(lp.A.nnz)
+    return 2 * nnz * (4 + pa) + (lp.n + 1) * 4 + (lp.m + 1) * 4 + 3 * lp.n * 8
 
 
 def percentile(xs, q):
@@ -123,8 +137,7 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
     u = torch.randn(lp.m, dtype=torch.float64, device="cuda")
     h.normal_matvec(u, reps=3)
     mv_ms = h.normal_matvec_timed(u, reps=args.matvec_reps)
-    pa = 4 if (precision == "mixed" or lp.a_dtype == "f32") else 8
-    mv_bytes = lp.m * lp.n * pa + lp.n * pa
+    mv_bytes = matvec_bytes(lp, precision)
     h.close()
     return dict(
         precision=precision, s=s_nnz, ok=bool(ok), status=int(res.status), solves_per_s=args.steps / wall,
@@ -182,6 +195,8 @@ def main():
     sk.load()
     lp = config_lp(args.config)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    if lp.fmt != "dense":
+        precs = ["fp64"]  # the sparse path keeps its values in their own precision
     s_list = [args.s] + [int(v) for v in args.s_extra.split(",") if v and int(v) != args.s]
     results = {}
     for s_nnz in s_list:
@@ -214,7 +229,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head["precision"] == "fp64" else "f64 (CG products f32)",
         "data": "synthetic planted LP (seeded), resident in HBM",
-        "config": {"workload": f"config {args.config}: dense {lp.m} x {lp.n} "
+        "config": {"workload": f"config {args.config}: {lp.fmt} {lp.m} x {lp.n} "
                                f"{'FP64' if lp.a_dtype == 'f64' else 'FP32'} planted LP, "
                                f"sketch w={lp.w}, s={args.s}, rel. gap {lp.eps_gap:g}",
                    "m": lp.m, "n": lp.n, "w": lp.w, "s": args.s,
@@ -226,7 +241,8 @@ def main():
         "mixed_over_fp64": speedup,
         "roofline": {"bound": "hbm", "achieved": mv["matvec_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": mv["matvec_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_colpass (fused normal matvec A D^2 A^T u)",
+                     "kernel": ("k_colpass (fused normal matvec A D^2 A^T u)" if lp.fmt == "dense"
+                                else "k_csc_dot + k_csr_seg + k_csr_fold (sparse normal matvec)"),
                      "avg_ms": mv["matvec_ms"], "bytes_per_launch": mv["matvec_bytes"]},
         "cpu_baseline": cpu,
     }

@@ -184,31 +184,50 @@ class LP:
     """One LP resident on the GPU (a handle from lp_create).
 
     A: dense (m, n) array/tensor (row-major in Python; it is handed to the
-    library column-major).  a_dtype: "f64" or "f32" (the precision A's values are
-    stored in).  Keyword parameters override skipm_params_default()."""
+    library column-major), or a scipy.sparse matrix (handed over as CSR).
+    a_dtype: "f64" or "f32" (the precision A's values are stored in).  Keyword
+    parameters override skipm_params_default()."""
 
     def __init__(self, A, b, c, a_dtype="f64", stream=None, **params):
+        import numpy as np
         import torch
         self._lib = load()
         self.stream = stream
+        self.handle = None
         tdt = torch.float64 if a_dtype == "f64" else torch.float32
-        At = _as_device(A, tdt)
-        m, n = At.shape
-        self.m, self.n = int(m), int(n)
-        a_col = At.t().contiguous()          # (n, m) row-major == (m, n) column-major
+        dt = SKIPM_F64 if a_dtype == "f64" else SKIPM_F32
         self._b = _as_device(b, torch.float64).contiguous()
         self._c = _as_device(c, torch.float64).contiguous()
-        prob = Problem(m=m, n=n, nnz=0, format=SKIPM_DENSE,
-                       a_dtype=SKIPM_F64 if a_dtype == "f64" else SKIPM_F32,
-                       a_vals=a_col.data_ptr(), lda=m, a_rowptr=None, a_colidx=None,
-                       b=self._b.data_ptr(), c=self._c.data_ptr())
+        keep = []
+        if hasattr(A, "tocsr"):
+            # scipy.sparse matrix: hand over CSR (int32 indices)
+            Acsr = A.tocsr()
+            Acsr.sort_indices()
+            m, n = Acsr.shape
+            rowptr = _as_device(np.asarray(Acsr.indptr, dtype=np.int32), torch.int32)
+            colidx = _as_device(np.asarray(Acsr.indices, dtype=np.int32), torch.int32)
+            vals = _as_device(np.asarray(Acsr.data), tdt).contiguous()
+            keep = [rowptr, colidx, vals]
+            prob = Problem(m=m, n=n, nnz=int(Acsr.nnz), format=SKIPM_CSR, a_dtype=dt,
+                           a_vals=vals.data_ptr(), lda=0, a_rowptr=rowptr.data_ptr(),
+                           a_colidx=colidx.data_ptr(), b=self._b.data_ptr(),
+                           c=self._c.data_ptr())
+        else:
+            At = _as_device(A, tdt)
+            m, n = At.shape
+            a_col = At.t().contiguous()          # (n, m) row-major == (m, n) column-major
+            keep = [a_col]
+            prob = Problem(m=m, n=n, nnz=0, format=SKIPM_DENSE, a_dtype=dt,
+                           a_vals=a_col.data_ptr(), lda=m, a_rowptr=None, a_colidx=None,
+                           b=self._b.data_ptr(), c=self._c.data_ptr())
+        self.m, self.n = int(m), int(n)
         self.params = default_params(**params)
         h = C.c_void_p()
         _check(self._lib.lp_create(C.byref(h), C.byref(prob), C.byref(self.params),
                                    _stream(stream)), "lp_create")
         self.handle = h
         self.w = self.params.w if self.params.w > 0 else 4 * self.m
-        del a_col
+        del keep
 
     def close(self):
         if getattr(self, "handle", None):

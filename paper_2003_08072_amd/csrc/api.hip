@@ -60,6 +60,10 @@ struct skipm_lp_s {
   int last_outer = 0;
   int demoted = 0;  // mixed precision switched to FP64 CG for the rest of this run
   int vrounds_built = 0;
+  // CSR storage (format SKIPM_CSR)
+  SparseA sp;
+  double *cf1 = nullptr, *cf2 = nullptr, *segsum = nullptr;
+  int nblk_csc = 1;
   int32_t *bucket = nullptr, *perm = nullptr, *perm_raw = nullptr, *bptr = nullptr,
           *bcnt = nullptr, *bcur = nullptr;
   int8_t* sign = nullptr;
@@ -161,7 +165,38 @@ ColPass colpass_A(skipm_lp_s* lp, int mode) {
   return cp;
 }
 
+int prologue_sparse(skipm_lp_s* lp, hipStream_t st) {
+  const SparseA& A = lp->sp;
+  if (launch_csc_dot(A, COL_PROLOGUE, lp->y, lp->x, lp->sv, lp->c, nullptr, nullptr, nullptr,
+                     lp->cf2, lp->rd, lp->d2, nullptr, lp->red, lp->sc, nullptr, lp->nblk_csc,
+                     st) != 0)
+    return set_error("m too large for the sparse path"), SKIPM_EINVAL;
+  // r_p = A x - b ; p = b - A (sigma mu / s + d2 r_d)
+  launch_csr_segsum(A, lp->x, lp->cf2, lp->segsum, nullptr, st);
+  launch_csr_fold(A, lp->segsum, 0, 1.0, lp->b, -1.0, lp->rp, nullptr, st);
+  launch_csr_fold(A, lp->segsum, 1, -1.0, lp->b, 1.0, lp->p, nullptr, st);
+  launch_prologue_finalize(lp->m, lp->rp, lp->b, lp->y, lp->red, lp->nblk_csc, lp->sc,
+                           lp->origin_pending, st);
+  lp->origin_pending = 0;
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// out = scale * A D^2 A^T u + beta * add, sparse A (two passes + fold)
+int normal_sparse(skipm_lp_s* lp, const double* u, double scale, const double* add, double beta,
+                  double* out, const int32_t* done, hipStream_t st) {
+  const SparseA& A = lp->sp;
+  if (launch_csc_dot(A, COL_NORMAL, u, nullptr, nullptr, nullptr, nullptr, lp->d2, lp->cf1,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, lp->sc, done, lp->nblk_csc,
+                     st) != 0)
+    return set_error("m too large for the sparse path"), SKIPM_EINVAL;
+  launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, done, st);
+  launch_csr_fold(A, lp->segsum, 0, scale, add, beta, out, done, st);
+  return SKIPM_OK;
+}
+
 int prologue(skipm_lp_s* lp, hipStream_t st) {
+  if (lp->fmt == SKIPM_CSR) return prologue_sparse(lp, st);
   ColPass cp = colpass_A(lp, COL_PROLOGUE);
   cp.u = lp->y;
   cp.x = lp->x;
@@ -226,6 +261,14 @@ int qinv_apply(skipm_lp_s* lp, const double* u, double* out, const int32_t* done
 // One CG iteration on A D^2 A^T (the chunk loop checks the done flag).
 int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
   const int32_t* done = lp->is + I_CG_DONE;
+  if (lp->fmt == SKIPM_CSR) {
+    SK_TRY(normal_sparse(lp, lp->cd, 1.0, nullptr, 0.0, lp->cq, done, st));
+    SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
+    launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
+                     nullptr, 0, lp->sc, lp->is, st);
+    SK_CHECK_HIP(hipGetLastError());
+    return SKIPM_OK;
+  }
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;
@@ -273,12 +316,16 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
 // FP64 residual of the normal equations, rt = rhs - A D^2 A^T x (one FP64 pass
 // over A), and S_RHO2 = rt^T Q^{-1} rt.
 int normal_residual_fp64(skipm_lp_s* lp, const double* rhs, const double* x, hipStream_t st) {
-  ColPass cp = colpass_A(lp, COL_NORMAL);
-  cp.u = x;
-  cp.d2 = lp->d2;
-  SK_TRY(run_colpass(cp, st));
-  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, rhs, 1.0, lp->rt, nullptr,
-                st);
+  if (lp->fmt == SKIPM_CSR) {
+    SK_TRY(normal_sparse(lp, x, -1.0, rhs, 1.0, lp->rt, nullptr, st));
+  } else {
+    ColPass cp = colpass_A(lp, COL_NORMAL);
+    cp.u = x;
+    cp.d2 = lp->d2;
+    SK_TRY(run_colpass(cp, st));
+    launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, rhs, 1.0, lp->rt,
+                  nullptr, st);
+  }
   SK_TRY(qinv_apply(lp, lp->rt, lp->uv1, nullptr, st));
   launch_dot(lp->rt, lp->uv1, lp->m, lp->sc, S_RHO2, st);
   SK_CHECK_HIP(hipGetLastError());
@@ -355,13 +402,28 @@ int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, in
 int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, double* B,
                 hipStream_t st) {
   SK_TRY(hash_items(lp, salt, st));
-  launch_sketch_dense(lp->A, lp->a_dtype, lp->lda, lp->m, lp->n, lp->s, dscale, is_d2, lp->bptr,
-                      lp->perm, lp->sign, lp->w, B, lp->lda, st);
+  if (lp->fmt == SKIPM_CSR)
+    launch_sketch_csc(lp->sp, lp->s, dscale, is_d2, lp->bptr, lp->perm, lp->sign, lp->w, B,
+                      lp->lda, st);
+  else
+    launch_sketch_dense(lp->A, lp->a_dtype, lp->lda, lp->m, lp->n, lp->s, dscale, is_d2,
+                        lp->bptr, lp->perm, lp->sign, lp->w, B, lp->lda, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
 
 int epilogue(skipm_lp_s* lp, hipStream_t st) {
+  if (lp->fmt == SKIPM_CSR) {
+    const SparseA& A = lp->sp;
+    if (launch_csc_dot(A, COL_EPILOGUE, lp->dy, nullptr, nullptr, nullptr, lp->rd, lp->d2,
+                       lp->cf1, nullptr, nullptr, nullptr, lp->ds, nullptr, lp->sc, nullptr,
+                       lp->nblk_csc, st) != 0)
+      return set_error("m too large for the sparse path"), SKIPM_EINVAL;
+    launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, nullptr, st);
+    launch_csr_fold(A, lp->segsum, 0, 1.0, lp->p, -1.0, lp->g, nullptr, st);
+    SK_CHECK_HIP(hipGetLastError());
+    return SKIPM_OK;
+  }
   ColPass cp = colpass_A(lp, COL_EPILOGUE);
   cp.u = lp->dy;
   cp.rd = lp->rd;
@@ -715,15 +777,21 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   *out = nullptr;
   const int64_t m = prob->m, n = prob->n;
   if (m < 1 || n < m) return set_error("need 1 <= m <= n"), SKIPM_EINVAL;
-  if (prob->format != SKIPM_DENSE)
-    return set_error("only SKIPM_DENSE storage is supported by this build"), SKIPM_EINVAL;
+  if (prob->format != SKIPM_DENSE && prob->format != SKIPM_CSR)
+    return set_error("format must be SKIPM_DENSE or SKIPM_CSR"), SKIPM_EINVAL;
   if (prob->a_dtype != SKIPM_F64 && prob->a_dtype != SKIPM_F32)
     return set_error("a_dtype must be SKIPM_F64 or SKIPM_F32"), SKIPM_EINVAL;
   if (!prob->a_vals || !prob->b || !prob->c) return set_error("null problem pointer"), SKIPM_EINVAL;
+  const bool csr = prob->format == SKIPM_CSR;
+  if (csr && (!prob->a_rowptr || !prob->a_colidx))
+    return set_error("CSR needs a_rowptr and a_colidx"), SKIPM_EINVAL;
+  if (csr && (prob->nnz < 0 || prob->nnz > INT32_MAX))
+    return set_error("nnz must lie in [0, 2^31)"), SKIPM_EINVAL;
+  if (csr && n > INT32_MAX - 1) return set_error("n too large for int32 indices"), SKIPM_EINVAL;
   const int64_t lda_in = prob->lda > 0 ? prob->lda : m;
-  if (lda_in < m) return set_error("lda < m"), SKIPM_EINVAL;
+  if (!csr && lda_in < m) return set_error("lda < m"), SKIPM_EINVAL;
   SK_TRY(validate_params(*prm, m, n));
-  if (m > 2048) return set_error("dense path supports m <= 2048"), SKIPM_EINVAL;
+  if (m > 2048) return set_error("m <= 2048 is supported"), SKIPM_EINVAL;
 
   skipm_lp_s* lp = new skipm_lp_s();
   hipGetDevice(&lp->device);
@@ -734,7 +802,9 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   lp->prm = *prm;
   lp->w = prm->w > 0 ? prm->w : (int)(4 * m);
   lp->s = prm->s;
-  lp->mixed = prm->precision == SKIPM_PREC_MIXED;
+  // a CSR problem's values are read as stored (FP32 or FP64) with FP64
+  // accumulation in every pass, so it has no separate mixed mode
+  lp->mixed = prm->precision == SKIPM_PREC_MIXED && !csr;
   lp->lda = round_up(m, 4);
   lp->mp = round_up(m, 64);
   lp->nb = chol_block(lp->mp);
@@ -747,7 +817,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     return rc;                               \
   }
   const size_t esz = lp->a_dtype == SKIPM_F64 ? 8 : 4;
-  {
+  if (!csr) {
     void* p = nullptr;
     if (hipMalloc(&p, esz * lda * n) != hipSuccess) {
       lp_destroy(lp);
@@ -755,6 +825,75 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     }
     lp->allocs.push_back(p);
     lp->A = p;
+  } else {
+    const int64_t nnz = prob->nnz;
+    lp->nnz = nnz;
+    SparseA& S = lp->sp;
+    S.m = m;
+    S.n = n;
+    S.nnz = nnz;
+    S.vdt = lp->a_dtype;
+    int32_t *rowptr, *colidx, *colptr, *rowidx, *cnt, *cursor, *segptr, *nsegv, *bad;
+    void *val, *cval;
+    ALLOC(rowptr, m + 1);
+    ALLOC(colidx, nnz);
+    ALLOC(colptr, n + 1);
+    ALLOC(rowidx, nnz);
+    ALLOC(cnt, std::max<int64_t>(n, m));
+    ALLOC(cursor, std::max<int64_t>(n, m));
+    ALLOC(segptr, m + 1);
+    ALLOC(nsegv, m);
+    ALLOC(bad, 1);
+    {
+      double* vp = nullptr;
+      double* cp = nullptr;
+      ALLOC(vp, (nnz * (int64_t)esz + 7) / 8);
+      ALLOC(cp, (nnz * (int64_t)esz + 7) / 8);
+      val = vp;
+      cval = cp;
+    }
+    SK_CHECK_HIP(hipMemcpyAsync(rowptr, prob->a_rowptr, (m + 1) * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, st));
+    if (nnz > 0) {
+      SK_CHECK_HIP(hipMemcpyAsync(colidx, prob->a_colidx, nnz * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, st));
+      SK_CHECK_HIP(hipMemcpyAsync(val, prob->a_vals, nnz * esz, hipMemcpyDeviceToDevice, st));
+    }
+    launch_fill_i32(bad, 0, 1, st);
+    launch_csr_check(rowptr, colidx, m, n, nnz, bad, st);
+    int32_t hbad = 0;
+    SK_CHECK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SK_CHECK_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+      lp_destroy(lp);
+      return set_error(hbad & 1 ? "CSR row pointers are invalid"
+                                : "CSR column indices out of range or not increasing"),
+             SKIPM_EINVAL;
+    }
+    launch_build_csc(rowptr, colidx, val, lp->a_dtype, m, n, nnz, cnt, colptr, cursor, rowidx,
+                     cval, st);
+    launch_build_segments(rowptr, m, kSeg, nsegv, segptr, cursor, nullptr, nullptr, st);
+    int32_t hnseg = 0;
+    SK_CHECK_HIP(hipMemcpyAsync(&hnseg, segptr + m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SK_CHECK_HIP(hipStreamSynchronize(st));
+    int32_t *seg_start, *seg_end;
+    ALLOC(seg_start, hnseg);
+    ALLOC(seg_end, hnseg);
+    launch_build_segments(rowptr, m, kSeg, nsegv, segptr, cursor, seg_start, seg_end, st);
+    S.rowptr = rowptr;
+    S.colidx = colidx;
+    S.val = val;
+    S.colptr = colptr;
+    S.rowidx = rowidx;
+    S.cval = cval;
+    S.nseg = hnseg;
+    S.segptr = segptr;
+    S.seg_start = seg_start;
+    S.seg_end = seg_end;
+    ALLOC(lp->cf1, n);
+    ALLOC(lp->cf2, n);
+    ALLOC(lp->segsum, 2 * (int64_t)hnseg);
+    lp->nblk_csc = csc_dot_nblk(n);
   }
   if (lp->mixed) ALLOC(lp->A32, lda * n);
   ALLOC(lp->b, mp);
@@ -817,7 +956,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     ALLOC(pp, pe);
     lp->part = pp;
   }
-  ALLOC(lp->red, (int64_t)std::max(std::max(lp->nblk_Ap, lp->nblk_vec), 64) * 8);
+  ALLOC(lp->red,
+        (int64_t)std::max(std::max(std::max(lp->nblk_Ap, lp->nblk_vec), lp->nblk_csc), 64) * 8);
   ALLOC(lp->sc, S_NSLOTS);
   ALLOC(lp->is, I_NINTS);
 #undef ALLOC
@@ -836,7 +976,9 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   launch_fill_f64(lp->B, 0.0, lda * w, st);
   launch_copy_f64(lp->b, prob->b, m, st);
   launch_copy_f64(lp->c, prob->c, n, st);
-  if (lp->a_dtype == SKIPM_F64) {
+  if (csr) {
+    // A lives in lp->sp
+  } else if (lp->a_dtype == SKIPM_F64) {
     launch_pad_copy_f64((double*)lp->A, lda, (const double*)prob->a_vals, lda_in, m, n, st);
     if (lp->mixed)
       launch_pad_copy_f64_to_f32(lp->A32, lda, (const double*)prob->a_vals, lda_in, m, n, st);
@@ -961,6 +1103,26 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   if (reps < 1) return set_error("reps must be >= 1"), SKIPM_EINVAL;
   SK_CHECK_HIP(hipSetDevice(lp->device));
   launch_copy_f64(lp->cd, u, lp->m, st);
+  if (lp->fmt == SKIPM_CSR) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+      SK_CHECK_HIP(hipEventCreate(&e0));
+      SK_CHECK_HIP(hipEventCreate(&e1));
+      SK_CHECK_HIP(hipEventRecord(e0, st));
+    }
+    for (int r = 0; r < reps; ++r) SK_TRY(normal_sparse(lp, lp->cd, 1.0, nullptr, 0.0, out, nullptr, st));
+    if (ms) {
+      float tot = 0;
+      SK_CHECK_HIP(hipEventRecord(e1, st));
+      SK_CHECK_HIP(hipEventSynchronize(e1));
+      SK_CHECK_HIP(hipEventElapsedTime(&tot, e0, e1));
+      *ms = tot / (float)reps;
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+    }
+    SK_CHECK_HIP(hipGetLastError());
+    return SKIPM_OK;
+  }
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;

@@ -135,6 +135,49 @@ void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk,
                    double scale, const double* add, double beta, double* out,
                    const int32_t* done, hipStream_t st);
 
+// sparse A: CSR for products A v (rows cut into segments of at most kSeg
+// non-zeros), CSC for the column dots and the sketch
+struct SparseA {
+  int64_t m = 0, n = 0, nnz = 0;
+  int vdt = SKIPM_F64;
+  const int32_t* rowptr = nullptr;
+  const int32_t* colidx = nullptr;
+  const void* val = nullptr;
+  const int32_t* colptr = nullptr;
+  const int32_t* rowidx = nullptr;
+  const void* cval = nullptr;
+  int64_t nseg = 0;
+  const int32_t* segptr = nullptr;
+  const int32_t* seg_start = nullptr;
+  const int32_t* seg_end = nullptr;
+};
+constexpr int kSeg = 2048;
+void launch_csr_check(const int32_t* rowptr, const int32_t* colidx, int64_t m, int64_t n,
+                      int64_t nnz, int32_t* bad, hipStream_t st);
+void launch_build_csc(const int32_t* rowptr, const int32_t* colidx, const void* val, int vdt,
+                      int64_t m, int64_t n, int64_t nnz, int32_t* cnt, int32_t* colptr,
+                      int32_t* cursor, int32_t* rowidx, void* cval, hipStream_t st);
+void launch_build_segments(const int32_t* rowptr, int64_t m, int seg, int32_t* nseg,
+                           int32_t* segptr, int32_t* cursor, int32_t* seg_start, int32_t* seg_end,
+                           hipStream_t st);
+// per column j: t_j = a_j^T u and the mode's work (COL_NORMAL: coef1 = d2 t;
+// COL_PROLOGUE: r_d, d^2, coef2 = sigma mu / s + d^2 r_d; COL_EPILOGUE: ds,
+// coef1 = d2 t; COL_DOT: coef1 = t)
+int launch_csc_dot(const SparseA& A, int mode, const double* u, const double* x, const double* s,
+                   const double* c, const double* rd, const double* d2, double* coef1,
+                   double* coef2, double* rd_out, double* d2_out, double* ds_out, double* red,
+                   const double* sc, const int32_t* done, int nblk, hipStream_t st);
+int csc_dot_nblk(int64_t n);
+// segment sums of A coef1 (and A coef2), then out = scale * (A coef_which) + beta * add
+void launch_csr_segsum(const SparseA& A, const double* coef1, const double* coef2,
+                       double* segsum, const int32_t* done, hipStream_t st);
+void launch_csr_fold(const SparseA& A, const double* segsum, int which, double scale,
+                     const double* add, double beta, double* out, const int32_t* done,
+                     hipStream_t st);
+void launch_sketch_csc(const SparseA& A, int s, const double* dscale, int is_d2,
+                       const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
+                       double* B, int64_t ldb, hipStream_t st);
+
 // Gram matrix and its inverse (blocked Cholesky, triangular inverse, X^T X)
 void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart,
                  int ksplit, int64_t mp, hipStream_t st);

@@ -309,3 +309,61 @@ def test_solve_config1_full_size(torch, sk):
     with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
         res = h.solve()
     check_solution(lp, res, lp.eps_gap)
+
+
+# ---------------------------------------------------------------------------
+# sparse (CSR) problems
+# ---------------------------------------------------------------------------
+
+def test_csr_rejects_bad_structure(torch, sk):
+    import scipy.sparse as sp
+    say("csr validation")
+    lp = dense_planted(4, 30, rng=np.random.default_rng(1))
+    A = sp.csr_matrix(lp.A)
+    A.indices[3], A.indices[4] = A.indices[4], A.indices[3]   # unsorted columns in row 0
+    A.has_sorted_indices = True                                  # keep the binding from sorting
+    A.sort_indices = lambda: None
+    with pytest.raises(sk.SkipmError) as e:
+        sk.LP(A, lp.b, lp.c)
+    assert e.value.code == sk.SKIPM_EINVAL
+
+
+@pytest.mark.parametrize("m,n,dens,s_nnz", [(20, 3000, 0.02, 2), (37, 5000, 0.005, 1),
+                                           (130, 20000, 0.002, 2)])
+def test_csr_solve_matches_planted_objective(torch, sk, m, n, dens, s_nnz):
+    from lpgen import csr_planted
+    lp = csr_planted(m, n, dens, rng=np.random.default_rng(m), eps_gap=1e-8)
+    say(f"csr solve m={m} n={n} density={dens} s={s_nnz}")
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", s=s_nnz, eps_gap=1e-8, seed=m) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-8)
+
+
+def test_csr_and_dense_agree(torch, sk):
+    from lpgen import csr_planted
+    lp = csr_planted(25, 2000, 0.01, rng=np.random.default_rng(3))
+    say("csr vs dense: pcg and sketch")
+    rng = np.random.default_rng(4)
+    d2 = rng.uniform(0.05, 20.0, lp.n)
+    p = rng.standard_normal(lp.m)
+    out = {}
+    for kind, A in (("csr", lp.A), ("dense", lp.A.toarray())):
+        with sk.LP(A, lp.b, lp.c, a_dtype="f32", seed=8, s=2) as h:
+            dy, info = h.pcg(d2, p, 3, tol=0.0, max_it=6)
+            B = h.sketch(np.sqrt(d2), 3).cpu().numpy()
+            out[kind] = (dy.cpu().numpy(), info.iters, B)
+    assert out["csr"][1] == out["dense"][1] == 6
+    assert np.linalg.norm(out["csr"][0] - out["dense"][0]) <= 1e-9 * np.linalg.norm(out["dense"][0])
+    W = sketch_matrix(8, 3, 2, lp.n, lp.w)
+    Bref = np.asarray((W.T @ (lp.A.toarray() * np.sqrt(d2)).T).T)
+    bound = np.asarray((abs(W).T @ abs(lp.A.toarray() * np.sqrt(d2)).T).T)
+    for kind in ("csr", "dense"):
+        assert np.all(np.abs(out[kind][2] - Bref) <= 64 * EPS * bound + 1e-300)
+
+
+def test_solve_config2_full_size(torch, sk):
+    lp = config_lp(2)
+    say("solve config 2 (CSR 1000 x 1000000, ~2e6 nnz, FP32 values, w=4000, s=1)")
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
+        res = h.solve()
+    check_solution(lp, res, lp.eps_gap)
