@@ -102,7 +102,7 @@ def percentile(xs, q):
 def run_mode(sk, torch, lp, precision, s_nnz, args):
     prec = sk.SKIPM_PREC_MIXED if precision == "mixed" else sk.SKIPM_PREC_FP64
     h = sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=s_nnz,
-              eps_gap=lp.eps_gap, precision=prec)
+              eps_gap=lp.eps_gap, precision=prec, max_outer=1000)
     stream = torch.cuda.current_stream()
     res = None
     for _ in range(args.warmup):

@@ -214,6 +214,86 @@ int ipm_step(skipm_lp_t lp, skipm_step_info* info, hipStream_t stream);
  * max_outer iterations.  res: host. */
 int lp_solve(skipm_lp_t lp, skipm_result* res, hipStream_t stream);
 
+/* ---- many LPs ------------------------------------------------------------ */
+
+/* Device bytes that lp_create and a following lp_solve allocate for this
+ * problem (an upper bound, counted the way the library allocates; what the
+ * request server admits against its budget).  prob's pointers are not read.
+ * *bytes: host. */
+int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* bytes);
+
+/* Device bytes the handle holds now.  *bytes: host. */
+int lp_device_bytes(skipm_lp_t lp, int64_t* bytes);
+
+/* Solve `count` independent LPs (handles from lp_create, each from its
+ * current iterate, as lp_solve).  `workers` host threads (<= 0: min(count, 8))
+ * each own one non-blocking stream of default priority and take the next
+ * unsolved handle in index order, so up to `workers` LPs run their IPM
+ * iterations at once and their kernels overlap on the device.  Each LP's
+ * arithmetic is that of lp_solve alone, so res[i] (and its final iterate) is
+ * bitwise the same as a lone solve.  The call first waits for all work queued
+ * on the device and returns when every LP has finished.  res: host array of
+ * `count`.  Returns SKIPM_OK when every solve ran, an LP's outcome (OK,
+ * ENOTCONV, ESTALL, ERANK, ENAN) being res[i].status; an argument, memory or
+ * device error stops the batch and is returned. */
+int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t workers);
+
+/* Request server: a FIFO of LP solves admitted by device-memory footprint.
+ * srv_create starts `slots` worker threads (each with its own non-blocking
+ * stream).  A worker takes the request at the head of the queue once its
+ * footprint (lp_footprint) fits in hbm_budget minus the footprints of the
+ * requests running; it then creates the LP from the request's buffers, solves
+ * it (lp_solve), optionally copies the final x out, and frees the LP.  Requests
+ * that arrive while others run are admitted as slots and memory free up, so
+ * their IPM iterations overlap on the device with those already running. */
+typedef struct skipm_server_s* skipm_server_t;
+
+#define SKIPM_REQ_QUEUED  0
+#define SKIPM_REQ_RUNNING 1
+#define SKIPM_REQ_DONE    2
+
+typedef struct {
+  skipm_result res;      /* as lp_solve; res.status also carries a create error */
+  int32_t state;         /* SKIPM_REQ_* */
+  int32_t rc;            /* SKIPM_OK, or the argument/memory/device error of the request */
+  int64_t footprint;     /* bytes reserved against the budget */
+  int64_t device_bytes;  /* bytes the LP actually held at the end of its solve */
+  double t_submit;       /* server clock (seconds since srv_create) */
+  double t_start;        /* admitted: a worker began creating the LP */
+  double t_done;         /* result available */
+} skipm_request_info;
+
+typedef struct {
+  int64_t budget, in_use, peak_in_use;
+  int32_t slots, running, queued;
+  int64_t completed;
+} skipm_server_stats;
+
+/* hbm_budget > 0 bytes; slots in [1, 64].  Uses the current device. */
+int srv_create(skipm_server_t* srv, int64_t hbm_budget, int32_t slots);
+
+/* Queue one solve.  prob's device buffers (A, b, c) are read when the request
+ * is admitted, after the work queued on `producer` at the time of this call:
+ * they must stay valid until the request is SKIPM_REQ_DONE.  x_out: device,
+ * n doubles, receives the final x (may be NULL).  *ticket: host.  Returns
+ * SKIPM_ENOMEM at once if the footprint exceeds the whole budget. */
+int srv_submit(skipm_server_t srv, const skipm_problem* prob, const skipm_params* prm,
+               double* x_out, hipStream_t producer, uint64_t* ticket);
+
+/* Current state of a request, without waiting.  info: host. */
+int srv_poll(skipm_server_t srv, uint64_t ticket, skipm_request_info* info);
+
+/* Wait until the request is done.  info: host. */
+int srv_wait(skipm_server_t srv, uint64_t ticket, skipm_request_info* info);
+
+/* Seconds since srv_create on the server's clock.  *t: host. */
+int srv_now(skipm_server_t srv, double* t);
+
+int srv_stats(skipm_server_t srv, skipm_server_stats* stats);
+
+/* Finish every queued and running request, stop the workers, free the server. */
+int srv_destroy(skipm_server_t srv);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* skipm_last_error(void);
 

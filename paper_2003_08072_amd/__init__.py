@@ -66,6 +66,22 @@ class PcgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("f0_norm", C.c_double), ("f_norm", C.c_double)]
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [("res", Result), ("state", C.c_int32), ("rc", C.c_int32),
+                ("footprint", C.c_int64), ("device_bytes", C.c_int64),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("budget", C.c_int64), ("in_use", C.c_int64), ("peak_in_use", C.c_int64),
+                ("slots", C.c_int32), ("running", C.c_int32), ("queued", C.c_int32),
+                ("completed", C.c_int64)]
+
+
+SKIPM_REQ_QUEUED = 0
+SKIPM_REQ_RUNNING = 1
+SKIPM_REQ_DONE = 2
+
 # every symbol the header declares, with its ctypes signature
 _VP = C.c_void_p
 SIGNATURES = {
@@ -85,6 +101,17 @@ SIGNATURES = {
     "normal_matvec_timed": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.POINTER(C.c_float), _VP]),
     "ipm_step": (C.c_int, [_VP, C.POINTER(StepInfo), _VP]),
     "lp_solve": (C.c_int, [_VP, C.POINTER(Result), _VP]),
+    "lp_footprint": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_int64)]),
+    "lp_device_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "lp_solve_batch": (C.c_int, [C.POINTER(_VP), C.c_int32, C.POINTER(Result), C.c_int32]),
+    "srv_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.c_int32]),
+    "srv_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP,
+                             C.POINTER(C.c_uint64)]),
+    "srv_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(RequestInfo)]),
+    "srv_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(RequestInfo)]),
+    "srv_now": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "srv_stats": (C.c_int, [_VP, C.POINTER(ServerStats)]),
+    "srv_destroy": (C.c_int, [_VP]),
     "skipm_last_error": (C.c_char_p, []),
 }
 
@@ -162,6 +189,46 @@ def _as_device(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
+def problem(A, b, c, a_dtype="f64"):
+    """(Problem, tensors that must outlive its use): A, b, c on the device in the
+    layout lp_create reads.  A: dense (m, n) array/tensor, handed over
+    column-major, or a scipy.sparse matrix, handed over as CSR (int32 indices)."""
+    import numpy as np
+    import torch
+    tdt = torch.float64 if a_dtype == "f64" else torch.float32
+    dt = SKIPM_F64 if a_dtype == "f64" else SKIPM_F32
+    bt = _as_device(b, torch.float64).contiguous()
+    ct = _as_device(c, torch.float64).contiguous()
+    if hasattr(A, "tocsr"):
+        Acsr = A.tocsr()
+        Acsr.sort_indices()
+        m, n = Acsr.shape
+        rowptr = _as_device(np.asarray(Acsr.indptr, dtype=np.int32), torch.int32)
+        colidx = _as_device(np.asarray(Acsr.indices, dtype=np.int32), torch.int32)
+        vals = _as_device(np.asarray(Acsr.data), tdt).contiguous()
+        keep = [rowptr, colidx, vals, bt, ct]
+        prob = Problem(m=m, n=n, nnz=int(Acsr.nnz), format=SKIPM_CSR, a_dtype=dt,
+                       a_vals=vals.data_ptr(), lda=0, a_rowptr=rowptr.data_ptr(),
+                       a_colidx=colidx.data_ptr(), b=bt.data_ptr(), c=ct.data_ptr())
+    else:
+        At = _as_device(A, tdt)
+        m, n = At.shape
+        a_col = At.t().contiguous()          # (n, m) row-major == (m, n) column-major
+        keep = [a_col, bt, ct]
+        prob = Problem(m=m, n=n, nnz=0, format=SKIPM_DENSE, a_dtype=dt,
+                       a_vals=a_col.data_ptr(), lda=m, a_rowptr=None, a_colidx=None,
+                       b=bt.data_ptr(), c=ct.data_ptr())
+    return prob, keep
+
+
+def footprint(prob: Problem, **params) -> int:
+    """Device bytes lp_create + lp_solve allocate for `prob` (lp_footprint)."""
+    out = C.c_int64()
+    prm = default_params(**params)
+    _check(load().lp_footprint(C.byref(prob), C.byref(prm), C.byref(out)), "lp_footprint")
+    return int(out.value)
+
+
 @dataclasses.dataclass
 class SolveResult:
     status: int
@@ -189,38 +256,11 @@ class LP:
     parameters override skipm_params_default()."""
 
     def __init__(self, A, b, c, a_dtype="f64", stream=None, **params):
-        import numpy as np
-        import torch
         self._lib = load()
         self.stream = stream
         self.handle = None
-        tdt = torch.float64 if a_dtype == "f64" else torch.float32
-        dt = SKIPM_F64 if a_dtype == "f64" else SKIPM_F32
-        self._b = _as_device(b, torch.float64).contiguous()
-        self._c = _as_device(c, torch.float64).contiguous()
-        keep = []
-        if hasattr(A, "tocsr"):
-            # scipy.sparse matrix: hand over CSR (int32 indices)
-            Acsr = A.tocsr()
-            Acsr.sort_indices()
-            m, n = Acsr.shape
-            rowptr = _as_device(np.asarray(Acsr.indptr, dtype=np.int32), torch.int32)
-            colidx = _as_device(np.asarray(Acsr.indices, dtype=np.int32), torch.int32)
-            vals = _as_device(np.asarray(Acsr.data), tdt).contiguous()
-            keep = [rowptr, colidx, vals]
-            prob = Problem(m=m, n=n, nnz=int(Acsr.nnz), format=SKIPM_CSR, a_dtype=dt,
-                           a_vals=vals.data_ptr(), lda=0, a_rowptr=rowptr.data_ptr(),
-                           a_colidx=colidx.data_ptr(), b=self._b.data_ptr(),
-                           c=self._c.data_ptr())
-        else:
-            At = _as_device(A, tdt)
-            m, n = At.shape
-            a_col = At.t().contiguous()          # (n, m) row-major == (m, n) column-major
-            keep = [a_col]
-            prob = Problem(m=m, n=n, nnz=0, format=SKIPM_DENSE, a_dtype=dt,
-                           a_vals=a_col.data_ptr(), lda=m, a_rowptr=None, a_colidx=None,
-                           b=self._b.data_ptr(), c=self._c.data_ptr())
-        self.m, self.n = int(m), int(n)
+        prob, keep = problem(A, b, c, a_dtype)
+        self.m, self.n = int(prob.m), int(prob.n)
         self.params = default_params(**params)
         h = C.c_void_p()
         _check(self._lib.lp_create(C.byref(h), C.byref(prob), C.byref(self.params),
@@ -328,3 +368,108 @@ class LP:
             _check(code, "lp_solve")
         return SolveResult(code, res.iters, res.cg_total, res.cg_max, res.obj_p, res.obj_d,
                            res.rel_gap, res.rp_norm, res.rd_norm, res.mu)
+
+    def device_bytes(self) -> int:
+        out = C.c_int64()
+        _check(self._lib.lp_device_bytes(self.handle, C.byref(out)), "lp_device_bytes")
+        return int(out.value)
+
+
+def _result(res: Result, status=None) -> SolveResult:
+    return SolveResult(res.status if status is None else status, res.iters, res.cg_total,
+                       res.cg_max, res.obj_p, res.obj_d, res.rel_gap, res.rp_norm, res.rd_norm,
+                       res.mu)
+
+
+def solve_batch(lps, workers=0):
+    """lp_solve_batch over LP objects; returns one SolveResult per LP."""
+    n = len(lps)
+    handles = (C.c_void_p * n)(*[lp.handle.value for lp in lps])
+    res = (Result * n)()
+    _check(load().lp_solve_batch(handles, n, res, int(workers)), "lp_solve_batch")
+    return [_result(r) for r in res]
+
+
+@dataclasses.dataclass
+class RequestResult:
+    result: SolveResult
+    state: int
+    rc: int
+    footprint: int
+    device_bytes: int
+    t_submit: float
+    t_start: float
+    t_done: float
+
+    @property
+    def latency(self):
+        return self.t_done - self.t_submit
+
+
+class Server:
+    """The request server (srv_*): FIFO admission by device-memory footprint,
+    `slots` LPs in flight at once."""
+
+    def __init__(self, hbm_budget, slots=4):
+        self._lib = load()
+        self.handle = None
+        h = C.c_void_p()
+        _check(self._lib.srv_create(C.byref(h), int(hbm_budget), int(slots)), "srv_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, A, b, c, a_dtype="f32", want_x=False, stream=None, **params):
+        import torch
+        prob, keep = problem(A, b, c, a_dtype)
+        prm = default_params(**params)
+        x = torch.empty(int(prob.n), dtype=torch.float64, device="cuda") if want_x else None
+        t = C.c_uint64()
+        _check(self._lib.srv_submit(self.handle, C.byref(prob), C.byref(prm), _ptr(x),
+                                    _stream(stream), C.byref(t)), "srv_submit")
+        self._keep[t.value] = (keep, x)
+        return t.value
+
+    def _info(self, fn, ticket):
+        info = RequestInfo()
+        _check(fn(self.handle, C.c_uint64(ticket), C.byref(info)), "srv_poll/wait")
+        out = RequestResult(_result(info.res), info.state, info.rc, info.footprint,
+                            info.device_bytes, info.t_submit, info.t_start, info.t_done)
+        return out
+
+    def poll(self, ticket):
+        return self._info(self._lib.srv_poll, ticket)
+
+    def wait(self, ticket):
+        """Wait for the request; returns (RequestResult, x or None) and drops the
+        request's input buffers."""
+        r = self._info(self._lib.srv_wait, ticket)
+        _, x = self._keep.pop(ticket, (None, None))
+        return r, x
+
+    def now(self):
+        t = C.c_double()
+        _check(self._lib.srv_now(self.handle, C.byref(t)), "srv_now")
+        return t.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(self._lib.srv_stats(self.handle, C.byref(s)), "srv_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.srv_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

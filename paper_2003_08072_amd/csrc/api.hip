@@ -32,6 +32,7 @@ using namespace skipm;
 
 struct skipm_lp_s {
   int device = 0;
+  int64_t bytes = 0;  // device bytes held (every allocation of the handle)
   int64_t m = 0, n = 0, nnz = 0;
   int fmt = SKIPM_DENSE, a_dtype = SKIPM_F64;
   int64_t lda = 0, mp = 0;
@@ -95,6 +96,7 @@ int dalloc(skipm_lp_s* lp, T** out, int64_t count) {
     return SKIPM_ENOMEM;
   }
   lp->allocs.push_back(p);
+  lp->bytes += (int64_t)bytes;
   *out = (T*)p;
   return SKIPM_OK;
 }
@@ -743,6 +745,95 @@ int skipm_params_default(skipm_params* out) {
   return SKIPM_OK;
 }
 
+int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* out) {
+  if (!prob || !prm || !out) return set_error("null argument"), SKIPM_EINVAL;
+  const int64_t m = prob->m, n = prob->n;
+  if (m < 1 || n < m || m > 2048) return set_error("need 1 <= m <= min(n, 2048)"), SKIPM_EINVAL;
+  SK_TRY(validate_params(*prm, m, n));
+  const bool csr = prob->format == SKIPM_CSR;
+  const bool f64 = prob->a_dtype == SKIPM_F64;
+  const int64_t esz = f64 ? 8 : 4;
+  const int64_t lda = round_up(m, 4), mp = round_up(m, 64);
+  const int64_t w = prm->w > 0 ? prm->w : 4 * m, s = prm->s;
+  int64_t b = 0, nalloc = 0;
+  auto add = [&](int64_t bytes) {
+    b += std::max<int64_t>(bytes, 8);
+    ++nalloc;
+  };
+  int nblk_csc = 0;
+  if (!csr) {
+    add(esz * lda * n);
+    if (prm->precision == SKIPM_PREC_MIXED && f64) add(4 * lda * n);
+  } else {
+    const int64_t nnz = prob->nnz;
+    const int64_t nseg = m + nnz / kSeg + 1;
+    add(4 * (m + 1));
+    add(4 * nnz);
+    add(4 * (n + 1));
+    add(4 * nnz);
+    add(4 * std::max(n, m));
+    add(4 * std::max(n, m));
+    add(4 * (m + 1));
+    add(4 * m);
+    add(4);
+    add(8 * ((nnz * esz + 7) / 8));
+    add(8 * ((nnz * esz + 7) / 8));
+    add(4 * nseg);
+    add(4 * nseg);
+    add(8 * n);
+    add(8 * n);
+    add(16 * nseg);
+    nblk_csc = csc_dot_nblk(n);
+  }
+  for (int i = 0; i < 8; ++i) add(8 * n);    // c x s d2 r_d dx ds v
+  for (int i = 0; i < 17; ++i) add(8 * mp);  // m-vectors
+  add(8 * w);
+  add(8 * w);
+  add(8 * lda * w);  // B
+  {
+    const int64_t T = mp / 64, ntiles = T * (T + 1) / 2;
+    int64_t ks = std::max<int64_t>(1, std::min<int64_t>(16, 320 / ntiles));
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, w / 64));
+    add(8 * ks * mp * mp);
+  }
+  add(8 * mp * mp);
+  add(8 * mp * mp);
+  add(4 * n * s);
+  add(n * s);
+  add(4 * n * s);
+  add(4 * n * s);
+  add(4 * (w + 1));
+  add(4 * w);
+  add(4 * w);
+  const int ta = prob->a_dtype;
+  const int nblk_A = colpass_nblk(lda, n, ta, SKIPM_F64, COL_NORMAL);
+  const int nblk_Ap = colpass_nblk(lda, n, ta, SKIPM_F64, COL_PROLOGUE);
+  const int nblk_A32 = colpass_nblk(lda, n, SKIPM_F32, SKIPM_F64, COL_NORMAL);
+  const int nblk_B = colpass_nblk(lda, w, SKIPM_F64, SKIPM_F64, COL_NORMAL);
+  const int nblk_vec = vec_nblk(n);
+  int64_t pe = std::max<int64_t>(2 * (int64_t)nblk_Ap * mp, (int64_t)nblk_A * mp);
+  pe = std::max<int64_t>(pe, (int64_t)nblk_B * mp);
+  pe = std::max<int64_t>(pe, (int64_t)nblk_A32 * mp);
+  pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
+  add(8 * pe);
+  add(8 * 8 * (int64_t)std::max(std::max(std::max(nblk_Ap, nblk_vec), nblk_csc), 64));
+  add(8 * S_NSLOTS);
+  add(4 * I_NINTS);
+  // correction-vector buffers (allocated at the first direction)
+  add(8 * lda * w);
+  add(8 * lda * w);
+  for (int i = 0; i < 4; ++i) add(8 * mp * mp);
+  // allocation granularity
+  *out = b + nalloc * (int64_t)(64 << 10);
+  return SKIPM_OK;
+}
+
+int lp_device_bytes(skipm_lp_t lp, int64_t* out) {
+  if (!lp || !out) return set_error("null argument"), SKIPM_EINVAL;
+  *out = lp->bytes;
+  return SKIPM_OK;
+}
+
 int lp_destroy(skipm_lp_t lp) {
   if (!lp) return SKIPM_OK;
   hipSetDevice(lp->device);
@@ -824,6 +915,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
       return set_error("hipMalloc of A failed"), SKIPM_ENOMEM;
     }
     lp->allocs.push_back(p);
+    lp->bytes += (int64_t)(esz * lda * n);
     lp->A = p;
   } else {
     const int64_t nnz = prob->nnz;

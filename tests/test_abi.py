@@ -68,3 +68,85 @@ def test_argument_validation_without_device():
         assert lib.lp_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(p), None) == \
             sk.SKIPM_EINVAL, bad
     assert lib.sketch_hash(0, 0, 3, 10, 10, None, None, None) == sk.SKIPM_EINVAL
+
+
+def _c_layouts():
+    """sizeof / offsetof of the header's structs, from a C compiler reading the
+    header itself (skipped without gcc or the HIP headers)."""
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None or not Path("/opt/rocm/include/hip").is_dir():
+        pytest.skip("gcc or HIP headers missing")
+    fields = {
+        "skipm_problem": ["m", "nnz", "format", "a_vals", "lda", "a_colidx", "c"],
+        "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed"],
+        "skipm_result": ["status", "cg_max", "obj_p", "mu"],
+        "skipm_step_info": ["mu", "v_resid", "cg_iters", "status"],
+        "skipm_pcg_info": ["iters", "f0_norm", "f_norm"],
+        "skipm_request_info": ["res", "state", "rc", "footprint", "device_bytes", "t_submit",
+                               "t_done"],
+        "skipm_server_stats": ["budget", "peak_in_use", "slots", "queued", "completed"],
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "skipm.h"', "int main(void){"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src = Path(d) / "l.c"
+        src.write_text("\n".join(lines))
+        exe = Path(d) / "l"
+        r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                            f"-I{HEADER.parent}", str(src), "-o", str(exe)],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("header does not compile as plain C here: " + r.stderr[-300:])
+        out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        st, f, v = line.split()
+        got[(st, f)] = int(v)
+    return got
+
+
+def test_ctypes_structs_match_the_c_compiler():
+    got = _c_layouts()
+    py = {"skipm_problem": sk.Problem, "skipm_params": sk.Params, "skipm_result": sk.Result,
+          "skipm_step_info": sk.StepInfo, "skipm_pcg_info": sk.PcgInfo,
+          "skipm_request_info": sk.RequestInfo, "skipm_server_stats": sk.ServerStats}
+    for (st, f), v in got.items():
+        cls = py[st]
+        if f == "sizeof":
+            assert ctypes.sizeof(cls) == v, st
+        else:
+            assert getattr(cls, f).offset == v, (st, f)
+
+
+def test_footprint_is_host_only_and_grows_with_the_problem():
+    small = sk.Problem(m=50, n=1000, nnz=0, format=sk.SKIPM_DENSE, a_dtype=sk.SKIPM_F64)
+    big = sk.Problem(m=500, n=100_000, nnz=0, format=sk.SKIPM_DENSE, a_dtype=sk.SKIPM_F64)
+    f_small, f_big = sk.footprint(small), sk.footprint(big)
+    assert f_small < f_big
+    assert f_big >= 500 * 100_000 * 8 + 2 * 500 * 2000 * 8   # A plus B and its refinement copy
+    mixed = sk.footprint(big, precision=sk.SKIPM_PREC_MIXED)
+    assert mixed >= f_big + 500 * 100_000 * 4                 # plus the FP32 copy
+    csr = sk.Problem(m=1000, n=1_000_000, nnz=1_999_000, format=sk.SKIPM_CSR,
+                     a_dtype=sk.SKIPM_F32)
+    f_csr = sk.footprint(csr)
+    assert 2 * 1_999_000 * 8 <= f_csr < 1_000_000 * 1000 * 4  # both copies, far below dense
+    with pytest.raises(sk.SkipmError):
+        sk.footprint(sk.Problem(m=10, n=5, format=sk.SKIPM_DENSE, a_dtype=sk.SKIPM_F64))
+
+
+def test_batch_and_server_validate_arguments_without_a_device():
+    lib = sk.load()
+    res = (sk.Result * 1)()
+    assert lib.lp_solve_batch(None, 0, res, 0) == sk.SKIPM_OK
+    handles = (ctypes.c_void_p * 1)(None)
+    assert lib.lp_solve_batch(handles, 1, res, 0) == sk.SKIPM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.srv_create(ctypes.byref(h), 1 << 30, 0) == sk.SKIPM_EINVAL
+    assert lib.srv_create(ctypes.byref(h), 0, 4) == sk.SKIPM_EINVAL
+    assert lib.srv_destroy(None) == sk.SKIPM_OK

@@ -1,0 +1,131 @@
+"""Many LPs at once: lp_solve_batch and the request server, through the C ABI.
+
+The bar: each LP's result and final iterate are bitwise the same alone and in
+a batch or in the server's mix (an LP's arithmetic never depends on what runs
+beside it), and each meets the stopping tolerance against its planted optimum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from lpgen import batch_lp, csr_planted, dense_planted
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2003_08072_amd as _sk
+    _sk.load()
+    return _sk
+
+
+def mixed_set():
+    """Small LPs of uneven shape and format: dense FP64, dense FP32, CSR."""
+    out = []
+    rng = np.random.default_rng(11)
+    for i, (m, n) in enumerate([(20, 500), (45, 2000), (7, 300), (64, 5000), (33, 900),
+                                (120, 6000)]):
+        out.append(dense_planted(m, n, rng=rng, a_dtype="f64" if i % 2 else "f32",
+                                 eps_gap=1e-8, seed=100 + i))
+    for i, (m, n, dens) in enumerate([(30, 4000, 0.01), (80, 10000, 0.005)]):
+        out.append(csr_planted(m, n, dens, rng=np.random.default_rng(20 + i), eps_gap=1e-8,
+                               seed=200 + i))
+    return out
+
+
+def check_planted(lp, r):
+    assert r.status == 0, r
+    assert r.rel_gap <= lp.eps_gap
+    assert abs(r.obj_p - lp.opt) <= 2 * lp.eps_gap * max(1.0, abs(lp.opt))
+
+
+def same(r1, r2):
+    for f in ("status", "iters", "cg_total", "cg_max", "obj_p", "obj_d", "rel_gap", "rp_norm",
+              "rd_norm", "mu"):
+        assert getattr(r1, f) == getattr(r2, f), f
+
+
+def test_batch_matches_lone_solves(torch, sk):
+    lps = mixed_set()
+    say(f"batch of {len(lps)} mixed LPs, 4 workers, vs lone solves")
+    hs = [sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed,
+                eps_gap=lp.eps_gap) for lp in lps]
+    lone, xs = [], []
+    for h in hs:
+        lone.append(h.solve())
+        xs.append(h.get_iterate()[0].cpu().numpy())
+        h.reset()
+    torch.cuda.synchronize()
+    batch = sk.solve_batch(hs, workers=4)
+    for lp, h, r1, r2, x1 in zip(lps, hs, lone, batch, xs):
+        check_planted(lp, r2)
+        same(r1, r2)
+        assert np.array_equal(h.get_iterate()[0].cpu().numpy(), x1)
+    for h in hs:
+        h.close()
+
+
+def test_batch_workload_sample(torch, sk):
+    idx = list(range(12))
+    say("batched workload: LPs 0..11 (dense FP32, m in [20, 400], n = m k)")
+    lps = [batch_lp(i) for i in idx]
+    hs = [sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed,
+                eps_gap=lp.eps_gap) for lp in lps]
+    res = sk.solve_batch(hs, workers=8)
+    for lp, r in zip(lps, res):
+        check_planted(lp, r)
+    for h in hs:
+        h.close()
+
+
+def test_server_same_alone_and_in_the_mix(torch, sk):
+    lps = mixed_set()
+    say(f"server: {len(lps)} requests, 3 slots, budget for about two at once")
+    fps = []
+    for lp in lps:
+        prob, keep = sk.problem(lp.A, lp.b, lp.c, lp.a_dtype)
+        fps.append(sk.footprint(prob, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap))
+        del keep
+    budget = int(sorted(fps)[-1] + sorted(fps)[-2])
+    alone = []
+    for lp in lps:
+        with sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed,
+                   eps_gap=lp.eps_gap) as h:
+            alone.append((h.solve(), h.get_iterate()[0].cpu().numpy(), h.device_bytes()))
+    with sk.Server(budget, slots=3) as srv:
+        tickets = [srv.submit(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, want_x=True, w=lp.w,
+                              seed=lp.seed, eps_gap=lp.eps_gap) for lp in lps]
+        got = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(lps) and st["running"] == 0 and st["queued"] == 0
+    assert st["peak_in_use"] <= budget
+    for lp, (r1, x1, bytes1), (rq, x2), fp in zip(lps, alone, got, fps):
+        assert rq.state == sk.SKIPM_REQ_DONE and rq.rc == 0
+        check_planted(lp, rq.result)
+        same(r1, rq.result)
+        assert np.array_equal(x2.cpu().numpy(), x1)
+        assert rq.footprint == fp and bytes1 <= fp and rq.device_bytes == bytes1
+        assert rq.t_submit <= rq.t_start <= rq.t_done
+
+
+def test_server_rejects_what_never_fits(torch, sk):
+    lp = dense_planted(20, 500, rng=np.random.default_rng(5), a_dtype="f32")
+    say("server: request above the whole budget")
+    with sk.Server(1 << 20, slots=1) as srv:
+        with pytest.raises(sk.SkipmError) as e:
+            srv.submit(lp.A, lp.b, lp.c, a_dtype="f32")
+        assert e.value.code == sk.SKIPM_ENOMEM

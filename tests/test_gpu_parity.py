@@ -364,6 +364,9 @@ def test_csr_and_dense_agree(torch, sk):
 def test_solve_config2_full_size(torch, sk):
     lp = config_lp(2)
     say("solve config 2 (CSR 1000 x 1000000, ~2e6 nnz, FP32 values, w=4000, s=1)")
-    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
+    # the exact-Cholesky oracle needs 306 IPM iterations on this LP: long runs of
+    # short steps, where a few columns sit on the neighbourhood's boundary
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap,
+               max_outer=1000) as h:
         res = h.solve()
     check_solution(lp, res, lp.eps_gap)
