@@ -32,7 +32,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4],
+                    help="0-2: one LP; 3: the batched workload (256 LPs); 4: the serving trace")
+    ap.add_argument("--batch", type=int, default=256, help="config 3: number of LPs")
+    ap.add_argument("--workers", type=int, default=8,
+                    help="config 3: host threads (streams) of lp_solve_batch; config 4: slots")
+    ap.add_argument("--requests", type=int, default=120,
+                    help="config 4: requests taken from the head of the arrival trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="config 4: arrivals per second")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0,
+                    help="config 4: device memory the server may admit against")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--s", type=int, default=1,
                     help="non-zeros per row of the sketch for the headline (1: CountSketch)")
@@ -177,6 +186,155 @@ def cpu_baseline(lp, budget):
                        f"{est_iters} iterations per solve")
 
 
+def _ok(res, lp):
+    return (res.status == 0 and res.rel_gap <= lp.eps_gap
+            and abs(res.obj_p - lp.opt) <= 2 * lp.eps_gap * max(1.0, abs(lp.opt)))
+
+
+def run_batch(sk, torch, args):
+    """Config 3: 256 dense FP32 planted LPs (m ~ U{20..400}, n = m k,
+    k ~ U{20..200}, w = 4m) solved by lp_solve_batch; a step is one pass over the
+    whole batch (reset every LP to the start point, solve all)."""
+    from lpgen.device import batch_lp_device
+    t0 = time.perf_counter()
+    lps, hs = [], []
+    for i in range(args.batch):
+        lp = batch_lp_device(i)
+        hs.append(sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, s=args.s,
+                        eps_gap=lp.eps_gap, max_outer=1000))
+        lp.A = None  # the handle holds its own copy
+        lps.append(lp)
+    torch.cuda.synchronize()
+    print(f"[bench] batch of {len(hs)} created in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    res = None
+    for _ in range(args.warmup):
+        for h in hs:
+            h.reset()
+        res = sk.solve_batch(hs, workers=args.workers)
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        for h in hs:
+            h.reset()
+        res = sk.solve_batch(hs, workers=args.workers)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t1)
+    ok = [_ok(r, lp) for r, lp in zip(res, lps)]
+    wall = sum(walls)
+    # bytes the CG products read over one batch pass (FP32 A, once per CG iteration)
+    cg_bytes = sum(4.0 * lp.m * lp.n * (r.cg_total + 2 * r.iters) for r, lp in zip(res, lps))
+    # dominant kernel: the fused normal matvec of the largest LP
+    big = max(range(len(lps)), key=lambda i: lps[i].m * lps[i].n)
+    h = hs[big]
+    h.reset()
+    h.step()
+    u = torch.randn(lps[big].m, dtype=torch.float64, device="cuda")
+    h.normal_matvec(u, reps=3)
+    mv_ms = h.normal_matvec_timed(u, reps=args.matvec_reps)
+    mv_bytes = 4 * lps[big].m * lps[big].n + 4 * lps[big].n
+    for hh in hs:
+        hh.close()
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = cpu_baseline_batch(args.cpu_budget)
+    return {
+        "metric": METRIC, "value": len(lps) * args.steps / wall, "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (A values f32)",
+        "data": "synthetic planted LPs generated on the device (seeded), resident in HBM",
+        "config": {"workload": f"config 3: {len(lps)} dense FP32 planted LPs, m~U{{20..400}}, "
+                               f"n=m*U{{20..200}}, w=4m, s={args.s}, rel. gap 1e-6, "
+                               f"lp_solve_batch with {args.workers} workers",
+                   "lps": len(lps), "s": args.s, "workers": args.workers,
+                   "total_A_bytes": int(sum(4 * lp.m * lp.n for lp in lps))},
+        "all_ok": all(ok), "n_ok": int(sum(ok)),
+        "ipm_iters_mean": sum(r.iters for r in res) / len(res),
+        "cg_total_mean": sum(r.cg_total for r in res) / len(res),
+        "batch_walls_s": walls,
+        "cg_product_gbs": cg_bytes * args.steps / wall / 1e9,
+        "roofline": {"bound": "hbm", "achieved": mv_bytes / (mv_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_colpass (fused normal matvec) on the largest LP "
+                               f"{lps[big].m} x {lps[big].n} FP32",
+                     "avg_ms": mv_ms, "bytes_per_launch": mv_bytes},
+        "cpu_baseline": cpu,
+    }
+
+
+def cpu_baseline_batch(budget):
+    """The oracle (exact-Cholesky IPM) on the host cores over the numpy LPs of
+    the batched workload, in index order, until `budget` seconds are spent."""
+    from lpgen import batch_lp
+    from oracle import ipm as O
+    cores = len(os.sched_getaffinity(0))
+    t_used, done, i = 0.0, 0, 0
+    while t_used < budget and i < 64:
+        lp = batch_lp(i)
+        t0 = time.perf_counter()
+        O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap))
+        t_used += time.perf_counter() - t0
+        done += 1
+        i += 1
+    return dict(value=done / t_used, unit="solves/s", cores=cores, kind="oracle",
+                sample=f"LPs 0..{done - 1} of the batched workload (numpy draws of the same "
+                       f"distribution), full exact-Cholesky solves, {t_used:.1f} s")
+
+
+def run_serving(sk, torch, args):
+    """Config 4: the head of the Poisson request trace, replayed in real time
+    against the request server (FIFO admission by device footprint).  Problem
+    data of every request is generated on the device before the clock starts;
+    each request is submitted at its arrival time."""
+    from lpgen import serving_trace
+    from lpgen.device import serving_lp_device
+    trace = serving_trace(n_req=args.requests, rate=args.rate)
+    t0 = time.perf_counter()
+    lps = [serving_lp_device(r) for r in trace]
+    torch.cuda.synchronize()
+    print(f"[bench] {len(lps)} requests generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    budget = int(args.hbm_budget_gb * 1e9)
+    srv = sk.Server(budget, slots=args.workers)
+    tickets = []
+    start = time.perf_counter()
+    s_start = srv.now()
+    for req, lp in zip(trace, lps):
+        delay = req["t"] - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed,
+                                  s=args.s, eps_gap=lp.eps_gap, max_outer=1000))
+    done = [srv.wait(t)[0] for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    lat = [d.latency * 1000.0 for d in done]
+    queue_ms = [(d.t_start - d.t_submit) * 1000.0 for d in done]
+    span = max(d.t_done for d in done) - s_start
+    ok = [_ok(d.result, lp) for d, lp in zip(done, lps)]
+    return {
+        "metric": METRIC, "value": len(done) / span, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1000.0 * span, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (A values f32)",
+        "data": "synthetic planted LPs generated on the device (seeded)",
+        "config": {"workload": f"config 4: first {len(done)} requests of the Poisson trace "
+                               f"({args.rate:g}/s), 50/50 dense FP32 / 1% CSR, w=4m, "
+                               f"s={args.s}, {args.workers} slots, budget "
+                               f"{args.hbm_budget_gb:g} GB",
+                   "requests": len(done), "rate": args.rate, "slots": args.workers,
+                   "s": args.s},
+        "all_ok": all(ok), "n_ok": int(sum(ok)),
+        "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+        "queue_p50_ms": percentile(queue_ms, 50), "queue_p99_ms": percentile(queue_ms, 99),
+        "offered_span_s": trace[-1]["t"],
+        "peak_hbm_in_use_gb": stats["peak_in_use"] / 1e9,
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -193,6 +351,12 @@ def main():
     from lpgen import config_lp
 
     sk.load()
+    if args.config == 3:
+        print(json.dumps(run_batch(sk, torch, args)), flush=True)
+        return
+    if args.config == 4:
+        print(json.dumps(run_serving(sk, torch, args)), flush=True)
+        return
     lp = config_lp(args.config)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     if lp.fmt != "dense":

@@ -11,6 +11,7 @@ from .planted import (  # noqa: F401
     csr_planted,
     config_lp,
     batch_lp,
+    batch_shape,
     serving_trace,
     serving_lp,
     sketch_seed,

@@ -130,6 +130,13 @@ def config_lp(cfg: int, idx: int = 0) -> PlantedLP:
                        p["eps_gap"], sketch_seed(cfg, idx), name)
 
 
+def batch_shape(idx: int):
+    """(m, k) of LP `idx` of the batched workload: m ~ U{20..400}, k ~ U{20..200}
+    (the first two draws of that LP's stream)."""
+    rng = np.random.default_rng(np.random.SeedSequence([3, idx]))
+    return int(rng.integers(20, 401)), int(rng.integers(20, 201))
+
+
 def batch_lp(idx: int) -> PlantedLP:
     """LP `idx` of the batched workload: m ~ U{20..400}, n = m*k, k ~ U{20..200},
     dense FP32 values, support m, w = 4m."""

@@ -192,14 +192,25 @@ def _as_device(a, dtype):
 def problem(A, b, c, a_dtype="f64"):
     """(Problem, tensors that must outlive its use): A, b, c on the device in the
     layout lp_create reads.  A: dense (m, n) array/tensor, handed over
-    column-major, or a scipy.sparse matrix, handed over as CSR (int32 indices)."""
+    column-major; a scipy.sparse matrix, handed over as CSR (int32 indices); or a
+    tuple (rowptr, colidx, values) of CSR device tensors (int32 indices)."""
     import numpy as np
     import torch
     tdt = torch.float64 if a_dtype == "f64" else torch.float32
     dt = SKIPM_F64 if a_dtype == "f64" else SKIPM_F32
     bt = _as_device(b, torch.float64).contiguous()
     ct = _as_device(c, torch.float64).contiguous()
-    if hasattr(A, "tocsr"):
+    if isinstance(A, tuple):
+        # CSR already on the device: (rowptr int32 (m+1), colidx int32 (nnz), values)
+        rowptr, colidx, vals = (t.contiguous() for t in A)
+        assert rowptr.dtype == torch.int32 and colidx.dtype == torch.int32
+        vals = vals.to(tdt)
+        m, n = bt.numel(), ct.numel()
+        keep = [rowptr, colidx, vals, bt, ct]
+        prob = Problem(m=m, n=n, nnz=int(colidx.numel()), format=SKIPM_CSR, a_dtype=dt,
+                       a_vals=vals.data_ptr(), lda=0, a_rowptr=rowptr.data_ptr(),
+                       a_colidx=colidx.data_ptr(), b=bt.data_ptr(), c=ct.data_ptr())
+    elif hasattr(A, "tocsr"):
         Acsr = A.tocsr()
         Acsr.sort_indices()
         m, n = Acsr.shape

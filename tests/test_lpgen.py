@@ -58,3 +58,33 @@ def test_batch_and_serving_shapes():
     small = min(tr, key=lambda r: r["m"] * r["n"])
     lp = serving_lp(small)
     _check_planted(lp)
+
+
+def _check_device_planted(A, lp, support):
+    x, y, s = lp.x_star.numpy(), lp.y_star.numpy(), lp.s_star.numpy()
+    assert np.allclose(A @ x, lp.b.numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(A.T @ y + s, lp.c.numpy(), rtol=1e-12, atol=1e-12)
+    assert np.all(x >= 0) and np.all(s >= 0) and np.all(x * s == 0)
+    assert np.count_nonzero(x) == support
+    assert abs(lp.opt - float(lp.c.numpy() @ x)) <= 1e-12 * max(1.0, abs(lp.opt))
+    assert abs(lp.opt - float(lp.b.numpy() @ y)) <= 1e-9 * max(1.0, abs(lp.opt))
+
+
+def test_device_generators_plant_an_optimum_on_cpu():
+    import scipy.sparse as ssp
+    import torch
+    from lpgen.device import csr_planted_device, dense_planted_device
+    lp = dense_planted_device(30, 700, seed=5, dev="cpu")
+    assert lp.A.dtype == torch.float32 and lp.A.t().is_contiguous()   # column-major storage
+    _check_device_planted(lp.A.to(torch.float64).numpy(), lp, 30)
+    sp = csr_planted_device(12, 3000, 0.01, seed=6, dev="cpu")
+    rowptr, colidx, vals = (t.numpy() for t in sp.A)
+    assert rowptr[0] == 0 and rowptr[-1] == colidx.size and np.all(np.diff(rowptr) >= 0)
+    for i in range(sp.m - 1):
+        cols = colidx[rowptr[i]:rowptr[i + 1]]
+        assert cols.size == 30 and np.all(np.diff(cols) > 0)
+        assert cols.min() >= 0 and cols.max() < sp.n
+    last = slice(rowptr[-2], rowptr[-1])
+    assert np.array_equal(colidx[last], np.arange(sp.n)) and np.all(vals[last] == 1.0)
+    Asp = ssp.csr_matrix((vals.astype(np.float64), colidx, rowptr), shape=(sp.m, sp.n))
+    _check_device_planted(Asp, sp, 12)
