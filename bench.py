@@ -24,6 +24,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the fused normal matvec on config 1, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 2.000, the factor a
+# 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
+# current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
+MEASURED_TRAFFIC = {(1, "mixed"): 202_055_194, (1, "fp64"): 402_925_338}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 
@@ -87,14 +93,14 @@ def run_probe(args):
 def matvec_bytes(lp, precision):
     """Algorithmic HBM bytes of one normal product A D^2 A^T u.
 
-    Dense: A once (m n values) and D^2 once (n values, stored in A's precision
-    inside the pass).  CSR: the column pass reads the CSC copy (row indices,
+    Dense: A once (m n values in the precision the CG reads), D^2 once (n FP64
+    values), u in and the product out (m FP64 each).  CSR: the column pass reads the CSC copy (row indices,
     values, column pointers) and D^2 and writes one coefficient per column; the
     row pass reads the CSR copy (column indices, values, row pointers) and the
     coefficients once."""
     pa = 4 if (precision == "mixed" or lp.a_dtype == "f32") else 8
     if lp.fmt == "dense":
-        return lp.m * lp.n * pa + lp.n * pa
+        return lp.m * lp.n * pa + lp.n * 8 + 2 * lp.m * 8
     nnz = int(lp.A.nnz)
     return 2 * nnz * (4 + pa) + (lp.n + 1) * 4 + (lp.m + 1) * 4 + 3 * lp.n * 8
 
@@ -120,6 +126,9 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
     lat = []
     iters = []
     cg = []
+    # in-situ timing of the dominant kernel: HIP events stamped with the start
+    # and end of every 8th CG product of the timed solves (library's stream)
+    h.kernel_timing(8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -135,12 +144,14 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
         cg.append(res.cg_total)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kt_ms, kt_n = h.kernel_time()
+    h.kernel_timing(0)
     ok = (res.status == 0 and res.rel_gap <= lp.eps_gap
           and abs(res.obj_p - lp.opt) <= 2 * lp.eps_gap * max(1.0, abs(lp.opt)))
-    # dominant kernel: the fused normal matvec (CG products), with the D^2 of the
-    # last IPM iteration; HIP events on the library's stream around back-to-back
-    # passes.  reset() first: a mixed-precision run that fell back to FP64
-    # products is timed with its FP32 products.
+    # the same product launched back to back outside the solve (D^2 of the first
+    # IPM iteration; HIP events around `matvec_reps` passes), for comparison.
+    # reset() first: a mixed-precision run that fell back to FP64 products is
+    # timed with its FP32 products.
     h.reset()
     h.step()
     u = torch.randn(lp.m, dtype=torch.float64, device="cuda")
@@ -154,7 +165,9 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
         p99_ms=percentile(lat, 99), ipm_iters=iters[-1], cg_total=cg[-1],
         rel_gap=res.rel_gap, obj_rel_err=abs(res.obj_p - lp.opt) / max(1.0, abs(lp.opt)),
         rp_rel=res.rp_norm / float(sum(v * v for v in lp.b) ** 0.5),
-        matvec_ms=mv_ms, matvec_bytes=mv_bytes, matvec_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9)
+        matvec_ms=kt_ms, matvec_samples=kt_n, matvec_bytes=mv_bytes,
+        matvec_gbs=mv_bytes / (kt_ms * 1e-3) / 1e9 if kt_n else None,
+        matvec_b2b_ms=mv_ms, matvec_b2b_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(lp, budget):
@@ -404,10 +417,16 @@ def main():
         "modes": results,
         "mixed_over_fp64": speedup,
         "roofline": {"bound": "hbm", "achieved": mv["matvec_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": mv["matvec_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": mv["matvec_gbs"] / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get((args.config, head["precision"])),
                      "kernel": ("k_colpass (fused normal matvec A D^2 A^T u)" if lp.fmt == "dense"
                                 else "k_csc_dot + k_csr_seg + k_csr_fold (sparse normal matvec)"),
-                     "avg_ms": mv["matvec_ms"], "bytes_per_launch": mv["matvec_bytes"]},
+                     "avg_ms": mv["matvec_ms"], "samples": mv["matvec_samples"],
+                     "timing": "HIP events stamped with the kernel's start and end "
+                               "(hipExtLaunchKernelGGL) on every 8th CG product of the "
+                               "timed solves",
+                     "bytes_per_launch": mv["matvec_bytes"],
+                     "back_to_back_gbs": mv["matvec_b2b_gbs"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

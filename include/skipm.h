@@ -206,6 +206,18 @@ int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps,
 int normal_matvec_timed(skipm_lp_t lp, const double* u, double* out, int32_t reps,
                         float* ms_per_pass, hipStream_t stream);
 
+/* Sampled timing of the CG's normal-equation product A D^2 A^T d inside
+ * ipm_step / lp_solve / pcg_solve (the solver's dominant kernel: the fused
+ * column pass for dense A, the column + row passes for CSR).  every > 0: a HIP
+ * event pair on the solve's stream brackets the product of every `every`-th CG
+ * iteration; pairs are read at the CG's host checks, and those of products
+ * that the done flag skipped are dropped.  every = 0 turns sampling off.
+ * Either call clears the accumulated samples. */
+int lp_kernel_timing(skipm_lp_t lp, int32_t every);
+
+/* Mean duration (ms, host) of the sampled products and their number. */
+int lp_kernel_time(skipm_lp_t lp, double* avg_ms, int64_t* samples);
+
 /* One iteration of Alg. 2 on the handle's iterate (steps a-g), or nothing if
  * the stopping test already holds (info->converged = 1).  info: host, may be NULL. */
 int ipm_step(skipm_lp_t lp, skipm_step_info* info, hipStream_t stream);

@@ -103,6 +103,8 @@ SIGNATURES = {
     "lp_solve": (C.c_int, [_VP, C.POINTER(Result), _VP]),
     "lp_footprint": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_int64)]),
     "lp_device_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "lp_kernel_timing": (C.c_int, [_VP, C.c_int32]),
+    "lp_kernel_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lp_solve_batch": (C.c_int, [C.POINTER(_VP), C.c_int32, C.POINTER(Result), C.c_int32]),
     "srv_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.c_int32]),
     "srv_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP,
@@ -379,6 +381,16 @@ class LP:
             _check(code, "lp_solve")
         return SolveResult(code, res.iters, res.cg_total, res.cg_max, res.obj_p, res.obj_d,
                            res.rel_gap, res.rp_norm, res.rd_norm, res.mu)
+
+    def kernel_timing(self, every=8):
+        """Sample the CG's normal-equation product with HIP events (0: off)."""
+        _check(self._lib.lp_kernel_timing(self.handle, int(every)), "lp_kernel_timing")
+
+    def kernel_time(self):
+        """(mean ms of the sampled products, number of samples)."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.lp_kernel_time(self.handle, C.byref(ms), C.byref(n)), "lp_kernel_time")
+        return float(ms.value), int(n.value)
 
     def device_bytes(self) -> int:
         out = C.c_int64()

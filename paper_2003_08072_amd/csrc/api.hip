@@ -81,6 +81,13 @@ struct skipm_lp_s {
   int small_steps = 0;
   double bnorm = 0, cnorm = 0;
   std::vector<void*> allocs;
+  // sampled HIP-event timing of the CG's normal-equation product (lp_kernel_timing):
+  // event pairs around every kt_every-th product, harvested at the CG's host checks
+  int kt_every = 0;
+  std::vector<hipEvent_t> kt_ev;  // 2 * kKtPairs events
+  std::vector<int> kt_iter;       // CG iteration of each pending pair
+  double kt_sum_ms = 0;
+  int64_t kt_count = 0;
 };
 
 namespace {
@@ -260,11 +267,54 @@ int qinv_apply(skipm_lp_s* lp, const double* u, double* out, const int32_t* done
   return run_colpass(cp, st);
 }
 
+constexpr int kKtPairs = 64;
+
+// Takes an event pair for a timing sample of the product of CG iteration
+// `iter` when sampling is on; returns the pair index or -1.
+int kt_take(skipm_lp_s* lp, int iter) {
+  if (lp->kt_every <= 0 || iter % lp->kt_every != 0) return -1;
+  const int q = (int)lp->kt_iter.size();
+  if (q >= kKtPairs) return -1;
+  lp->kt_iter.push_back(iter);
+  return q;
+}
+
+// Sparse product (three kernels): events recorded on the stream around them.
+int kt_begin(skipm_lp_s* lp, int iter, hipStream_t st) {
+  const int q = kt_take(lp, iter);
+  if (q >= 0 && hipEventRecord(lp->kt_ev[2 * q], st) != hipSuccess) {
+    lp->kt_iter.pop_back();
+    return -1;
+  }
+  return q;
+}
+
+void kt_end(skipm_lp_s* lp, int q, hipStream_t st) {
+  if (q >= 0) hipEventRecord(lp->kt_ev[2 * q + 1], st);
+}
+
+// After a host synchronisation: keep the samples of products that ran (CG
+// iteration index below the number of iterations the CG executed; later ones
+// were skipped by the done flag).
+void kt_harvest(skipm_lp_s* lp, int executed) {
+  for (size_t q = 0; q < lp->kt_iter.size(); ++q) {
+    if (lp->kt_iter[q] >= executed) continue;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, lp->kt_ev[2 * q], lp->kt_ev[2 * q + 1]) == hipSuccess) {
+      lp->kt_sum_ms += ms;
+      ++lp->kt_count;
+    }
+  }
+  lp->kt_iter.clear();
+}
+
 // One CG iteration on A D^2 A^T (the chunk loop checks the done flag).
-int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
+int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   const int32_t* done = lp->is + I_CG_DONE;
   if (lp->fmt == SKIPM_CSR) {
+    const int q = kt_begin(lp, iter, st);
     SK_TRY(normal_sparse(lp, lp->cd, 1.0, nullptr, 0.0, lp->cq, done, st));
+    kt_end(lp, q, st);
     SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
     launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
                      nullptr, 0, lp->sc, lp->is, st);
@@ -280,6 +330,11 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, hipStream_t st) {
     cp.nblk = lp->nblk_A32;
   }
   cp.done = done;
+  const int q = kt_take(lp, iter);
+  if (q >= 0) {  // dense product: the runtime stamps the events with the kernel itself
+    cp.ev0 = lp->kt_ev[2 * q];
+    cp.ev1 = lp->kt_ev[2 * q + 1];
+  }
   SK_TRY(run_colpass(cp, st));
   launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, lp->cq, done, st);
   SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
@@ -299,9 +354,11 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   int chunk = std::max(1, std::min(first_chunk, max_it));
   *fact_fail = 0;
   for (;;) {
-    for (int q = 0; q < chunk && enq < max_it; ++q, ++enq) SK_TRY(pcg_iteration(lp, xsol, st));
+    for (int q = 0; q < chunk && enq < max_it; ++q, ++enq)
+      SK_TRY(pcg_iteration(lp, xsol, enq, st));
     SK_TRY(sync_read(lp, st));
     const int32_t* hi = host_ints(lp);
+    kt_harvest(lp, hi[I_FACT_FAIL] ? 0 : hi[I_CG_ITERS]);
     if (hi[I_FACT_FAIL]) {
       *fact_fail = 1;
       *its = hi[I_CG_ITERS];
@@ -828,6 +885,28 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   return SKIPM_OK;
 }
 
+int lp_kernel_timing(skipm_lp_t lp, int32_t every) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  if (every < 0) return set_error("every must be >= 0"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  if (every > 0 && lp->kt_ev.empty()) {
+    lp->kt_ev.resize(2 * kKtPairs, nullptr);
+    for (auto& e : lp->kt_ev) SK_CHECK_HIP(hipEventCreate(&e));
+  }
+  lp->kt_every = every;
+  lp->kt_iter.clear();
+  lp->kt_sum_ms = 0;
+  lp->kt_count = 0;
+  return SKIPM_OK;
+}
+
+int lp_kernel_time(skipm_lp_t lp, double* avg_ms, int64_t* samples) {
+  if (!lp || !avg_ms || !samples) return set_error("null argument"), SKIPM_EINVAL;
+  *samples = lp->kt_count;
+  *avg_ms = lp->kt_count ? lp->kt_sum_ms / (double)lp->kt_count : 0.0;
+  return SKIPM_OK;
+}
+
 int lp_device_bytes(skipm_lp_t lp, int64_t* out) {
   if (!lp || !out) return set_error("null argument"), SKIPM_EINVAL;
   *out = lp->bytes;
@@ -838,6 +917,8 @@ int lp_destroy(skipm_lp_t lp) {
   if (!lp) return SKIPM_OK;
   hipSetDevice(lp->device);
   for (void* p : lp->allocs) hipFree(p);
+  for (hipEvent_t e : lp->kt_ev)
+    if (e) hipEventDestroy(e);
   if (lp->hsc) hipHostFree(lp->hsc);
   delete lp;
   return SKIPM_OK;

@@ -22,6 +22,8 @@
 // its accumulators in registers, folds its waves together through LDS in a
 // fixed order and writes one partial vector; launch_finish sums the partials
 // of all workgroups in a fixed order, so results are bitwise reproducible.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace skipm {
@@ -404,16 +406,24 @@ constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
 }
 
 template <typename TA, typename TC, int MODE, int G, int R>
-void launch_one(const Args& a, int nblk, hipStream_t st) {
+void launch_one(const Args& a, int nblk, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int NT = threads_for(MODE, R, Vec<TA>::V, (int)sizeof(TC));
-  hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, a);
+  if (e0)  // events stamped by the runtime with the kernel's own start and end
+    hipExtLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, e0,
+                          e1, 0, a);
+  else
+    hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, a);
 }
 
 template <typename TA, typename TC, int MODE>
-int dispatch(const Args& a, int nblk, hipStream_t st) {
+int dispatch(const Args& a, int nblk, hipStream_t st, hipEvent_t e0 = nullptr,
+             hipEvent_t e1 = nullptr) {
   const Shape sh = pick_shape(a.lda, Vec<TA>::V);
-#define SK_CASE(GG, RR) \
-  if (sh.G == GG && sh.R == RR) { launch_one<TA, TC, MODE, GG, RR>(a, nblk, st); return 0; }
+#define SK_CASE(GG, RR)                                              \
+  if (sh.G == GG && sh.R == RR) {                                    \
+    launch_one<TA, TC, MODE, GG, RR>(a, nblk, st, e0, e1);           \
+    return 0;                                                        \
+  }
   SK_CASE(16, 1) SK_CASE(16, 2)
   SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
   SK_CASE(64, 6) SK_CASE(64, 8) SK_CASE(64, 12) SK_CASE(64, 16)
@@ -505,7 +515,7 @@ int launch_colpass(ColPass& c, hipStream_t st) {
   int rc = -1;
   if (c.ta == SKIPM_F64 && c.tc == SKIPM_F64) {
     switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<double, double, COL_NORMAL>(a, nblk, st); break;
+      case COL_NORMAL: rc = dispatch<double, double, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
       case COL_PROLOGUE: rc = dispatch<double, double, COL_PROLOGUE>(a, nblk, st); break;
       case COL_EPILOGUE: rc = dispatch<double, double, COL_EPILOGUE>(a, nblk, st); break;
       case COL_DOT: rc = dispatch<double, double, COL_DOT>(a, nblk, st); break;
@@ -513,14 +523,14 @@ int launch_colpass(ColPass& c, hipStream_t st) {
     }
   } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F64) {
     switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<float, double, COL_NORMAL>(a, nblk, st); break;
+      case COL_NORMAL: rc = dispatch<float, double, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
       case COL_PROLOGUE: rc = dispatch<float, double, COL_PROLOGUE>(a, nblk, st); break;
       case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, st); break;
       case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, st); break;
     }
   } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F32) {
     switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<float, float, COL_NORMAL>(a, nblk, st); break;
+      case COL_NORMAL: rc = dispatch<float, float, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
       case COL_DOT: rc = dispatch<float, float, COL_DOT>(a, nblk, st); break;
     }
   }

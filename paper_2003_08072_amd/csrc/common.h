@@ -117,6 +117,8 @@ struct ColPass {
   const double* sc;         // device scalar slots
   const int32_t* done;      // optional early-exit flag
   int nblk;                 // filled by the launcher
+  hipEvent_t ev0 = nullptr;  // COL_NORMAL: optional events stamped with the kernel's
+  hipEvent_t ev1 = nullptr;  // start and end (sampled timing)
 };
 enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
 int launch_colpass(ColPass& a, hipStream_t st);
