@@ -83,7 +83,11 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   constexpr int NACC = MODE == COL_PROLOGUE ? 2 : (MODE == COL_DOT ? 0 : 1);
   constexpr int NACC1 = NACC > 0 ? NACC : 1;
   constexpr int LROWS = G * R * V;
-  __shared__ TC lds[NACC1][LROWS];
+  // Wave fold of the partial sums: with many waves, each wave parks its sums in
+  // its own LDS row and the rows are added in one step; otherwise (or when
+  // that would take more than 64 KB) the waves add into one row in turn.
+  constexpr bool kOneStep = NW >= 8 && NW * LROWS * sizeof(TC) <= 65536;
+  __shared__ TC lbuf[kOneStep ? NW * LROWS : NACC1 * LROWS];
   __shared__ double sred[NW][4];
 
   if (a.done && *a.done) return;
@@ -232,24 +236,48 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
         if (NACC > 1) acc2[r][e] += __shfl_xor(acc2[r][e], off, 64);
       }
   }
-  // fold the waves together in a fixed order
-  for (int w = 0; w < NW; ++w) {
-    if (wid == w && grp == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          const int idx = (r * G + lg) * V + e;
-          lds[0][idx] = (w == 0 ? (TC)0 : lds[0][idx]) + acc1[r][e];
-          if (NACC > 1) lds[NACC1 - 1][idx] = (w == 0 ? (TC)0 : lds[NACC1 - 1][idx]) + acc2[r][e];
-        }
-    }
-    __syncthreads();
-  }
   TC* part = (TC*)a.part + (int64_t)blockIdx.x * NACC * a.ldp;
-  for (int64_t i = threadIdx.x; i < a.m; i += NT) {
-    part[i] = lds[0][i];
-    if (NACC > 1) part[a.ldp + i] = lds[NACC1 - 1][i];
+  if constexpr (kOneStep) {
+    // each row of the partial is the sum over waves in wave order: the same
+    // order, hence the same rounding, as the turn-by-turn fold below
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+      if (grp == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            lbuf[wid * LROWS + (r * G + lg) * V + e] = k == 0 ? acc1[r][e] : acc2[r][e];
+      }
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < a.m; i += NT) {
+        TC sum = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += lbuf[w * LROWS + i];
+        part[k * a.ldp + i] = sum;
+      }
+      if (k + 1 < NACC) __syncthreads();
+    }
+  } else {
+    for (int w = 0; w < NW; ++w) {
+      if (wid == w && grp == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const int idx = (r * G + lg) * V + e;
+            lbuf[idx] = (w == 0 ? (TC)0 : lbuf[idx]) + acc1[r][e];
+            if (NACC > 1)
+              lbuf[(NACC1 - 1) * LROWS + idx] =
+                  (w == 0 ? (TC)0 : lbuf[(NACC1 - 1) * LROWS + idx]) + acc2[r][e];
+          }
+      }
+      __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < a.m; i += NT) {
+      part[i] = lbuf[i];
+      if (NACC > 1) part[a.ldp + i] = lbuf[(NACC1 - 1) * LROWS + i];
+    }
   }
   if (MODE == COL_PROLOGUE && threadIdx.x == 0) {
     double t0 = 0, t1 = 0, t2 = 0;
