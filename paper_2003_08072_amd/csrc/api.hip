@@ -80,6 +80,10 @@ struct skipm_lp_s {
   int origin_pending = 1;
   int small_steps = 0;
   double bnorm = 0, cnorm = 0;
+  // fused CG (dense A): second direction buffer and the partial sums
+  double* cd2 = nullptr;
+  double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
+  int cg_nf = 0, cg_nd = 0;
   std::vector<void*> allocs;
   // sampled HIP-event timing of the CG's normal-equation product (lp_kernel_timing):
   // event pairs around every kt_every-th product, harvested at the CG's host checks
@@ -335,11 +339,51 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
     cp.ev0 = lp->kt_ev[2 * q];
     cp.ev1 = lp->kt_ev[2 * q + 1];
   }
+  // Three launches per iteration: the product pass opens the iteration (stop
+  // test, beta, d_k), the finish adds d^T q partials, the Q^{-1} pass closes it
+  // (alpha, x, r, z and r^T z partials).  d alternates between two buffers.
+  double* dk = (iter & 1) ? lp->cd2 : lp->cd;
+  const double* dprev = (iter & 1) ? lp->cd : lp->cd2;
+  double* pdq = lp->cgred;
+  double* prz = lp->cgred + lp->cg_nf;
+  cp.u = lp->cd;  // d_0 (written by the CG init) for iteration 0
+  cp.cg.on = 1;
+  cp.cg.k = iter;
+  cp.cg.z = lp->cz;
+  cp.cg.d_old = dprev;
+  cp.cg.d_new = dk;
+  cp.cg.prz = prz;
+  cp.cg.np = lp->cg_nd;
+  cp.cg.sc = lp->sc;
+  cp.cg.is = lp->is;
   SK_TRY(run_colpass(cp, st));
-  launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, lp->cq, done, st);
-  SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
-  launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
-                   nullptr, 0, lp->sc, lp->is, st);
+  if (launch_finish_dot(lp->part, cp.tc, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
+      lp->cg_nf)
+    return set_error("fused CG: finish shape mismatch"), SKIPM_EINVAL;
+  ColPass pq{};
+  pq.mode = COL_DOT;
+  pq.A = lp->G;
+  pq.ta = SKIPM_F64;
+  pq.tc = SKIPM_F64;
+  pq.lda = lp->mp;
+  pq.m = lp->mp;
+  pq.n = lp->m;
+  pq.u = lp->cq;
+  pq.done = done;
+  pq.nblk = lp->cg_nd;
+  pq.cg.on = 1;
+  pq.cg.k = iter;
+  pq.cg.sc = lp->sc;
+  pq.cg.is = lp->is;
+  pq.cg.q = lp->cq;
+  pq.cg.d = dk;
+  pq.cg.x = xsol;
+  pq.cg.r = lp->cr;
+  pq.cg.zz = lp->cz;
+  pq.cg.pdq = pdq;
+  pq.cg.nf = lp->cg_nf;
+  pq.cg.prz_out = prz;
+  SK_TRY(run_colpass(pq, st));
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -356,6 +400,8 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   for (;;) {
     for (int q = 0; q < chunk && enq < max_it; ++q, ++enq)
       SK_TRY(pcg_iteration(lp, xsol, enq, st));
+    if (lp->fmt != SKIPM_CSR && enq >= max_it)  // fused CG: close the capped run
+      launch_cg_close(lp->cgred + lp->cg_nf, lp->cg_nd, enq, lp->sc, lp->is, st);
     SK_TRY(sync_read(lp, st));
     const int32_t* hi = host_ints(lp);
     kt_harvest(lp, hi[I_FACT_FAIL] ? 0 : hi[I_CG_ITERS]);
@@ -843,7 +889,8 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
     nblk_csc = csc_dot_nblk(n);
   }
   for (int i = 0; i < 8; ++i) add(8 * n);    // c x s d2 r_d dx ds v
-  for (int i = 0; i < 17; ++i) add(8 * mp);  // m-vectors
+  for (int i = 0; i < 18; ++i) add(8 * mp);  // m-vectors
+  add(8 * (finish_nblk(m) + 2 * (int64_t)colpass_nblk_dot(mp, m, SKIPM_F64)));  // CG partials
   add(8 * w);
   add(8 * w);
   add(8 * lda * w);  // B
@@ -1086,6 +1133,10 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cr, mp);
   ALLOC(lp->cz, mp);
   ALLOC(lp->cd, mp);
+  ALLOC(lp->cd2, mp);
+  lp->cg_nf = finish_nblk(m);
+  lp->cg_nd = colpass_nblk_dot(mp, m, SKIPM_F64);
+  ALLOC(lp->cgred, lp->cg_nf + 2 * (int64_t)lp->cg_nd);
   ALLOC(lp->cq, mp);
   ALLOC(lp->cw, mp);
   ALLOC(lp->cx, mp);
@@ -1143,7 +1194,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   launch_fill_f64(lp->sc, 0.0, S_NSLOTS, st);
   launch_fill_i32(lp->is, 0, I_NINTS, st);
   double* zero_vecs[] = {lp->b,  lp->y,  lp->rp, lp->p,  lp->dy, lp->g,  lp->cr,  lp->cz,
-                         lp->cd, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2,
+                         lp->cd, lp->cd2, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2,
                          lp->rt, lp->dyc};
   for (double* z : zero_vecs) launch_fill_f64(z, 0.0, mp, st);
   launch_fill_f64(lp->B, 0.0, lda * w, st);

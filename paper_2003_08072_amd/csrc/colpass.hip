@@ -72,7 +72,18 @@ struct Args {
   double* red;
   const double* sc;
   const int32_t* done;
+  CgFuse cg;
 };
+
+// Sum of v[0..n) over a wave in a fixed order (lane strides, then a butterfly).
+__device__ __forceinline__ double wave_sum_strided(const double* __restrict__ v, int n, int stride,
+                                                   int lane) {
+  double s = 0;
+  for (int p = lane; p < n; p += 64) s += v[(int64_t)p * stride];
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
 
 template <typename TA, typename TC, int G, int R, int MODE, int NT>
 __global__ __launch_bounds__(NT) void k_colpass(Args a) {
@@ -102,17 +113,108 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   const TC* __restrict__ d2 = (const TC*)a.d2;
 
   bool valid[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) valid[r] = (int64_t)(r * G + lg) * V < a.lda;
+  auto load_col = [&](VT* dst, const int64_t col) {
+    const VT* p = (const VT*)(A + col * a.lda);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (valid[r]) dst[r] = p[r * G + lg];
+  };
+  // The first columns are requested before anything else: they depend on
+  // nothing, so their latency overlaps the set-up below.  Two columns per trip
+  // later, the next two prefetched while these are used (up to four columns
+  // per lane group in flight).
+  VT c0v[R], c1v[R], n0v[R], n1v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    c0v[r] = (VT)0;
+    c1v[r] = (VT)0;
+    n0v[r] = (VT)0;
+    n1v[r] = (VT)0;
+  }
+  int64_t col = c0 + slot;
+  if (col < c1) load_col(c0v, col);
+  if (col + NSLOT < c1) load_col(c1v, col + NSLOT);
+
+  const bool cg = a.cg.on != 0;
+  const bool cg_dir = cg && MODE == COL_NORMAL && a.cg.k > 0;
   TC uu[R][V];
+  double dold[R][V];
   TC acc1[R][V], acc2[R][V];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t row0 = (int64_t)(r * G + lg) * V;
-    valid[r] = row0 < a.lda;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      uu[r][e] = (valid[r] && MODE != COL_AXPY) ? u[row0 + e] : (TC)0;
+      if (cg_dir) {  // z_k and d_{k-1}; d_k is formed once beta_k is known
+        uu[r][e] = valid[r] ? (TC)a.cg.z[row0 + e] : (TC)0;
+        dold[r][e] = valid[r] ? a.cg.d_old[row0 + e] : 0.0;
+      } else {
+        uu[r][e] = (valid[r] && MODE != COL_AXPY) ? u[row0 + e] : (TC)0;
+        dold[r][e] = 0;
+      }
       acc1[r][e] = 0;
       acc2[r][e] = 0;
+    }
+  }
+
+  // fused CG bookkeeping at the start of the pass (every block computes the
+  // same sums in the same order, so every block takes the same decision)
+  __shared__ double cgs[2];
+  double cg_beta = 0, cg_alpha = 0;
+  if (cg && (MODE == COL_NORMAL || MODE == COL_DOT)) {
+    const int64_t k = a.cg.k;
+    if (wid == 0) {
+      double s0 = 0, s1 = 0;
+      if (MODE == COL_NORMAL && k > 0) {
+        s0 = wave_sum_strided(a.cg.prz, a.cg.np, 2, lane);
+        s1 = wave_sum_strided(a.cg.prz + 1, a.cg.np, 2, lane);
+      } else if (MODE == COL_DOT) {
+        s0 = wave_sum_strided(a.cg.pdq, a.cg.nf, 1, lane);
+      }
+      if (lane == 0) {
+        cgs[0] = s0;
+        cgs[1] = s1;
+      }
+    }
+    __syncthreads();
+    double* sc = a.cg.sc;
+    int32_t* is = a.cg.is;
+    if (MODE == COL_NORMAL && k > 0) {
+      const double rz = cgs[0], rr = cgs[1];
+      const double crit = is[I_CG_RESID] ? rr : rz;
+      const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
+      cg_beta = rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)];
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_CG_RZ] = rz;
+        sc[S_V_RR] = rr;
+        sc[S_CG_RZH0 + (int)(k & 1)] = rz;
+        is[I_CG_ITERS] = (int32_t)k;
+        if (stop) is[I_CG_DONE] = 1;
+      }
+      if (stop) return;
+    } else if (MODE == COL_DOT) {
+      const double dq = cgs[0];
+      if (!(dq > 0)) {  // breakdown: the operator lost positive definiteness numerically
+        if (blockIdx.x == 0 && threadIdx.x == 0) is[I_CG_DONE] = 1;
+        return;
+      }
+      cg_alpha = sc[S_CG_RZH0 + (int)(k & 1)] / dq;
+    }
+  }
+  double cg_pz = 0, cg_pr = 0;
+  if (cg_dir) {  // d_k = z_k + beta_k d_{k-1}; block 0 stores it
+    const bool store = blockIdx.x == 0 && wid == 0 && grp == 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t row0 = (int64_t)(r * G + lg) * V;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const double dk = (double)uu[r][e] + cg_beta * dold[r][e];
+        if (store && valid[r]) a.cg.d_new[row0 + e] = dk;
+        uu[r][e] = (TC)dk;
+      }
     }
   }
   double mu = 0, sigma = 0;
@@ -141,7 +243,20 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
 #pragma unroll
           for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
       } else if (MODE == COL_DOT) {
-        if (lg == 0) ((TC*)a.t_out)[col] = dot;
+        if (cg) {
+          if (lg == 0) {  // w_j = (Q^{-1} q)_j: update x, r, z at j
+            const double dj = a.cg.d[col];
+            const double rj = a.cg.r[col] - cg_alpha * a.cg.q[col];
+            const double zj = a.cg.zz[col] - cg_alpha * (double)dot;
+            a.cg.x[col] += cg_alpha * dj;
+            a.cg.r[col] = rj;
+            a.cg.zz[col] = zj;
+            cg_pz += rj * zj;
+            cg_pr += rj * rj;
+          }
+        } else if (lg == 0) {
+          ((TC*)a.t_out)[col] = dot;
+        }
       } else if (MODE == COL_NORMAL) {
         const TC coef = d2 ? d2[col] * dot : dot;
         if (a.t_out && lg == 0) ((TC*)a.t_out)[col] = dot;
@@ -181,25 +296,6 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
           }
       }
   };
-  auto load_col = [&](VT* dst, const int64_t col) {
-    const VT* p = (const VT*)(A + col * a.lda);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (valid[r]) dst[r] = p[r * G + lg];
-  };
-  // Two columns per trip, the next two prefetched while these are used, so up
-  // to four columns per lane group are in flight.
-  VT c0v[R], c1v[R], n0v[R], n1v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    c0v[r] = (VT)0;
-    c1v[r] = (VT)0;
-    n0v[r] = (VT)0;
-    n1v[r] = (VT)0;
-  }
-  int64_t col = c0 + slot;
-  if (col < c1) load_col(c0v, col);
-  if (col + NSLOT < c1) load_col(c1v, col + NSLOT);
   while (col < c1) {
     if (col + 2 * NSLOT < c1) load_col(n0v, col + 2 * NSLOT);
     if (col + 3 * NSLOT < c1) load_col(n1v, col + 3 * NSLOT);
@@ -224,7 +320,30 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
       sred[wid][2] = sr2;
     }
   }
-  if (NACC == 0) return;
+  if (NACC == 0) {
+    if (cg && MODE == COL_DOT) {  // block partials of r^T z, r^T r in a fixed order
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        cg_pz += __shfl_xor(cg_pz, off, 64);
+        cg_pr += __shfl_xor(cg_pr, off, 64);
+      }
+      if (lane == 0) {
+        sred[wid][0] = cg_pz;
+        sred[wid][1] = cg_pr;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t0 = 0, t1 = 0;
+        for (int w = 0; w < NW; ++w) {
+          t0 += sred[w][0];
+          t1 += sred[w][1];
+        }
+        a.cg.prz_out[2 * blockIdx.x] = t0;
+        a.cg.prz_out[2 * blockIdx.x + 1] = t1;
+      }
+    }
+    return;
+  }
   // fold the groups of a wave (same rows) together
 #pragma unroll
   for (int off = G; off < 64; off <<= 1) {
@@ -404,6 +523,49 @@ __global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int
   }
 }
 
+// k_finish for the fused CG: out = sum of the partials, and per workgroup the
+// partial sum of dvec_i out_i over its 16 rows, in row order.
+__global__ __launch_bounds__(256) void k_finish_dot(const double* __restrict__ part, int64_t ldp,
+                                                    int nblk, int64_t m,
+                                                    const double* __restrict__ dvec,
+                                                    double* __restrict__ out,
+                                                    double* __restrict__ dq_out,
+                                                    const int32_t* __restrict__ done) {
+  __shared__ double tile[16][17];
+  if (done && *done) return;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + tx;
+  double acc = 0;
+  if (i < m) {
+    int b = ty;
+    for (; b + 7 * 16 < nblk; b += 8 * 16) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + 16 * q) * ldp + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    for (; b < nblk; b += 16) acc += part[(int64_t)b * ldp + i];
+  }
+  tile[ty][tx] = acc;
+  __syncthreads();
+  for (int h = 8; h > 0; h >>= 1) {
+    if (ty < h) tile[ty][tx] += tile[ty + h][tx];
+    __syncthreads();
+  }
+  if (ty == 0) {
+    const double v = tile[0][tx];
+    if (i < m) out[i] = v;
+    tile[1][tx] = i < m ? dvec[i] * v : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int c = 0; c < 16; ++c) s += tile[1][c];
+    dq_out[blockIdx.x] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
@@ -535,6 +697,7 @@ int launch_colpass(ColPass& c, hipStream_t st) {
   a.red = c.red;
   a.sc = c.sc;
   a.done = c.done;
+  a.cg = c.cg;
   if (c.nblk <= 0)
     c.nblk = c.mode == COL_DOT ? colpass_nblk_dot(c.lda, c.n, c.ta)
                                : colpass_nblk(c.lda, c.n, c.ta, c.tc, c.mode);
@@ -577,6 +740,18 @@ void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t 
   else
     sketch_dispatch<float>((const float*)A, lda, s, dscale, is_d2, ptr, perm, sign, w, B, ldb,
                            st);
+}
+
+int finish_nblk(int64_t m) { return (int)((m + 15) / 16); }
+
+int launch_finish_dot(const void* part, int tc, int64_t ldp, int nblk, int64_t m,
+                      const double* dvec, double* out, double* dq_out, const int32_t* done,
+                      hipStream_t st) {
+  if (tc != SKIPM_F64) return -1;
+  const int blocks = finish_nblk(m);
+  hipLaunchKernelGGL(k_finish_dot, dim3(blocks), dim3(256), 0, st, (const double*)part, ldp, nblk,
+                     m, dvec, out, dq_out, done);
+  return blocks;
 }
 
 void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,

@@ -55,6 +55,7 @@ enum Slot : int {
   S_CG_RZ, S_CG_RZ0, S_CG_TOL2, S_CG_PQ,
   S_V_RR, S_V_GG, // v-solve: ||r||^2, ||g||^2
   S_RHO2,         // mixed precision: r^T Q^{-1} r of the FP64 normal-equation residual
+  S_CG_RZH0, S_CG_RZH1,  // fused CG: r_k^T z_k of iteration k in slot S_CG_RZH0 + k % 2
   S_NSLOTS = 40
 };
 
@@ -94,6 +95,36 @@ void launch_bucket_sort(const int32_t* ptr, const int32_t* raw, int32_t* perm, i
                         hipStream_t st);
 
 // dense column passes
+// CG bookkeeping fused into the passes of one preconditioned CG iteration k
+// (M = Q, z = Q^{-1} r):
+//   COL_NORMAL pass:  rz_k, rr_k from the previous COL_DOT pass's partials;
+//                     stop test; beta_k = rz_k / rz_{k-1}; d_k = z_k + beta_k d_{k-1}
+//                     (every block forms d_k for itself, block 0 stores it);
+//                     then q_k = A D^2 A^T d_k as usual
+//   finish:           q_k, and per-block partials of d_k^T q_k
+//   COL_DOT over Q^{-1}: alpha_k = rz_k / d_k^T q_k; w = Q^{-1} q_k; x += alpha d;
+//                     r -= alpha q; z -= alpha w; per-block partials of r^T z, r^T r
+// Every partial is summed in a fixed order, so the iterates are reproducible.
+struct CgFuse {
+  int on = 0;
+  int64_t k = 0;               // CG iteration
+  const double* z = nullptr;   // NORMAL: z_k
+  const double* d_old = nullptr;  // NORMAL: d_{k-1} (d_0 itself when k = 0)
+  double* d_new = nullptr;     // NORMAL: d_k (written by block 0)
+  const double* prz = nullptr; // NORMAL: [np][2] partial (r^T z, r^T r)
+  int np = 0;
+  double* sc = nullptr;
+  int32_t* is = nullptr;
+  const double* q = nullptr;   // DOT: q_k
+  const double* d = nullptr;   // DOT: d_k
+  double* x = nullptr;         // DOT: the CG solution
+  double* r = nullptr;
+  double* zz = nullptr;
+  const double* pdq = nullptr; // DOT: [nf] partial d^T q of the finish
+  int nf = 0;
+  double* prz_out = nullptr;   // DOT: [nblk][2]
+};
+
 struct ColPass {
   int mode;                 // see COL_* below
   const void* A;            // column-major, element type ta
@@ -117,6 +148,7 @@ struct ColPass {
   const double* sc;         // device scalar slots
   const int32_t* done;      // optional early-exit flag
   int nblk;                 // filled by the launcher
+  CgFuse cg;                // fused CG bookkeeping (COL_NORMAL, COL_DOT)
   hipEvent_t ev0 = nullptr;  // COL_NORMAL: optional events stamped with the kernel's
   hipEvent_t ev1 = nullptr;  // start and end (sampled timing)
 };
@@ -133,6 +165,13 @@ void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t 
                          int64_t ldb, hipStream_t st);
 
 // sum of partials along the block axis: out[i] = scale*sum_b part[b][off+i] + beta*add[i]
+// launch_finish plus, per workgroup of 16 rows, the partial sum of dvec_i out_i
+// (dq_out[blockIdx]); returns the number of workgroups
+int launch_finish_dot(const void* part, int tc, int64_t ldp, int nblk, int64_t m,
+                      const double* dvec, double* out, double* dq_out, const int32_t* done,
+                      hipStream_t st);
+int finish_nblk(int64_t m);
+int colpass_nblk_dot(int64_t lda, int64_t n, int ta);
 void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,
                    double scale, const double* add, double beta, double* out,
                    const int32_t* done, hipStream_t st);
@@ -206,6 +245,10 @@ void launch_dot(const double* a, const double* b, int64_t m, double* sc, int slo
 void launch_cg_init(int64_t m, const double* p, const double* z, double* r, double* zz,
                     double* d, float* df, double* x, double* tw, int64_t nw, double* sc,
                     int32_t* is, double tol, int max_it, int resid_test, hipStream_t st);
+// fused CG: close a run stopped by its iteration cap after iteration k - 1
+// (rz_k, rr_k from the partials, iteration count k, done flag)
+void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* is,
+                     hipStream_t st);
 void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
                       double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
                       double* sc, int32_t* is, hipStream_t st);

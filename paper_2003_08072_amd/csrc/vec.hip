@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(int64_t m, const double*
   if (threadIdx.x == 0) {
     sc[S_CG_RZ] = rz;
     sc[S_CG_RZ0] = rz;
+    sc[S_CG_RZH0] = rz;
     const double base = resid_test ? rr : rz;
     sc[S_CG_TOL2] = tol > 0 ? tol * tol * base : -1.0;
     sc[S_V_RR] = rr;
@@ -197,6 +198,32 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(int64_t m, const doubl
     is[I_CG_ITERS] = it;
     const double crit = is[I_CG_RESID] ? rr : rz_new;
     if (it >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz_new > 0)) is[I_CG_DONE] = 1;
+  }
+}
+
+// Fused CG stopped by its iteration cap after iteration k - 1: the bookkeeping
+// the next iteration's first pass would have done (rz_k, rr_k, count, done).
+__global__ __launch_bounds__(64) void k_cg_close(const double* __restrict__ prz, int np,
+                                                 int64_t k, double* __restrict__ sc,
+                                                 int32_t* __restrict__ is) {
+  if (is[I_CG_DONE]) return;
+  const int lane = threadIdx.x;
+  double s0 = 0, s1 = 0;
+  for (int p = lane; p < np; p += 64) {
+    s0 += prz[2 * p];
+    s1 += prz[2 * p + 1];
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+  }
+  if (lane == 0) {
+    sc[S_CG_RZ] = s0;
+    sc[S_V_RR] = s1;
+    sc[S_CG_RZH0 + (int)(k & 1)] = s0;
+    is[I_CG_ITERS] = (int32_t)k;
+    is[I_CG_DONE] = 1;
   }
 }
 
@@ -516,6 +543,11 @@ void launch_cg_init(int64_t m, const double* p, const double* z, double* r, doub
                     double tol, int max_it, int resid_test, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kCgThreads), 0, st, m, p, z, r, zz, d, df, x, tw, nw,
                      sc, is, tol, max_it, resid_test);
+}
+
+void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* is,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_close, dim3(1), dim3(64), 0, st, prz, np, k, sc, is);
 }
 
 void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
