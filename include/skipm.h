@@ -58,6 +58,9 @@ extern "C" {
 #define SKIPM_F32 1
 
 /* arithmetic of the CG solve */
+#define SKIPM_INNER_CG         0  /* preconditioned CG (Alg. 1 step 3) */
+#define SKIPM_INNER_SD         1  /* preconditioned steepest descent (App. B, Alg. 4) */
+#define SKIPM_INNER_RICHARDSON 2  /* preconditioned Richardson iteration (App. A, Alg. 3) */
 #define SKIPM_PREC_FP64  0   /* everything FP64 */
 #define SKIPM_PREC_MIXED 1   /* CG products read an FP32 copy of A (FP64 accumulation) inside
                                 an iterative refinement on FP64 residuals; residuals, v,
@@ -99,6 +102,8 @@ typedef struct {
   int32_t resketch;  /* 1: fresh W every IPM iteration (salt = iteration), 0: one W  [1] */
   int32_t precision; /* SKIPM_PREC_FP64 or SKIPM_PREC_MIXED  [FP64]                    */
   uint64_t seed;     /* sketch seed  [0]                                               */
+  int32_t inner;     /* solver of Alg. 2 step (c): SKIPM_INNER_CG (Alg. 1), _SD (steepest
+                        descent, App. B Alg. 4) or _RICHARDSON (App. A Alg. 3)  [CG]   */
 } skipm_params;
 
 /* Result of lp_solve (host struct). */

@@ -186,16 +186,73 @@ class PCGResult:
     f_norms: list          # ||f^(j)||, j = 0..iters
 
 
+def sketch_preconditioner(AD, W):
+    """Alg. 1 steps 1-2: B = A D W, its thin SVD, and Q^{-1/2} = U diag(1/sv) U^T."""
+    B = np.asarray((W.T @ AD.T).T) if sp.issparse(W) else AD @ W
+    U, sv, Vh = np.linalg.svd(B, full_matrices=False)
+    if sv.size < AD.shape[0] or sv[-1] <= 0 or not np.all(np.isfinite(sv)):
+        raise np.linalg.LinAlgError("rank(A D W) < m")
+    return (U / sv) @ U.T, U, sv, Vh
+
+
+def sketch_richardson(AD, p, W, t=None, tol=None, max_it=1000):
+    """Alg. 3 (App. A): z^j = z^{j-1} + Q^{-1/2}(p - A D^2 A^T Q^{-1/2} z^{j-1})
+    from z^0 = 0, for exactly t iterations, or until ||f^(j)|| <= tol ||f^(0)||
+    with f^(j) = Q^{-1/2}(A D^2 A^T Q^{-1/2} z^j - p)."""
+    Qmh, U, sv, Vh = sketch_preconditioner(AD, W)
+
+    def residual(z):
+        return Qmh @ (AD @ (AD.T @ (Qmh @ z))) - Qmh @ p
+
+    z = np.zeros_like(p)
+    f = residual(z)
+    f_norms = [float(np.linalg.norm(f))]
+    limit = t if t is not None else max_it
+    it = 0
+    while it < limit:
+        if t is None and f_norms[-1] <= tol * f_norms[0]:
+            break
+        z = z + Qmh @ (p - AD @ (AD.T @ (Qmh @ z)))
+        f = residual(z)
+        it += 1
+        f_norms.append(float(np.linalg.norm(f)))
+    return PCGResult(z, Qmh @ z, Qmh, U, sv, Vh, it, f_norms)
+
+
+def sketch_sd(AD, p, W, t=None, tol=None, max_it=1000):
+    """Alg. 4 (App. B): steepest descent on Q^{-1/2} A D^2 A^T Q^{-1/2} z =
+    Q^{-1/2} p from z^0 = 0: alpha_j = f^T f / f^T M f, z^{j+1} = z^j - alpha_j f^(j),
+    M = Q^{-1/2} A D^2 A^T Q^{-1/2}; stops as sketch_richardson."""
+    Qmh, U, sv, Vh = sketch_preconditioner(AD, W)
+
+    def op(u):
+        return Qmh @ (AD @ (AD.T @ (Qmh @ u)))
+
+    z = np.zeros_like(p)
+    f = op(z) - Qmh @ p
+    f_norms = [float(np.linalg.norm(f))]
+    limit = t if t is not None else max_it
+    it = 0
+    while it < limit:
+        if t is None and f_norms[-1] <= tol * f_norms[0]:
+            break
+        ff = float(f @ f)
+        if ff == 0.0:
+            break
+        alpha = ff / float(f @ op(f))
+        z = z - alpha * f
+        f = op(z) - Qmh @ p
+        it += 1
+        f_norms.append(float(np.linalg.norm(f)))
+    return PCGResult(z, Qmh @ z, Qmh, U, sv, Vh, it, f_norms)
+
+
 def sketch_pcg(AD, p, W, t=None, tol=None, max_it=1000):
     """Alg. 1.  Step 1: B = A D W and its thin SVD.  Step 2: Q^{-1/2} =
     U diag(1/sv) U^T.  Step 3: standard CG from z = 0 on
     Q^{-1/2} A D^2 A^T Q^{-1/2} z = Q^{-1/2} p, for exactly t iterations, or until
     ||f^(j)|| <= tol ||f^(0)|| (at most max_it iterations)."""
-    B = np.asarray((W.T @ AD.T).T) if sp.issparse(W) else AD @ W
-    U, sv, Vh = np.linalg.svd(B, full_matrices=False)
-    if sv.size < AD.shape[0] or sv[-1] <= 0 or not np.all(np.isfinite(sv)):
-        raise np.linalg.LinAlgError("rank(A D W) < m")
-    Qmh = (U / sv) @ U.T
+    Qmh, U, sv, Vh = sketch_preconditioner(AD, W)
 
     def op(u):
         h = Qmh @ u
@@ -266,14 +323,19 @@ def exact_direction(A, b, c, x, y, s, sigma):
     return Direction(dx, dy, ds, np.zeros_like(x), p, rp, rd, mu)
 
 
-def sketch_direction(A, b, c, x, y, s, sigma, W, tol_cg=1e-5, max_cg=1000, t=None):
-    """Alg. 2 steps (b)-(d) with W from step (a)."""
+INNER_SOLVERS = {"cg": sketch_pcg, "sd": sketch_sd, "richardson": sketch_richardson}
+
+
+def sketch_direction(A, b, c, x, y, s, sigma, W, tol_cg=1e-5, max_cg=1000, t=None,
+                     inner="cg"):
+    """Alg. 2 steps (b)-(d) with W from step (a); step (c)'s solver is CG
+    (Alg. 1), steepest descent (Alg. 4) or Richardson (Alg. 3)."""
     rp, rd = residuals(A, b, c, x, y, s)
     mu = duality_measure(x, s)
     d2 = x / s
     p = normal_rhs(A, b, c, x, y, s, sigma, mu)
     AD = scaled_matrix(A, np.sqrt(d2))
-    res = sketch_pcg(AD, p, W, t=t, tol=tol_cg, max_it=max_cg)
+    res = INNER_SOLVERS[inner](AD, p, W, t=t, tol=tol_cg, max_it=max_cg)
     dy = res.dy
     g = _mv(A, d2 * _rmv(A, dy)) - p
     v = correction_vector(x, s, W, res.U, res.sv, res.Vh, g)
@@ -298,6 +360,7 @@ class IPMParams:
     tol_cg: float = 1e-5
     max_cg: int = 1000
     cg_t: int | None = None     # fixed CG iteration count instead of tol_cg
+    inner: str = "cg"           # "cg" (Alg. 1) | "sd" (Alg. 4) | "richardson" (Alg. 3)
 
 
 @dataclasses.dataclass
@@ -359,7 +422,7 @@ def ipm(A, b, c, params: IPMParams | None = None, x0=None, y0=None, s0=None):
             else:
                 W = sketch_matrix(prm.seed, k if prm.resketch else 0, prm.s_nnz, n, w)
                 dirn = sketch_direction(A, b, c, x, y, s, prm.sigma, W, prm.tol_cg,
-                                        prm.max_cg, prm.cg_t)
+                                        prm.max_cg, prm.cg_t, prm.inner)
         except np.linalg.LinAlgError:
             status = "numerical"
             break

@@ -123,6 +123,8 @@ int validate_params(const skipm_params& p, int64_t m, int64_t n) {
   if (p.max_cg < 1 || p.max_outer < 0) return set_error("bad iteration caps"), SKIPM_EINVAL;
   if (p.precision != SKIPM_PREC_FP64 && p.precision != SKIPM_PREC_MIXED)
     return set_error("unknown precision"), SKIPM_EINVAL;
+  if (p.inner != SKIPM_INNER_CG && p.inner != SKIPM_INNER_SD && p.inner != SKIPM_INNER_RICHARDSON)
+    return set_error("unknown inner solver"), SKIPM_EINVAL;
   if (n * p.s > INT32_MAX) return set_error("n*s exceeds int32 item indices"), SKIPM_EINVAL;
   return SKIPM_OK;
 }
@@ -321,7 +323,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
     kt_end(lp, q, st);
     SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
     launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
-                     nullptr, 0, lp->sc, lp->is, st);
+                     nullptr, 0, lp->sc, lp->is, lp->prm.inner, st);
     SK_CHECK_HIP(hipGetLastError());
     return SKIPM_OK;
   }
@@ -348,6 +350,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   double* prz = lp->cgred + lp->cg_nf;
   cp.u = lp->cd;  // d_0 (written by the CG init) for iteration 0
   cp.cg.on = 1;
+  cp.cg.inner = lp->prm.inner;
   cp.cg.k = iter;
   cp.cg.z = lp->cz;
   cp.cg.d_old = dprev;
@@ -372,6 +375,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   pq.done = done;
   pq.nblk = lp->cg_nd;
   pq.cg.on = 1;
+  pq.cg.inner = lp->prm.inner;
   pq.cg.k = iter;
   pq.cg.sc = lp->sc;
   pq.cg.is = lp->is;
@@ -845,6 +849,7 @@ int skipm_params_default(skipm_params* out) {
   out->resketch = 1;
   out->precision = SKIPM_PREC_FP64;
   out->seed = 0;
+  out->inner = SKIPM_INNER_CG;
   return SKIPM_OK;
 }
 

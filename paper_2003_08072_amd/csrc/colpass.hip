@@ -185,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
       const double rz = cgs[0], rr = cgs[1];
       const double crit = is[I_CG_RESID] ? rr : rz;
       const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
-      cg_beta = rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)];
+      cg_beta = a.cg.inner == SKIPM_INNER_CG ? rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)] : 0.0;
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc[S_CG_RZ] = rz;
         sc[S_V_RR] = rr;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
         if (blockIdx.x == 0 && threadIdx.x == 0) is[I_CG_DONE] = 1;
         return;
       }
-      cg_alpha = sc[S_CG_RZH0 + (int)(k & 1)] / dq;
+      cg_alpha = a.cg.inner == SKIPM_INNER_RICHARDSON ? 1.0 : sc[S_CG_RZH0 + (int)(k & 1)] / dq;
     }
   }
   double cg_pz = 0, cg_pr = 0;

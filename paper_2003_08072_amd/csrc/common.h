@@ -107,6 +107,8 @@ void launch_bucket_sort(const int32_t* ptr, const int32_t* raw, int32_t* perm, i
 // Every partial is summed in a fixed order, so the iterates are reproducible.
 struct CgFuse {
   int on = 0;
+  int inner = SKIPM_INNER_CG;  // CG: beta_k = rz_k / rz_{k-1}; SD: beta = 0;
+                               // Richardson: beta = 0 and alpha = 1
   int64_t k = 0;               // CG iteration
   const double* z = nullptr;   // NORMAL: z_k
   const double* d_old = nullptr;  // NORMAL: d_{k-1} (d_0 itself when k = 0)
@@ -251,7 +253,7 @@ void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* 
                      hipStream_t st);
 void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
                       double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
-                      double* sc, int32_t* is, hipStream_t st);
+                      double* sc, int32_t* is, int inner, hipStream_t st);
 
 // n-vector kernels of the IPM iteration
 void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,

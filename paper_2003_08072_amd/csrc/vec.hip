@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(int64_t m, const doubl
                                                           double* __restrict__ tw,
                                                           const double* __restrict__ tq,
                                                           int64_t nw, double* __restrict__ sc,
-                                                          int32_t* __restrict__ is) {
+                                                          int32_t* __restrict__ is, int inner) {
   __shared__ double buf[kCgThreads / 64];
   if (is[I_CG_DONE]) return;
   double pq = 0;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(int64_t m, const doubl
     if (threadIdx.x == 0) is[I_CG_DONE] = 1;
     return;
   }
-  const double alpha = rz / pq;
+  const double alpha = inner == SKIPM_INNER_RICHARDSON ? 1.0 : rz / pq;
   double rz_new = 0, rr = 0;
   for (int64_t i = threadIdx.x; i < m; i += kCgThreads) {
     const double di = d[i];
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(int64_t m, const doubl
   for (int64_t i = threadIdx.x; i < nw; i += kCgThreads) tw[i] += alpha * tq[i];
   rz_new = block_sum<kCgThreads>(rz_new, buf);
   rr = block_sum<kCgThreads>(rr, buf);
-  const double beta = rz_new / rz;
+  const double beta = inner == SKIPM_INNER_CG ? rz_new / rz : 0.0;
   for (int64_t i = threadIdx.x; i < m; i += kCgThreads) {
     const double di = z[i] + beta * d[i];
     d[i] = di;
@@ -552,9 +552,9 @@ void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* 
 
 void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
                       double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
-                      double* sc, int32_t* is, hipStream_t st) {
+                      double* sc, int32_t* is, int inner, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_update, dim3(1), dim3(kCgThreads), 0, st, m, q, wq, r, z, d, df, x, tw,
-                     tq, nw, sc, is);
+                     tq, nw, sc, is, inner);
 }
 
 void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,

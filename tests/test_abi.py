@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes follow the C layout of the header structs on x86-64
-    assert ctypes.sizeof(sk.Params) == 6 * 8 + 6 * 4 + 8
+    assert ctypes.sizeof(sk.Params) == 6 * 8 + 6 * 4 + 8 + 8
     assert ctypes.sizeof(sk.Problem) == 3 * 8 + 2 * 4 + 8 + 8 + 4 * 8
     assert ctypes.sizeof(sk.Result) == 4 * 4 + 6 * 8
     assert ctypes.sizeof(sk.StepInfo) == 11 * 8 + 4 * 4
@@ -80,7 +80,7 @@ def _c_layouts():
         pytest.skip("gcc or HIP headers missing")
     fields = {
         "skipm_problem": ["m", "nnz", "format", "a_vals", "lda", "a_colidx", "c"],
-        "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed"],
+        "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed", "inner"],
         "skipm_result": ["status", "cg_max", "obj_p", "mu"],
         "skipm_step_info": ["mu", "v_resid", "cg_iters", "status"],
         "skipm_pcg_info": ["iters", "f0_norm", "f_norm"],

@@ -134,6 +134,52 @@ def test_pcg_fixed_iterations_match_alg1(torch, sk, cg_case, t):
     assert info.f0_norm == pytest.approx(ref.f_norms[0], rel=1e-10)
 
 
+@pytest.mark.parametrize("inner,t,fmt", [("sd", 1, "dense"), ("sd", 6, "dense"),
+                                         ("richardson", 1, "dense"), ("richardson", 6, "dense"),
+                                         ("sd", 6, "csr"), ("richardson", 6, "csr")])
+def test_inner_solvers_fixed_iterations_match_oracle(torch, sk, cg_case, inner, t, fmt):
+    """Steepest descent (App. B, Alg. 4) and Richardson (App. A, Alg. 3) in place
+    of CG, on a sketch wide enough for Richardson to contract (w = n, s = 8)."""
+    import scipy.sparse as ssp
+    lp, x, s = cg_case
+    say(f"inner solver {inner} t={t} {fmt}")
+    code = {"sd": sk.SKIPM_INNER_SD, "richardson": sk.SKIPM_INNER_RICHARDSON}[inner]
+    d2 = x / s
+    p = np.random.default_rng(40 + t).standard_normal(lp.m)
+    A = ssp.csr_matrix(lp.A) if fmt == "csr" else lp.A
+    with sk.LP(A, lp.b, lp.c, seed=33, s=8, w=lp.n, inner=code) as h:
+        dy, info = h.pcg(d2, p, 2, tol=0.0, max_it=t)
+        dy = dy.cpu().numpy()
+    assert info.iters == t
+    W = sketch_matrix(33, 2, 8, lp.n, lp.n)
+    solver = O.sketch_sd if inner == "sd" else O.sketch_richardson
+    ref = solver(lp.A * np.sqrt(d2), p, W, t=t)
+    assert np.linalg.norm(dy - ref.dy) <= 1e-9 * np.linalg.norm(ref.dy)
+    assert info.f_norm == pytest.approx(ref.f_norms[-1], rel=1e-6)
+
+
+@pytest.mark.parametrize("inner", ["sd", "richardson"])
+def test_solve_with_inner_solver(torch, sk, inner):
+    lp = dense_planted(30, 1200, rng=np.random.default_rng(12), eps_gap=1e-8)
+    say(f"solve with inner solver {inner} (w = n, s = 8)")
+    code = {"sd": sk.SKIPM_INNER_SD, "richardson": sk.SKIPM_INNER_RICHARDSON}[inner]
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.n, s=8, seed=5, eps_gap=1e-8, inner=code,
+               max_cg=2000) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-8)
+
+
+def test_solve_with_one_fixed_sketch(torch, sk):
+    """resketch = 0: one W (salt 0) for every IPM iteration, its bucket order
+    computed once."""
+    lp = config_lp(0)
+    say("solve config 0 with one fixed sketch (resketch = 0), s = 2")
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, s=2, seed=lp.seed, eps_gap=lp.eps_gap,
+               resketch=0) as h:
+        res = h.solve()
+    check_solution(lp, res, lp.eps_gap)
+
+
 @pytest.mark.parametrize("iters", [2, 10])
 def test_pcg_tight_tolerance_matches_cholesky(torch, sk, cg_case, iters):
     lp, _, _ = cg_case

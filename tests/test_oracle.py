@@ -348,6 +348,120 @@ def test_lemma4_v_bound_diagnostic(small_lp):
 
 
 # ---------------------------------------------------------------------------
+# App. A (Richardson, Alg. 3) and App. B (steepest descent, Alg. 4)
+# ---------------------------------------------------------------------------
+
+def _good_sketch_system(lp, seed=3):
+    """A mid-IPM A D and a sketch wide and dense enough for ||I - M|| < 1."""
+    x, y, s, _ = _mid_iterate(lp, 3)
+    AD = _scaled(lp, x, s)
+    W = sketch_matrix(seed, 0, 8, lp.n, lp.n)
+    p = np.random.default_rng(seed).standard_normal(lp.m)
+    return AD, W, p
+
+
+def test_richardson_residual_recursion_closed_form(small_lp):
+    """Lemma (App. A): f^(j) = (I - M)^j f^(0), M = Q^{-1/2} A D^2 A^T Q^{-1/2};
+    the powers are taken from M's eigendecomposition, not from the iteration."""
+    AD, W, p = _good_sketch_system(small_lp)
+    res = O.sketch_richardson(AD, p, W, t=6)
+    M = res.Qmh @ AD @ AD.T @ res.Qmh
+    lam, V = np.linalg.eigh((M + M.T) / 2)
+    f0 = -(res.Qmh @ p)
+    for j in range(7):
+        fj = V @ ((1.0 - lam) ** j * (V.T @ f0))
+        assert abs(res.f_norms[j] - np.linalg.norm(fj)) <= 1e-10 * np.linalg.norm(f0)
+
+
+def test_richardson_contracts_by_zeta(small_lp):
+    """Lemma (App. A): ||f^(j)|| <= zeta ||f^(j-1)|| with zeta = ||I - M||_2 < 1."""
+    AD, W, p = _good_sketch_system(small_lp, seed=5)
+    res = O.sketch_richardson(AD, p, W, t=8)
+    sv = np.linalg.svd(res.Qmh @ AD, compute_uv=False)
+    zeta = max(abs(1 - sv[0] ** 2), abs(1 - sv[-1] ** 2))
+    assert zeta < 1
+    f = res.f_norms
+    for j in range(1, len(f)):
+        assert f[j] <= zeta * f[j - 1] * (1 + 1e-9)
+
+
+def test_steepest_descent_line_search_and_orthogonality(small_lp):
+    """Alg. 4: alpha_j is the exact minimiser of the quadratic along -f^(j), so
+    consecutive residuals are orthogonal (App. B)."""
+    AD, W, p = _good_sketch_system(small_lp, seed=7)
+    Qmh, _, _, _ = O.sketch_preconditioner(AD, W)
+    M = Qmh @ AD @ AD.T @ Qmh
+    rhs = Qmh @ p
+
+    def phi(z):
+        return 0.5 * z @ M @ z - rhs @ z
+
+    prev = None
+    for t in range(1, 6):
+        z = O.sketch_sd(AD, p, W, t=t).z
+        f = M @ z - rhs
+        if prev is not None:
+            zp, fp = prev
+            assert abs(f @ fp) <= 1e-9 * np.linalg.norm(f) * np.linalg.norm(fp) + 1e-14
+            a = (fp @ fp) / (fp @ M @ fp)
+            for scale in (0.9, 1.1):
+                assert phi(zp - a * fp) < phi(zp - scale * a * fp)
+        prev = (z, f)
+
+
+def test_richardson_and_sd_converge_to_cholesky_solution(small_lp):
+    AD, W, p = _good_sketch_system(small_lp, seed=9)
+    dy = np.linalg.solve(AD @ AD.T, p)
+    for solver in (O.sketch_richardson, O.sketch_sd):
+        res = solver(AD, p, W, tol=1e-13, max_it=500)
+        assert np.linalg.norm(res.dy - dy) <= 1e-9 * np.linalg.norm(dy), solver.__name__
+
+
+def test_exact_preconditioner_one_step_for_every_inner_solver(small_lp):
+    """With a signed-permutation W, Q = A D^2 A^T and M = I: Richardson and
+    steepest descent (alpha = 1) both finish in one iteration."""
+    lp = small_lp
+    x, y, s, _ = _mid_iterate(lp)
+    AD = _scaled(lp, x, s)
+    rng = np.random.default_rng(11)
+    W = sp.csr_matrix((rng.choice([-1.0, 1.0], lp.n), (np.arange(lp.n), rng.permutation(lp.n))),
+                      shape=(lp.n, lp.n))
+    p = rng.standard_normal(lp.m)
+    dy = np.linalg.solve(AD @ AD.T, p)
+    for solver in (O.sketch_richardson, O.sketch_sd):
+        res = solver(AD, p, W, tol=1e-10, max_it=50)
+        assert res.iters == 1
+        assert np.linalg.norm(res.dy - dy) <= 1e-9 * np.linalg.norm(dy)
+
+
+def test_ipm_with_each_inner_solver_reaches_the_planted_optimum():
+    lp = dense_planted(12, 200, rng=np.random.default_rng(21), eps_gap=1e-8)
+    for inner in ("sd", "richardson"):
+        r = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="sketch", eps_gap=1e-8, w=lp.n,
+                                                  s_nnz=8, seed=4, inner=inner, max_cg=2000))
+        assert r.status == "optimal", inner
+        assert abs(r.obj_p - lp.opt) <= 2e-8 * max(1.0, abs(lp.opt)), inner
+
+
+def test_planted_mistake_in_richardson_sign_breaks_recursion(small_lp):
+    """The closed form of the Richardson residual catches a step whose
+    correction enters with the wrong sign (z - Q^{-1/2}(p - ...))."""
+    AD, W, p = _good_sketch_system(small_lp)
+    good = O.sketch_richardson(AD, p, W, t=3)
+    Qmh = good.Qmh
+    M = Qmh @ AD @ AD.T @ Qmh
+    lam, V = np.linalg.eigh((M + M.T) / 2)
+    f0 = -(Qmh @ p)
+    f3 = np.linalg.norm(V @ ((1.0 - lam) ** 3 * (V.T @ f0)))
+    z = np.zeros_like(p)
+    for _ in range(3):
+        z = z - Qmh @ (p - AD @ (AD.T @ (Qmh @ z)))
+    bad_f3 = np.linalg.norm(M @ z - Qmh @ p)
+    assert abs(good.f_norms[3] - f3) <= 1e-10 * np.linalg.norm(f0)
+    assert abs(bad_f3 - f3) > 1e-3 * np.linalg.norm(f0)
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes are caught
 # ---------------------------------------------------------------------------
 
