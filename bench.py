@@ -53,6 +53,11 @@ def parse():
                     help="non-zeros per row of the sketch for the headline (1: CountSketch)")
     ap.add_argument("--s-extra", default="2",
                     help="comma-separated extra values of s measured beside the headline")
+    ap.add_argument("--inner", default="cg", choices=["cg", "sd", "richardson"],
+                    help="solver of Alg. 2 step (c): CG (Alg. 1), steepest descent (Alg. 4), "
+                         "Richardson (Alg. 3)")
+    ap.add_argument("--resketch", type=int, default=1, choices=[0, 1],
+                    help="1: fresh W every IPM iteration; 0: one W for the whole solve")
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=25.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
@@ -116,8 +121,11 @@ def percentile(xs, q):
 
 def run_mode(sk, torch, lp, precision, s_nnz, args):
     prec = sk.SKIPM_PREC_MIXED if precision == "mixed" else sk.SKIPM_PREC_FP64
+    inner = {"cg": sk.SKIPM_INNER_CG, "sd": sk.SKIPM_INNER_SD,
+             "richardson": sk.SKIPM_INNER_RICHARDSON}[args.inner]
     h = sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=s_nnz,
-              eps_gap=lp.eps_gap, precision=prec, max_outer=1000)
+              eps_gap=lp.eps_gap, precision=prec, max_outer=1000, inner=inner,
+              resketch=args.resketch, max_cg=5000 if args.inner != "cg" else 500)
     stream = torch.cuda.current_stream()
     res = None
     for _ in range(args.warmup):
@@ -410,7 +418,8 @@ def main():
                                f"{'FP64' if lp.a_dtype == 'f64' else 'FP32'} planted LP, "
                                f"sketch w={lp.w}, s={args.s}, rel. gap {lp.eps_gap:g}",
                    "m": lp.m, "n": lp.n, "w": lp.w, "s": args.s,
-                   "precision": head["precision"]},
+                   "precision": head["precision"], "inner": args.inner,
+                   "resketch": args.resketch},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],
         "matvec_gbs": head["matvec_gbs"],
