@@ -82,6 +82,7 @@ struct skipm_lp_s {
   double bnorm = 0, cnorm = 0;
   // fused CG (dense A): second direction buffer and the partial sums
   double* cd2 = nullptr;
+  double* Ct = nullptr;  // mp x mp scratch of the triangular inverse
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
   std::vector<void*> allocs;
@@ -250,7 +251,7 @@ int factor(skipm_lp_s* lp, double shift, hipStream_t st) {
   if (shift > 0) launch_shift_diag(lp->G, lp->mp, lp->m, shift, st);
   launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
   launch_fill_f64(lp->Xb, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
-  launch_spd_inverse(lp->G, lp->Xb, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  launch_spd_inverse(lp->G, lp->Xb, lp->Ct, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -314,16 +315,41 @@ void kt_harvest(skipm_lp_s* lp, int executed) {
   lp->kt_iter.clear();
 }
 
+int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, const double* pdq,
+                  double* prz, const int32_t* done, hipStream_t st);
+
 // One CG iteration on A D^2 A^T (the chunk loop checks the done flag).
 int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   const int32_t* done = lp->is + I_CG_DONE;
+  double* dk = (iter & 1) ? lp->cd2 : lp->cd;
+  const double* dprev = (iter & 1) ? lp->cd : lp->cd2;
+  double* pdq = lp->cgred;
+  double* prz = lp->cgred + lp->cg_nf;
   if (lp->fmt == SKIPM_CSR) {
+    // four launches per iteration: the column pass opens the iteration (stop
+    // test, beta, d_k), the row pass and fold give q and d^T q partials, the
+    // Q^{-1} pass closes it
+    CgFuse cg{};
+    cg.on = 1;
+    cg.inner = lp->prm.inner;
+    cg.k = iter;
+    cg.z = lp->cz;
+    cg.d_old = dprev;
+    cg.d_new = dk;
+    cg.prz = prz;
+    cg.np = lp->cg_nd;
+    cg.sc = lp->sc;
+    cg.is = lp->is;
+    const SparseA& A = lp->sp;
     const int q = kt_begin(lp, iter, st);
-    SK_TRY(normal_sparse(lp, lp->cd, 1.0, nullptr, 0.0, lp->cq, done, st));
+    if (launch_csc_dot(A, COL_NORMAL, lp->cd, nullptr, nullptr, nullptr, nullptr, lp->d2, lp->cf1,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, lp->sc, done, lp->nblk_csc,
+                       st, &cg) != 0)
+      return set_error("m too large for the sparse path"), SKIPM_EINVAL;
+    launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, done, st);
+    launch_csr_fold(A, lp->segsum, 0, 1.0, nullptr, 0.0, lp->cq, done, st, dk, pdq);
     kt_end(lp, q, st);
-    SK_TRY(qinv_apply(lp, lp->cq, lp->cw, done, st));
-    launch_cg_update(lp->m, lp->cq, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr,
-                     nullptr, 0, lp->sc, lp->is, lp->prm.inner, st);
+    SK_TRY(cg_close_pass(lp, xsol, iter, dk, pdq, prz, done, st));
     SK_CHECK_HIP(hipGetLastError());
     return SKIPM_OK;
   }
@@ -344,10 +370,6 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   // Three launches per iteration: the product pass opens the iteration (stop
   // test, beta, d_k), the finish adds d^T q partials, the Q^{-1} pass closes it
   // (alpha, x, r, z and r^T z partials).  d alternates between two buffers.
-  double* dk = (iter & 1) ? lp->cd2 : lp->cd;
-  const double* dprev = (iter & 1) ? lp->cd : lp->cd2;
-  double* pdq = lp->cgred;
-  double* prz = lp->cgred + lp->cg_nf;
   cp.u = lp->cd;  // d_0 (written by the CG init) for iteration 0
   cp.cg.on = 1;
   cp.cg.inner = lp->prm.inner;
@@ -363,6 +385,15 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   if (launch_finish_dot(lp->part, cp.tc, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
       lp->cg_nf)
     return set_error("fused CG: finish shape mismatch"), SKIPM_EINVAL;
+  SK_TRY(cg_close_pass(lp, xsol, iter, dk, pdq, prz, done, st));
+  SK_CHECK_HIP(hipGetLastError());
+  return SKIPM_OK;
+}
+
+// The Q^{-1} pass that closes CG iteration `iter`: alpha, w = Q^{-1} q, the x,
+// r, z updates and the r^T z, r^T r partials.
+int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, const double* pdq,
+                  double* prz, const int32_t* done, hipStream_t st) {
   ColPass pq{};
   pq.mode = COL_DOT;
   pq.A = lp->G;
@@ -404,7 +435,7 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   for (;;) {
     for (int q = 0; q < chunk && enq < max_it; ++q, ++enq)
       SK_TRY(pcg_iteration(lp, xsol, enq, st));
-    if (lp->fmt != SKIPM_CSR && enq >= max_it)  // fused CG: close the capped run
+    if (enq >= max_it)  // close the capped run (the next iteration's opening pass would)
       launch_cg_close(lp->cgred + lp->cg_nf, lp->cg_nd, enq, lp->sc, lp->is, st);
     SK_TRY(sync_read(lp, st));
     const int32_t* hi = host_ints(lp);
@@ -647,7 +678,7 @@ int true_residual(skipm_lp_s* lp, hipStream_t st) {
 int spd_inverse_checked(skipm_lp_s* lp, double* Gm, double* Xm, hipStream_t st) {
   launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
   launch_fill_f64(Xm, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
-  launch_spd_inverse(Gm, Xm, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  launch_spd_inverse(Gm, Xm, lp->Ct, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -895,7 +926,8 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   }
   for (int i = 0; i < 8; ++i) add(8 * n);    // c x s d2 r_d dx ds v
   for (int i = 0; i < 18; ++i) add(8 * mp);  // m-vectors
-  add(8 * (finish_nblk(m) + 2 * (int64_t)colpass_nblk_dot(mp, m, SKIPM_F64)));  // CG partials
+  add(8 * ((csr ? csr_fold_nblk(m) : finish_nblk(m)) +
+           2 * (int64_t)colpass_nblk_dot(mp, m, SKIPM_F64)));  // CG partials
   add(8 * w);
   add(8 * w);
   add(8 * lda * w);  // B
@@ -907,6 +939,7 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   }
   add(8 * mp * mp);
   add(8 * mp * mp);
+  add(8 * mp * mp);  // scratch of the triangular inverse
   add(4 * n * s);
   add(n * s);
   add(4 * n * s);
@@ -1139,7 +1172,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cz, mp);
   ALLOC(lp->cd, mp);
   ALLOC(lp->cd2, mp);
-  lp->cg_nf = finish_nblk(m);
+  lp->cg_nf = csr ? csr_fold_nblk(m) : finish_nblk(m);
   lp->cg_nd = colpass_nblk_dot(mp, m, SKIPM_F64);
   ALLOC(lp->cgred, lp->cg_nf + 2 * (int64_t)lp->cg_nd);
   ALLOC(lp->cq, mp);
@@ -1164,6 +1197,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->Gpart, (int64_t)lp->ksplit * mp * mp);
   ALLOC(lp->G, mp * mp);
   ALLOC(lp->Xb, mp * mp);
+  ALLOC(lp->Ct, mp * mp);
   ALLOC(lp->bucket, n * lp->s);
   ALLOC(lp->sign, n * lp->s);
   ALLOC(lp->perm, n * lp->s);

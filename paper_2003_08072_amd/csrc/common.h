@@ -194,7 +194,7 @@ struct SparseA {
   const int32_t* seg_start = nullptr;
   const int32_t* seg_end = nullptr;
 };
-constexpr int kSeg = 2048;
+constexpr int kSeg = 512;
 void launch_csr_check(const int32_t* rowptr, const int32_t* colidx, int64_t m, int64_t n,
                       int64_t nnz, int32_t* bad, hipStream_t st);
 void launch_build_csc(const int32_t* rowptr, const int32_t* colidx, const void* val, int vdt,
@@ -209,14 +209,16 @@ void launch_build_segments(const int32_t* rowptr, int64_t m, int seg, int32_t* n
 int launch_csc_dot(const SparseA& A, int mode, const double* u, const double* x, const double* s,
                    const double* c, const double* rd, const double* d2, double* coef1,
                    double* coef2, double* rd_out, double* d2_out, double* ds_out, double* red,
-                   const double* sc, const int32_t* done, int nblk, hipStream_t st);
+                   const double* sc, const int32_t* done, int nblk, hipStream_t st,
+                   const CgFuse* cg = nullptr);
 int csc_dot_nblk(int64_t n);
+int csr_fold_nblk(int64_t m);
 // segment sums of A coef1 (and A coef2), then out = scale * (A coef_which) + beta * add
 void launch_csr_segsum(const SparseA& A, const double* coef1, const double* coef2,
                        double* segsum, const int32_t* done, hipStream_t st);
 void launch_csr_fold(const SparseA& A, const double* segsum, int which, double scale,
                      const double* add, double beta, double* out, const int32_t* done,
-                     hipStream_t st);
+                     hipStream_t st, const double* dvec = nullptr, double* dq_out = nullptr);
 void launch_sketch_csc(const SparseA& A, int s, const double* dscale, int is_d2,
                        const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
                        double* B, int64_t ldb, hipStream_t st);
@@ -228,7 +230,7 @@ void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, 
                         hipStream_t st);
 int chol_block(int64_t mp);
 // G (mp x mp, SPD) -> G^{-1} in place via Cholesky; Xb: mp x mp scratch (holds L^{-1})
-void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail,
+void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int nb, int32_t* fail,
                         hipStream_t st);
 void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t st);
 // Out = X In, X block-lower-triangular mp x mp
@@ -251,9 +253,6 @@ void launch_cg_init(int64_t m, const double* p, const double* z, double* r, doub
 // (rz_k, rr_k from the partials, iteration count k, done flag)
 void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* is,
                      hipStream_t st);
-void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
-                      double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
-                      double* sc, int32_t* is, int inner, hipStream_t st);
 
 // n-vector kernels of the IPM iteration
 void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,

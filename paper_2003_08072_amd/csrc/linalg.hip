@@ -287,44 +287,72 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
     }
 }
 
-// Off-diagonal blocks of X = L^{-1}, block row i: for k < i,
-//   X_ik = -X_ii * sum_{j=k}^{i-1} L_ij X_jk      (one workgroup per k)
+// X = L^{-1} from its diagonal blocks by recursive doubling.  At a level with
+// ranges of `half` blocks, pair p joins a = [a0, a0 + half) and the range b that
+// follows it (at most `half` blocks); with X_aa and X_bb already inverses,
+//   X_ba = -X_bb (L_ba X_aa).
+// k_trinv_c forms C = L_ba X_aa (X_aa lower triangular: tile (i, c) needs
+// blocks j >= c), k_trinv_x then X_ba = -X_bb C (tile (r, c) needs j <= r).
+// Grid: (half, half, pairs), one workgroup per tile.
 template <int NB>
-__global__ __launch_bounds__(256) void k_trinv_row(const double* __restrict__ G,
-                                                   double* __restrict__ Xb, int64_t mp, int i) {
+__global__ __launch_bounds__(256) void k_trinv_c(const double* __restrict__ G,
+                                                 const double* __restrict__ Xb,
+                                                 double* __restrict__ Ct, int64_t mp, int half,
+                                                 int T) {
   __shared__ double At[NB][NB + 1];
   __shared__ double Bt[NB][NB + 1];
-  const int k = blockIdx.x;
-  const int64_t I0 = (int64_t)i * NB, K0 = (int64_t)k * NB;
+  const int a0 = blockIdx.z * 2 * half, b0 = a0 + half;
+  const int nbb = T - b0 < half ? T - b0 : half;
+  const int ai = blockIdx.x, bi = blockIdx.y;
+  if (bi >= nbb) return;
+  const int64_t R0 = (int64_t)(b0 + bi) * NB, C0 = (int64_t)(a0 + ai) * NB;
   TileAcc<NB> ta;
   ta.zero();
-  for (int j = k; j < i; ++j) {
-    const int64_t J0 = (int64_t)j * NB;
+  for (int j = ai; j < half; ++j) {
+    const int64_t J0 = (int64_t)(a0 + j) * NB;
     __syncthreads();
-    load_tile<NB>(At, G, mp, I0, J0);   // L_ij
-    load_tile<NB>(Bt, Xb, mp, J0, K0);  // X_jk
+    load_tile<NB>(At, G, mp, R0, J0);   // L_(b0+bi),(a0+j)
+    load_tile<NB>(Bt, Xb, mp, J0, C0);  // X_(a0+j),(a0+ai)
     __syncthreads();
     ta.mma_nn(At, Bt);
   }
-  // S -> LDS (Bt), then X_ik = -X_ii S
   constexpr int TW = NB / 16;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __syncthreads();
 #pragma unroll
   for (int p = 0; p < TW; ++p)
 #pragma unroll
-    for (int o = 0; o < TW; ++o) Bt[ty * TW + p][tx * TW + o] = ta.acc[p][o];
-  load_tile<NB>(At, Xb, mp, I0, I0);  // X_ii
-  __syncthreads();
+    for (int o = 0; o < TW; ++o)
+      Ct[(R0 + ty * TW + p) + (C0 + tx * TW + o) * mp] = ta.acc[p][o];
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_trinv_x(const double* __restrict__ Ct,
+                                                 double* __restrict__ Xb, int64_t mp, int half,
+                                                 int T) {
+  __shared__ double At[NB][NB + 1];
+  __shared__ double Bt[NB][NB + 1];
+  const int a0 = blockIdx.z * 2 * half, b0 = a0 + half;
+  const int nbb = T - b0 < half ? T - b0 : half;
+  const int ai = blockIdx.x, bi = blockIdx.y;
+  if (bi >= nbb) return;
+  const int64_t R0 = (int64_t)(b0 + bi) * NB, C0 = (int64_t)(a0 + ai) * NB;
+  TileAcc<NB> ta;
   ta.zero();
-  ta.mma_nn(At, Bt);
+  for (int j = 0; j <= bi; ++j) {
+    const int64_t J0 = (int64_t)(b0 + j) * NB;
+    __syncthreads();
+    load_tile<NB>(At, Xb, mp, R0, J0);  // X_(b0+bi),(b0+j)
+    load_tile<NB>(Bt, Ct, mp, J0, C0);  // C_(b0+j),(a0+ai)
+    __syncthreads();
+    ta.mma_nn(At, Bt);
+  }
+  constexpr int TW = NB / 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
   for (int p = 0; p < TW; ++p)
 #pragma unroll
-    for (int o = 0; o < TW; ++o) {
-      const int64_t gi = I0 + ty * TW + p, gk = K0 + tx * TW + o;
-      Xb[gi + gk * mp] = -ta.acc[p][o];
-    }
+    for (int o = 0; o < TW; ++o)
+      Xb[(R0 + ty * TW + p) + (C0 + tx * TW + o) * mp] = -ta.acc[p][o];
 }
 
 // P = X^T X: P_ij = sum_{l >= i} X_li^T X_lj for j <= i, mirrored; written over G.
@@ -438,7 +466,7 @@ void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, 
 
 int chol_block(int64_t mp) { return mp > 0 ? 32 : 32; }  // mp is a multiple of 64
 
-void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail,
+void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int nb, int32_t* fail,
                         hipStream_t st) {
   const int T = (int)(mp / nb);
   for (int k = 0; k < T; ++k) {
@@ -455,11 +483,16 @@ void launch_spd_inverse(double* G, double* Xb, int64_t mp, int nb, int32_t* fail
                            mp, k);
     }
   }
-  for (int i = 1; i < T; ++i) {
-    if (nb == 32)
-      hipLaunchKernelGGL(k_trinv_row<32>, dim3(i), dim3(256), 0, st, G, Xb, mp, i);
-    else
-      hipLaunchKernelGGL(k_trinv_row<64>, dim3(i), dim3(256), 0, st, G, Xb, mp, i);
+  // X = L^{-1}: log2(T) levels of two launches each
+  for (int half = 1; half < T; half *= 2) {
+    const dim3 grid(half, half, (T + 2 * half - 1) / (2 * half));
+    if (nb == 32) {
+      hipLaunchKernelGGL(k_trinv_c<32>, grid, dim3(256), 0, st, G, Xb, Ct, mp, half, T);
+      hipLaunchKernelGGL(k_trinv_x<32>, grid, dim3(256), 0, st, Ct, Xb, mp, half, T);
+    } else {
+      hipLaunchKernelGGL(k_trinv_c<64>, grid, dim3(256), 0, st, G, Xb, Ct, mp, half, T);
+      hipLaunchKernelGGL(k_trinv_x<64>, grid, dim3(256), 0, st, Ct, Xb, mp, half, T);
+    }
   }
   const int npairs = T * (T + 1) / 2;
   if (nb == 32)

@@ -28,26 +28,27 @@ __device__ __forceinline__ double wsum(double v) {
 
 // rowptr monotone from 0 to nnz, column indices in range and strictly
 // increasing inside each row.  One thread per row.
+// One wave per row: row pointers in range and monotone, columns in range and
+// strictly increasing along the row.
 __global__ __launch_bounds__(256) void k_csr_check(const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colidx,
                                                    int64_t m, int64_t n, int64_t nnz,
                                                    int32_t* __restrict__ bad) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < m; i += nwaves) {
     const int64_t b = rowptr[i], e = rowptr[i + 1];
     if ((i == 0 && b != 0) || b < 0 || e < b || e > nnz || (i == m - 1 && e != nnz)) {
-      atomicOr(bad, 1);
+      if (lane == 0) atomicOr(bad, 1);
       continue;
     }
-    int64_t prev = -1;
-    for (int64_t k = b; k < e; ++k) {
+    int flag = 0;
+    for (int64_t k = b + lane; k < e; k += 64) {
       const int64_t c = colidx[k];
-      if (c < 0 || c >= n || c <= prev) {
-        atomicOr(bad, 2);
-        break;
-      }
-      prev = c;
+      if (c < 0 || c >= n || (k > b && c <= (int64_t)colidx[k - 1])) flag = 1;
     }
+    if (flag) atomicOr(bad, 2);
   }
 }
 
@@ -156,6 +157,7 @@ struct CscArgs {
   double* red;
   const double* sc;
   const int32_t* done;
+  CgFuse cg;  // COL_NORMAL inside CG: open the iteration (stop test, beta, d_k)
 };
 
 template <typename TV, int MODE>
@@ -163,7 +165,51 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
   __shared__ double us[kMaxRowsLds];
   __shared__ double sred[4][2];
   if (a.done && *a.done) return;
-  for (int64_t i = threadIdx.x; i < a.m; i += blockDim.x) us[i] = a.u[i];
+  if (MODE == COL_NORMAL && a.cg.on && a.cg.k > 0) {
+    // the same sums in the same order in every workgroup: the same decision
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+      double s0 = 0, s1 = 0;
+      for (int p = lane; p < a.cg.np; p += 64) {
+        s0 += a.cg.prz[2 * p];
+        s1 += a.cg.prz[2 * p + 1];
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+      }
+      if (lane == 0) {
+        sred[0][0] = s0;
+        sred[0][1] = s1;
+      }
+    }
+    __syncthreads();
+    const int64_t k = a.cg.k;
+    double* sc = a.cg.sc;
+    int32_t* is = a.cg.is;
+    const double rz = sred[0][0], rr = sred[0][1];
+    const double crit = is[I_CG_RESID] ? rr : rz;
+    const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
+    const double beta =
+        a.cg.inner == SKIPM_INNER_CG ? rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)] : 0.0;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[S_CG_RZ] = rz;
+      sc[S_V_RR] = rr;
+      sc[S_CG_RZH0 + (int)(k & 1)] = rz;
+      is[I_CG_ITERS] = (int32_t)k;
+      if (stop) is[I_CG_DONE] = 1;
+    }
+    if (stop) return;
+    for (int64_t i = threadIdx.x; i < a.m; i += blockDim.x) {
+      const double di = a.cg.z[i] + beta * a.cg.d_old[i];
+      us[i] = di;
+      if (blockIdx.x == 0) a.cg.d_new[i] = di;
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < a.m; i += blockDim.x) us[i] = a.u[i];
+  }
   __syncthreads();
   const TV* __restrict__ cv = (const TV*)a.cval;
   double mu = 0, sigma = 0;
@@ -233,11 +279,31 @@ __global__ __launch_bounds__(256) void k_csr_seg(const int32_t* __restrict__ col
   if (s >= nseg) return;
   const int64_t b = seg_start[s], e = seg_end[s];
   double acc1 = 0, acc2 = 0;
-  for (int64_t k = b + lane; k < e; k += 64) {
-    const double v = (double)val[k];
-    const int32_t c = colidx[k];
-    acc1 += v * coef1[c];
-    if (NV > 1) acc2 += v * coef2[c];
+  // four non-zeros per lane per trip: their indices and values are loaded
+  // first, then the four gathers are in flight together; the products are
+  // added in non-zero order
+  constexpr int U = 4;
+  for (int64_t k = b + lane; k < e; k += 64 * U) {
+    int32_t c[U];
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = k + 64 * u;
+      c[u] = kk < e ? colidx[kk] : -1;
+      v[u] = kk < e ? (double)val[kk] : 0.0;
+    }
+    double g1[U], g2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      g1[u] = c[u] >= 0 ? coef1[c[u]] : 0.0;
+      if (NV > 1) g2[u] = c[u] >= 0 ? coef2[c[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c[u] < 0) break;
+      acc1 += v[u] * g1[u];
+      if (NV > 1) acc2 += v[u] * g2[u];
+    }
   }
   acc1 = wsum(acc1);
   if (NV > 1) acc2 = wsum(acc2);
@@ -247,24 +313,33 @@ __global__ __launch_bounds__(256) void k_csr_seg(const int32_t* __restrict__ col
   }
 }
 
-// One wave per row: out[i] = scale * sum of the row's segment sums (in order) + beta * add[i]
+// One wave per row: out[i] = scale * sum of the row's segment sums (in order) + beta * add[i];
+// with dvec, also the workgroup's partial sum of dvec_i out_i (its four rows in order).
 __global__ __launch_bounds__(256) void k_csr_fold(const double* __restrict__ segsum,
                                                   const int32_t* __restrict__ segptr, int64_t m,
                                                   double scale, const double* __restrict__ add,
                                                   double beta, double* __restrict__ out,
+                                                  const double* __restrict__ dvec,
+                                                  double* __restrict__ dq_out,
                                                   const int32_t* __restrict__ done) {
+  __shared__ double dq[4];
   if (done && *done) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (i >= m) return;
-  const int64_t b = segptr[i], e = segptr[i + 1];
-  double acc = 0;
-  for (int64_t s = b + lane; s < e; s += 64) acc += segsum[s];
-  acc = wsum(acc);
-  if (lane == 0) {
-    double v = scale * acc;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + wid;
+  double v = 0;
+  if (i < m) {
+    const int64_t b = segptr[i], e = segptr[i + 1];
+    double acc = 0;
+    for (int64_t s = b + lane; s < e; s += 64) acc += segsum[s];
+    acc = wsum(acc);
+    v = scale * acc;
     if (add) v += beta * add[i];
-    out[i] = v;
+    if (lane == 0) out[i] = v;
+  }
+  if (dvec) {  // uniform: every wave of the workgroup reaches the barrier
+    if (lane == 0) dq[wid] = i < m ? dvec[i] * v : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) dq_out[blockIdx.x] = ((dq[0] + dq[1]) + dq[2]) + dq[3];
   }
 }
 
@@ -313,8 +388,8 @@ unsigned grid_n(int64_t n, int per = 256) {
 
 void launch_csr_check(const int32_t* rowptr, const int32_t* colidx, int64_t m, int64_t n,
                       int64_t nnz, int32_t* bad, hipStream_t st) {
-  hipLaunchKernelGGL(k_csr_check, dim3(grid_n(m)), dim3(256), 0, st, rowptr, colidx, m, n, nnz,
-                     bad);
+  hipLaunchKernelGGL(k_csr_check, dim3(grid_n(m * 64)), dim3(256), 0, st, rowptr, colidx, m, n,
+                     nnz, bad);
 }
 
 void launch_build_csc(const int32_t* rowptr, const int32_t* colidx, const void* val, int vdt,
@@ -349,8 +424,10 @@ void launch_build_segments(const int32_t* rowptr, int64_t m, int seg, int32_t* n
 int launch_csc_dot(const SparseA& A, int mode, const double* u, const double* x, const double* s,
                    const double* c, const double* rd, const double* d2, double* coef1,
                    double* coef2, double* rd_out, double* d2_out, double* ds_out, double* red,
-                   const double* sc, const int32_t* done, int nblk, hipStream_t st) {
+                   const double* sc, const int32_t* done, int nblk, hipStream_t st,
+                   const CgFuse* cg) {
   CscArgs a{};
+  if (cg) a.cg = *cg;
   a.colptr = A.colptr;
   a.rowidx = A.rowidx;
   a.cval = A.cval;
@@ -424,11 +501,13 @@ void launch_csr_segsum(const SparseA& A, const double* coef1, const double* coef
 
 void launch_csr_fold(const SparseA& A, const double* segsum, int which, double scale,
                      const double* add, double beta, double* out, const int32_t* done,
-                     hipStream_t st) {
-  const unsigned gm = (unsigned)((A.m + 3) / 4);
+                     hipStream_t st, const double* dvec, double* dq_out) {
+  const unsigned gm = (unsigned)csr_fold_nblk(A.m);
   hipLaunchKernelGGL(k_csr_fold, dim3(gm), dim3(256), 0, st, segsum + (int64_t)which * A.nseg,
-                     A.segptr, A.m, scale, add, beta, out, done);
+                     A.segptr, A.m, scale, add, beta, out, dvec, dq_out, done);
 }
+
+int csr_fold_nblk(int64_t m) { return (int)((m + 3) / 4); }
 
 void launch_sketch_csc(const SparseA& A, int s, const double* dscale, int is_d2,
                        const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,

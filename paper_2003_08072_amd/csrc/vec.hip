@@ -96,11 +96,11 @@ unsigned grid_for(int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// CG (single workgroup; m-vectors are small)
+// CG state (the iterations themselves are fused into the product and Q^{-1}
+// passes, see CgFuse)
 //   init:   x = 0, r = rhs, z = P rhs (given), d = z, rz = r^T z,
 //           stop threshold tol^2 rz0 (or tol^2 r^T r for the residual test)
-//   update: pq = d^T q; alpha = rz / pq; x += alpha d; r -= alpha q;
-//           z -= alpha P q; rz' = r^T z; d = z + (rz'/rz) d
+//   close:  the bookkeeping of a run stopped by its iteration cap
 // The CG kernels return at once when the done flag is set, so a fixed chunk
 // of iterations can be enqueued without reading the flag on the host.
 // ---------------------------------------------------------------------------
@@ -144,60 +144,6 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(int64_t m, const double*
     is[I_CG_MAX] = max_it;
     is[I_CG_DONE] = (max_it <= 0 || !(rz > 0) || (resid_test ? rr : rz) <= sc[S_CG_TOL2]) ? 1 : 0;
     is[I_CG_RESID] = resid_test;
-  }
-}
-
-__global__ __launch_bounds__(kCgThreads) void k_cg_update(int64_t m, const double* __restrict__ q,
-                                                          const double* __restrict__ wq,
-                                                          double* __restrict__ r,
-                                                          double* __restrict__ z,
-                                                          double* __restrict__ d,
-                                                          float* __restrict__ df,
-                                                          double* __restrict__ x,
-                                                          double* __restrict__ tw,
-                                                          const double* __restrict__ tq,
-                                                          int64_t nw, double* __restrict__ sc,
-                                                          int32_t* __restrict__ is, int inner) {
-  __shared__ double buf[kCgThreads / 64];
-  if (is[I_CG_DONE]) return;
-  double pq = 0;
-  for (int64_t i = threadIdx.x; i < m; i += kCgThreads) pq += d[i] * q[i];
-  pq = block_sum<kCgThreads>(pq, buf);
-  const double rz = sc[S_CG_RZ];
-  if (!(pq > 0)) {  // breakdown: the operator lost positive definiteness numerically
-    __syncthreads();
-    if (threadIdx.x == 0) is[I_CG_DONE] = 1;
-    return;
-  }
-  const double alpha = inner == SKIPM_INNER_RICHARDSON ? 1.0 : rz / pq;
-  double rz_new = 0, rr = 0;
-  for (int64_t i = threadIdx.x; i < m; i += kCgThreads) {
-    const double di = d[i];
-    x[i] += alpha * di;
-    const double ri = r[i] - alpha * q[i];
-    const double zi = z[i] - alpha * wq[i];
-    r[i] = ri;
-    z[i] = zi;
-    rz_new += ri * zi;
-    rr += ri * ri;
-  }
-  for (int64_t i = threadIdx.x; i < nw; i += kCgThreads) tw[i] += alpha * tq[i];
-  rz_new = block_sum<kCgThreads>(rz_new, buf);
-  rr = block_sum<kCgThreads>(rr, buf);
-  const double beta = inner == SKIPM_INNER_CG ? rz_new / rz : 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += kCgThreads) {
-    const double di = z[i] + beta * d[i];
-    d[i] = di;
-    if (df) df[i] = (float)di;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    sc[S_CG_RZ] = rz_new;
-    sc[S_V_RR] = rr;
-    const int it = is[I_CG_ITERS] + 1;
-    is[I_CG_ITERS] = it;
-    const double crit = is[I_CG_RESID] ? rr : rz_new;
-    if (it >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz_new > 0)) is[I_CG_DONE] = 1;
   }
 }
 
@@ -548,13 +494,6 @@ void launch_cg_init(int64_t m, const double* p, const double* z, double* r, doub
 void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* is,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_cg_close, dim3(1), dim3(64), 0, st, prz, np, k, sc, is);
-}
-
-void launch_cg_update(int64_t m, const double* q, const double* wq, double* r, double* z,
-                      double* d, float* df, double* x, double* tw, const double* tq, int64_t nw,
-                      double* sc, int32_t* is, int inner, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(1), dim3(kCgThreads), 0, st, m, q, wq, r, z, d, df, x, tw,
-                     tq, nw, sc, is, inner);
 }
 
 void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,
