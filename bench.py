@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 2.000, the factor a
 # 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
 # current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
-MEASURED_TRAFFIC = {(1, "mixed"): 202_055_194, (1, "fp64"): 402_925_338}
+MEASURED_TRAFFIC = {(1, "mixed"): 202_001_602, (1, "fp64"): 403_380_805}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 
