@@ -61,6 +61,8 @@ extern "C" {
 #define SKIPM_INNER_CG         0  /* preconditioned CG (Alg. 1 step 3) */
 #define SKIPM_INNER_SD         1  /* preconditioned steepest descent (App. B, Alg. 4) */
 #define SKIPM_INNER_RICHARDSON 2  /* preconditioned Richardson iteration (App. A, Alg. 3) */
+#define SKIPM_SKETCH_COUNT     0  /* block CountSketch (sparse embedding of Sec. 2) */
+#define SKIPM_SKETCH_GAUSSIAN  1  /* dense N(0,1) sketch W_G (Sec. 5) */
 #define SKIPM_PREC_FP64  0   /* everything FP64 */
 #define SKIPM_PREC_MIXED 1   /* CG products read an FP32 copy of A (FP64 accumulation) inside
                                 an iterative refinement on FP64 residuals; residuals, v,
@@ -104,6 +106,9 @@ typedef struct {
   uint64_t seed;     /* sketch seed  [0]                                               */
   int32_t inner;     /* solver of Alg. 2 step (c): SKIPM_INNER_CG (Alg. 1), _SD (steepest
                         descent, App. B Alg. 4) or _RICHARDSON (App. A Alg. 3)  [CG]   */
+  int32_t sketch;    /* SKIPM_SKETCH_COUNT: the sparse embedding of Sec. 2 (s non-zeros
+                        per row); SKIPM_SKETCH_GAUSSIAN: the dense Gaussian W_G of
+                        Sec. 5 (dense FP64 A only; s is ignored)  [COUNT]            */
 } skipm_params;
 
 /* Result of lp_solve (host struct). */

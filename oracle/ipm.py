@@ -40,7 +40,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .sketch import sketch_matrix
+from .sketch import gaussian_sketch_matrix, sketch_matrix
 
 
 # ----------------------------------------------------------------------------
@@ -361,6 +361,7 @@ class IPMParams:
     max_cg: int = 1000
     cg_t: int | None = None     # fixed CG iteration count instead of tol_cg
     inner: str = "cg"           # "cg" (Alg. 1) | "sd" (Alg. 4) | "richardson" (Alg. 3)
+    sketch: str = "count"       # "count" (Sec. 2) | "gaussian" (W_G of Sec. 5)
 
 
 @dataclasses.dataclass
@@ -420,7 +421,11 @@ def ipm(A, b, c, params: IPMParams | None = None, x0=None, y0=None, s0=None):
             if prm.solver == "exact":
                 dirn = exact_direction(A, b, c, x, y, s, prm.sigma)
             else:
-                W = sketch_matrix(prm.seed, k if prm.resketch else 0, prm.s_nnz, n, w)
+                salt = k if prm.resketch else 0
+                if prm.sketch == "gaussian":
+                    W = gaussian_sketch_matrix(prm.seed, salt, n, w)
+                else:
+                    W = sketch_matrix(prm.seed, salt, prm.s_nnz, n, w)
                 dirn = sketch_direction(A, b, c, x, y, s, prm.sigma, W, prm.tol_cg,
                                         prm.max_cg, prm.cg_t, prm.inner)
         except np.linalg.LinAlgError:

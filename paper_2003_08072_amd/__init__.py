@@ -31,6 +31,8 @@ SKIPM_F32 = 1
 SKIPM_INNER_CG = 0
 SKIPM_INNER_SD = 1
 SKIPM_INNER_RICHARDSON = 2
+SKIPM_SKETCH_COUNT = 0
+SKIPM_SKETCH_GAUSSIAN = 1
 SKIPM_PREC_FP64 = 0
 SKIPM_PREC_MIXED = 1
 
@@ -47,7 +49,7 @@ class Params(C.Structure):
                 ("eps_gap", C.c_double), ("eps_feas", C.c_double), ("guard", C.c_double),
                 ("w", C.c_int32), ("s", C.c_int32), ("max_cg", C.c_int32),
                 ("max_outer", C.c_int32), ("resketch", C.c_int32), ("precision", C.c_int32),
-                ("seed", C.c_uint64), ("inner", C.c_int32)]
+                ("seed", C.c_uint64), ("inner", C.c_int32), ("sketch", C.c_int32)]
 
 
 class Result(C.Structure):

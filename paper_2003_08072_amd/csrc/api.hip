@@ -21,6 +21,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 
 namespace skipm {
@@ -83,6 +85,10 @@ struct skipm_lp_s {
   // fused CG (dense A): second direction buffer and the partial sums
   double* cd2 = nullptr;
   double* Ct = nullptr;  // mp x mp scratch of the triangular inverse
+  // Gaussian sketch: Wd = D W_G (n x w), W t for the correction vector, rocBLAS
+  double* Wd = nullptr;
+  double* gy = nullptr;
+  rocblas_handle blas = nullptr;
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
   std::vector<void*> allocs;
@@ -126,6 +132,8 @@ int validate_params(const skipm_params& p, int64_t m, int64_t n) {
     return set_error("unknown precision"), SKIPM_EINVAL;
   if (p.inner != SKIPM_INNER_CG && p.inner != SKIPM_INNER_SD && p.inner != SKIPM_INNER_RICHARDSON)
     return set_error("unknown inner solver"), SKIPM_EINVAL;
+  if (p.sketch != SKIPM_SKETCH_COUNT && p.sketch != SKIPM_SKETCH_GAUSSIAN)
+    return set_error("unknown sketch"), SKIPM_EINVAL;
   if (n * p.s > INT32_MAX) return set_error("n*s exceeds int32 item indices"), SKIPM_EINVAL;
   return SKIPM_OK;
 }
@@ -539,8 +547,31 @@ int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, in
   return SKIPM_ERANK;
 }
 
+int gaussian_ready(skipm_lp_s* lp) {
+  if (!lp->Wd) SK_TRY(dalloc(lp, &lp->Wd, lp->n * (int64_t)lp->w));
+  if (!lp->gy) SK_TRY(dalloc(lp, &lp->gy, lp->n));
+  if (!lp->blas && rocblas_create_handle(&lp->blas) != rocblas_status_success) {
+    lp->blas = nullptr;
+    return set_error("rocblas_create_handle failed"), SKIPM_EDEVICE;
+  }
+  return SKIPM_OK;
+}
+
 int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, double* B,
                 hipStream_t st) {
+  if (lp->prm.sketch == SKIPM_SKETCH_GAUSSIAN) {
+    // B = A (D W_G): fill D W_G, then one FP64 GEMM over the padded rows
+    SK_TRY(gaussian_ready(lp));
+    launch_gauss_fill(lp->prm.seed, salt, lp->n, lp->w, dscale, is_d2, lp->Wd, lp->n, st);
+    SK_CHECK_HIP(hipGetLastError());
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success ||
+        rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, (int)lp->lda,
+                      lp->w, (int)lp->n, &one, (const double*)lp->A, (int)lp->lda, lp->Wd,
+                      (int)lp->n, &zero, B, (int)lp->lda) != rocblas_status_success)
+      return set_error("rocblas_dgemm (Gaussian sketch) failed"), SKIPM_EDEVICE;
+    return SKIPM_OK;
+  }
   SK_TRY(hash_items(lp, salt, st));
   if (lp->fmt == SKIPM_CSR)
     launch_sketch_csc(lp->sp, lp->s, dscale, is_d2, lp->bptr, lp->perm, lp->sign, lp->w, B,
@@ -757,8 +788,18 @@ int v_solve(skipm_lp_s* lp, int* its, double* rel_out, hipStream_t st) {
 }
 
 int finish_step(skipm_lp_s* lp, hipStream_t st) {
+  const double* wt = nullptr;
+  if (lp->prm.sketch == SKIPM_SKETCH_GAUSSIAN) {
+    // (D W_G) t; the direction kernel forms v_j = sqrt(x_j s_j) (W_G t)_j = s_j (D W_G t)_j
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success ||
+        rocblas_dgemv(lp->blas, rocblas_operation_none, (int)lp->n, lp->w, &one, lp->Wd,
+                      (int)lp->n, lp->tw, 1, &zero, lp->gy, 1) != rocblas_status_success)
+      return set_error("rocblas_dgemv (Gaussian sketch) failed"), SKIPM_EDEVICE;
+    wt = lp->gy;
+  }
   launch_direction(lp->n, lp->s, lp->x, lp->sv, lp->d2, lp->ds, lp->bucket, lp->sign, lp->tw,
-                   lp->v, lp->dx, lp->red, lp->nblk_vec, lp->sc, st);
+                   wt, lp->v, lp->dx, lp->red, lp->nblk_vec, lp->sc, st);
   launch_reduce_slots(lp->red, lp->nblk_vec, 5, lp->sc, S_A0, 0, st);
   launch_step_terms(lp->n, lp->x, lp->sv, lp->dx, lp->ds, lp->red, lp->nblk_vec, lp->sc, st);
   launch_reduce_slots(lp->red, lp->nblk_vec, 2, lp->sc, S_EXIT, 1, st);
@@ -881,6 +922,7 @@ int skipm_params_default(skipm_params* out) {
   out->precision = SKIPM_PREC_FP64;
   out->seed = 0;
   out->inner = SKIPM_INNER_CG;
+  out->sketch = SKIPM_SKETCH_COUNT;
   return SKIPM_OK;
 }
 
@@ -961,6 +1003,10 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   add(8 * 8 * (int64_t)std::max(std::max(std::max(nblk_Ap, nblk_vec), nblk_csc), 64));
   add(8 * S_NSLOTS);
   add(4 * I_NINTS);
+  if (prm->sketch == SKIPM_SKETCH_GAUSSIAN) {  // D W_G and (D W_G) t
+    add(8 * n * w);
+    add(8 * n);
+  }
   // correction-vector buffers (allocated at the first direction)
   add(8 * lda * w);
   add(8 * lda * w);
@@ -1004,6 +1050,7 @@ int lp_destroy(skipm_lp_t lp) {
   for (void* p : lp->allocs) hipFree(p);
   for (hipEvent_t e : lp->kt_ev)
     if (e) hipEventDestroy(e);
+  if (lp->blas) rocblas_destroy_handle(lp->blas);
   if (lp->hsc) hipHostFree(lp->hsc);
   delete lp;
   return SKIPM_OK;
@@ -1049,6 +1096,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   if (!csr && lda_in < m) return set_error("lda < m"), SKIPM_EINVAL;
   SK_TRY(validate_params(*prm, m, n));
   if (m > 2048) return set_error("m <= 2048 is supported"), SKIPM_EINVAL;
+  if (prm->sketch == SKIPM_SKETCH_GAUSSIAN && (csr || prob->a_dtype != SKIPM_F64))
+    return set_error("the Gaussian sketch needs dense FP64 A"), SKIPM_EINVAL;
 
   skipm_lp_s* lp = new skipm_lp_s();
   hipGetDevice(&lp->device);

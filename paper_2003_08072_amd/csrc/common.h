@@ -161,6 +161,9 @@ int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode);
 
 // bucket-ordered sketch B[:, b] = sum over items in bucket b of sign * d_j * A[:, j]
 // (dscale holds d, or d^2 when is_d2 != 0)
+// Gaussian sketch (dense A): Wd = D W_G, n x w column-major with leading dim ldw
+void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const double* dscale,
+                       int is_d2, double* Wd, int64_t ldw, hipStream_t st);
 void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t n, int s,
                          const double* dscale, int is_d2, const int32_t* ptr,
                          const int32_t* perm, const int8_t* sign, int w, double* B,
@@ -261,8 +264,8 @@ void launch_prologue_finalize(int64_t m, const double* rp, const double* b, cons
 void launch_mu_finalize(const double* red, int nblk, int64_t n, double* sc, hipStream_t st);
 void launch_direction(int64_t n, int s, const double* x, const double* sv, const double* d2,
                       const double* ds, const int32_t* bucket, const int8_t* sign,
-                      const double* tw, double* v, double* dx, double* red, int nblk,
-                      const double* sc, hipStream_t st);
+                      const double* tw, const double* wt, double* v, double* dx, double* red,
+                      int nblk, const double* sc, hipStream_t st);
 void launch_reduce_slots(const double* red, int nblk, int nq, double* sc, int slot0,
                          int op, hipStream_t st);
 void launch_step_terms(int64_t n, const double* x, const double* s, const double* dx,

@@ -1,0 +1,68 @@
+// Gaussian sketching matrix W_G (Sec. 5; the paper's experiments use it) for
+// dense A.  W_G (n x w, N(0, 1) entries from a counter-based generator) is
+// written already scaled by D, Wd = D W_G, so that the sketch is one plain
+// GEMM, B = A Wd (rocBLAS, FP64 on the matrix cores), and the correction
+// vector's W t is one GEMV, (W_G t)_j = (Wd t)_j / d_j.
+//
+// Entry (j, c) with salt k (the same definition as the reference generator):
+//   base = mix(seed + G (1 + k)), h1 = mix(base ^ 2(jw + c)), h2 = mix(base ^ (2(jw + c) + 1))
+//   u1 = ((h1 >> 11) + 1) 2^-53, u2 = (h2 >> 11) 2^-53
+//   z = sqrt(-2 ln u1) cos(2 pi u2), rounded to an 8-bit significand (ties to even)
+#include "common.h"
+
+namespace skipm {
+
+namespace {
+
+__device__ __forceinline__ uint64_t gmix(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+__device__ __forceinline__ double gauss_entry(uint64_t base, uint64_t idx) {
+  const uint64_t h1 = gmix(base ^ (2 * idx));
+  const uint64_t h2 = gmix(base ^ (2 * idx + 1));
+  const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
+  const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  int e = 0;
+  const double m = frexp(z, &e);
+  return ldexp(rint(ldexp(m, 8)), e - 8);
+}
+
+// Wd[j + c ldw] = d_j W_G[j, c]; one thread per (j, c), j fastest
+__global__ __launch_bounds__(256) void k_gauss_fill(uint64_t base, int64_t n, int64_t w,
+                                                    const double* __restrict__ dscale, int is_d2,
+                                                    double* __restrict__ Wd, int64_t ldw) {
+  const int64_t total = n * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t c = e / n, j = e - c * n;
+    const double dj = is_d2 ? sqrt(dscale[j]) : dscale[j];
+    Wd[j + c * ldw] = dj * gauss_entry(base, (uint64_t)j * (uint64_t)w + (uint64_t)c);
+  }
+}
+
+}  // namespace
+
+void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const double* dscale,
+                       int is_d2, double* Wd, int64_t ldw, hipStream_t st) {
+  // base = mix(seed + G (1 + k)), on the host (mod 2^64)
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(1 + k);
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  int64_t blocks = (n * w + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_gauss_fill, dim3((unsigned)blocks), dim3(256), 0, st, z, n, w, dscale,
+                     is_d2, Wd, ldw);
+}
+
+}  // namespace skipm

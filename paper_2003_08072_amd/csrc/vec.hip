@@ -223,8 +223,8 @@ __global__ __launch_bounds__(kVecThreads) void k_direction(
     int64_t n, int s, const double* __restrict__ x, const double* __restrict__ sv,
     const double* __restrict__ d2, const double* __restrict__ ds,
     const int32_t* __restrict__ bucket, const int8_t* __restrict__ sign,
-    const double* __restrict__ tw, double* __restrict__ v, double* __restrict__ dx,
-    double* __restrict__ red, const double* __restrict__ sc) {
+    const double* __restrict__ tw, const double* __restrict__ wt, double* __restrict__ v,
+    double* __restrict__ dx, double* __restrict__ red, const double* __restrict__ sc) {
   __shared__ double buf[kVecThreads / 64];
   const double smu = sc[S_SIGMA] * sc[S_MU];
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -233,9 +233,14 @@ __global__ __launch_bounds__(kVecThreads) void k_direction(
   double a0 = 0, a1 = 0, a2 = 0, vs = 0, v2 = 0;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kVecThreads) {
     const double xj = x[j], sj = sv[j], dsj = ds[j];
-    double acc = 0;
-    for (int r = 0; r < s; ++r) acc += (double)sign[j * s + r] * tw[bucket[j * s + r]];
-    const double vj = sqrt(xj * sj) * acc;
+    double vj;
+    if (wt) {  // Gaussian sketch: wt = (D W_G) t, and sqrt(x_j s_j) / d_j = s_j
+      vj = sj * wt[j];
+    } else {
+      double acc = 0;
+      for (int r = 0; r < s; ++r) acc += (double)sign[j * s + r] * tw[bucket[j * s + r]];
+      vj = sqrt(xj * sj) * acc;
+    }
     const double dxj = -xj + smu / sj - d2[j] * dsj - vj / sj;
     v[j] = vj;
     dx[j] = dxj;
@@ -505,10 +510,10 @@ void launch_prologue_finalize(int64_t m, const double* rp, const double* b, cons
 
 void launch_direction(int64_t n, int s, const double* x, const double* sv, const double* d2,
                       const double* ds, const int32_t* bucket, const int8_t* sign,
-                      const double* tw, double* v, double* dx, double* red, int nblk,
-                      const double* sc, hipStream_t st) {
+                      const double* tw, const double* wt, double* v, double* dx, double* red,
+                      int nblk, const double* sc, hipStream_t st) {
   hipLaunchKernelGGL(k_direction, dim3(nblk), dim3(kVecThreads), 0, st, n, s, x, sv, d2, ds,
-                     bucket, sign, tw, v, dx, red, sc);
+                     bucket, sign, tw, wt, v, dx, red, sc);
 }
 
 void launch_reduce_slots(const double* red, int nblk, int nq, double* sc, int slot0, int op,

@@ -80,7 +80,7 @@ def _c_layouts():
         pytest.skip("gcc or HIP headers missing")
     fields = {
         "skipm_problem": ["m", "nnz", "format", "a_vals", "lda", "a_colidx", "c"],
-        "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed", "inner"],
+        "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed", "inner", "sketch"],
         "skipm_result": ["status", "cg_max", "obj_p", "mu"],
         "skipm_step_info": ["mu", "v_resid", "cg_iters", "status"],
         "skipm_pcg_info": ["iters", "f0_norm", "f_norm"],

@@ -169,6 +169,61 @@ def test_solve_with_inner_solver(torch, sk, inner):
     check_solution(lp, res, 1e-8)
 
 
+# ---------------------------------------------------------------------------
+# Gaussian sketch W_G (Sec. 5)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,w,k", [(37, 500, 148, 0), (64, 2000, 256, 5), (5, 64, 20, 2)])
+def test_gaussian_sketch_apply(torch, sk, m, n, w, k):
+    from oracle.sketch import gaussian_sketch_matrix
+    say(f"gaussian sketch m={m} n={n} w={w} k={k}")
+    rng = np.random.default_rng(m + n)
+    lp = dense_planted(m, n, rng=rng)
+    d = rng.uniform(0.01, 10.0, n)
+    with sk.LP(lp.A, lp.b, lp.c, w=w, seed=19, sketch=sk.SKIPM_SKETCH_GAUSSIAN) as h:
+        B = h.sketch(d, k).cpu().numpy()
+    W = gaussian_sketch_matrix(19, k, n, w)
+    AD = lp.A * d
+    Bref = AD @ W
+    bound = np.abs(AD) @ np.abs(W)
+    assert np.all(np.abs(B - Bref) <= 4 * n * EPS * bound + 1e-300)
+
+
+def test_gaussian_pcg_fixed_iterations_match_alg1(torch, sk, cg_case):
+    from oracle.sketch import gaussian_sketch_matrix
+    lp, x, s = cg_case
+    say("pcg with the Gaussian sketch, fixed t = 4")
+    d2 = x / s
+    p = np.random.default_rng(6).standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, seed=23, sketch=sk.SKIPM_SKETCH_GAUSSIAN) as h:
+        dy, info = h.pcg(d2, p, 3, tol=0.0, max_it=4)
+        dy = dy.cpu().numpy()
+    ref = O.sketch_pcg(lp.A * np.sqrt(d2), p, gaussian_sketch_matrix(23, 3, lp.n, lp.w), t=4)
+    assert info.iters == 4
+    assert np.linalg.norm(dy - ref.dy) <= 1e-9 * np.linalg.norm(ref.dy)
+
+
+@pytest.mark.parametrize("m,n", [(50, 1000), (33, 700), (130, 4000)])
+def test_solve_with_gaussian_sketch(torch, sk, m, n):
+    lp = dense_planted(m, n, rng=np.random.default_rng(m), eps_gap=1e-8)
+    say(f"solve with the Gaussian sketch m={m} n={n} w=4m")
+    with sk.LP(lp.A, lp.b, lp.c, w=4 * m, seed=3, eps_gap=1e-8,
+               sketch=sk.SKIPM_SKETCH_GAUSSIAN) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-8)
+    assert res.cg_max <= 40
+
+
+def test_gaussian_sketch_needs_dense_fp64(torch, sk):
+    import scipy.sparse as ssp
+    say("gaussian sketch argument checks")
+    lp = dense_planted(10, 200, rng=np.random.default_rng(2))
+    for A, dt in ((lp.A, "f32"), (ssp.csr_matrix(lp.A), "f64")):
+        with pytest.raises(sk.SkipmError) as e:
+            sk.LP(A, lp.b, lp.c, a_dtype=dt, sketch=sk.SKIPM_SKETCH_GAUSSIAN)
+        assert e.value.code == sk.SKIPM_EINVAL
+
+
 def test_solve_with_one_fixed_sketch(torch, sk):
     """resketch = 0: one W (salt 0) for every IPM iteration, its bucket order
     computed once."""

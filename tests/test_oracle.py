@@ -348,6 +348,78 @@ def test_lemma4_v_bound_diagnostic(small_lp):
 
 
 # ---------------------------------------------------------------------------
+# Gaussian sketching matrix W_G (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def test_gaussian_sketch_is_standard_normal():
+    """Entries of W_G: N(0, 1) to the resolution of 2e5 samples, rounded to an
+    8-bit significand (exactly representable in bfloat16)."""
+    from scipy import stats
+    from oracle.sketch import gaussian_sketch_matrix
+    W = gaussian_sketch_matrix(7, 3, 400, 500)
+    z = W.ravel()
+    nz = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(nz)
+    assert abs(z.var() - 1.0) < 0.015
+    assert abs(stats.skew(z)) < 0.02 and abs(stats.kurtosis(z)) < 0.05
+    assert stats.kstest(z, "norm").statistic < 0.005
+    bits = z.astype(np.float32).view(np.uint32)
+    assert np.all((bits & 0xFFFF) == 0)
+    assert np.array_equal(z.astype(np.float32).astype(np.float64), z)
+
+
+def test_gaussian_sketch_entries_independent_and_salted():
+    from oracle.sketch import gaussian_sketch_matrix
+    W0 = gaussian_sketch_matrix(7, 0, 300, 400)
+    W1 = gaussian_sketch_matrix(7, 1, 300, 400)
+    assert np.array_equal(W0, gaussian_sketch_matrix(7, 0, 300, 400))
+    lim = 5 / math.sqrt(W0.size)
+    assert abs(np.corrcoef(W0.ravel(), W1.ravel())[0, 1]) < lim
+    assert abs(np.corrcoef(W0[:, :-1].ravel(), W0[:, 1:].ravel())[0, 1]) < lim
+    assert abs(np.corrcoef(W0[:-1].ravel(), W0[1:].ravel())[0, 1]) < lim
+    # a different shape indexes the same stream: entry (j, c) is base ^ 2 (j w + c)
+    Wn = gaussian_sketch_matrix(7, 0, 600, 400)
+    assert np.array_equal(Wn[:300], W0)
+
+
+def test_gaussian_sketch_spectrum_within_marchenko_pastur(small_lp):
+    """With W_G (w = 4m) the preconditioned matrix Q^{-1/2} A D^2 A^T Q^{-1/2}
+    has kappa <= ((1 + sqrt(m/w)) / (1 - sqrt(m/w)))^2 = 9 up to the finite-size
+    edge fluctuation (the extreme singular values of a Gaussian matrix)."""
+    from oracle.sketch import gaussian_sketch_matrix
+    lp = small_lp
+    x, y, s, _ = _mid_iterate(lp)
+    AD = _scaled(lp, x, s)
+    W = gaussian_sketch_matrix(3, 0, lp.n, 4 * lp.m)
+    res = O.sketch_pcg(AD, np.ones(lp.m), W, t=1)
+    sv = np.linalg.svd(res.Qmh @ AD, compute_uv=False)
+    assert (sv[0] / sv[-1]) ** 2 <= 9 * 1.6
+
+
+def test_ipm_with_gaussian_sketch_reaches_the_planted_optimum():
+    lp = dense_planted(15, 300, rng=np.random.default_rng(31), eps_gap=1e-8)
+    r = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="sketch", sketch="gaussian", eps_gap=1e-8,
+                                              w=4 * lp.m, seed=2))
+    assert r.status == "optimal"
+    assert abs(r.obj_p - lp.opt) <= 2e-8 * max(1.0, abs(lp.opt))
+    assert max(h["cg_iters"] for h in r.history) <= 40
+
+
+def test_planted_mistake_in_gaussian_scale_fails_the_variance_pin():
+    """Dropping the factor 2 of -2 ln u1 halves the variance: the moment pin
+    catches it."""
+    from oracle import sketch as S
+    base = S.mix_int(7 + S.GOLDEN * 1)
+    idx = np.arange(100000, dtype=np.uint64)
+    h1 = S.mix_array(np.uint64(base) ^ (idx * np.uint64(2)))
+    h2 = S.mix_array(np.uint64(base) ^ (idx * np.uint64(2) + np.uint64(1)))
+    u1 = ((h1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (h2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    bad = np.sqrt(-np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    assert abs(bad.var() - 1.0) > 0.3
+
+
+# ---------------------------------------------------------------------------
 # App. A (Richardson, Alg. 3) and App. B (steepest descent, Alg. 4)
 # ---------------------------------------------------------------------------
 
