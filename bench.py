@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--inner", default="cg", choices=["cg", "sd", "richardson"],
                     help="solver of Alg. 2 step (c): CG (Alg. 1), steepest descent (Alg. 4), "
                          "Richardson (Alg. 3)")
+    ap.add_argument("--sketch", default="count", choices=["count", "gaussian"],
+                    help="count: block CountSketch (Sec. 2); gaussian: dense W_G (Sec. 5)")
     ap.add_argument("--resketch", type=int, default=1, choices=[0, 1],
                     help="1: fresh W every IPM iteration; 0: one W for the whole solve")
     ap.add_argument("--matvec-reps", type=int, default=50)
@@ -125,7 +127,8 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
              "richardson": sk.SKIPM_INNER_RICHARDSON}[args.inner]
     h = sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=s_nnz,
               eps_gap=lp.eps_gap, precision=prec, max_outer=1000, inner=inner,
-              resketch=args.resketch, max_cg=5000 if args.inner != "cg" else 500)
+              resketch=args.resketch, max_cg=5000 if args.inner != "cg" else 500,
+              sketch=sk.SKIPM_SKETCH_GAUSSIAN if args.sketch == "gaussian" else sk.SKIPM_SKETCH_COUNT)
     stream = torch.cuda.current_stream()
     res = None
     for _ in range(args.warmup):
@@ -418,7 +421,7 @@ def main():
                                f"{'FP64' if lp.a_dtype == 'f64' else 'FP32'} planted LP, "
                                f"sketch w={lp.w}, s={args.s}, rel. gap {lp.eps_gap:g}",
                    "m": lp.m, "n": lp.n, "w": lp.w, "s": args.s,
-                   "precision": head["precision"], "inner": args.inner,
+                   "precision": head["precision"], "inner": args.inner, "sketch": args.sketch,
                    "resketch": args.resketch},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],

@@ -94,13 +94,16 @@ def sketch_matrix(seed: int, k: int, s: int, n: int, w: int) -> sp.csr_matrix:
 # experiments use it)
 # ----------------------------------------------------------------------------
 #
-# Entry (j, c) of the n x w matrix, with salt k:
+# Entries (j, c) and (j, c + 1), c even, of the n x w matrix, with salt k
+# (one Box-Muller pair; Box and Muller, 1958):
 #   base      mix(seed + 0x9E3779B97F4A7C15 * (1 + k))
-#   h1, h2    mix(base XOR 2 (j w + c)), mix(base XOR (2 (j w + c) + 1))
+#   q         j w + c
+#   h1, h2    mix(base XOR 2 q), mix(base XOR (2 q + 1))
 #   u1        ((h1 >> 11) + 1) 2^-53   in (0, 1]
 #   u2        (h2 >> 11) 2^-53         in [0, 1)
-#   z         sqrt(-2 ln u1) cos(2 pi u2)      (Box and Muller, 1958)
-#   W_jc      z rounded to 8 significant bits, ties to even
+#   r, t      sqrt(-2 ln u1), 2 pi u2
+#   W_jc      r cos t,  W_j,c+1  r sin t   (when c + 1 < w)
+# each rounded to 8 significant bits, ties to even.
 # The last step makes the entry exactly representable in bfloat16 and makes two
 # implementations agree even where their log / cos differ in the last bit of
 # the FP64 result (they disagree only when z lies within an FP64 rounding error
@@ -115,11 +118,14 @@ def round_to_8_bits(z: np.ndarray) -> np.ndarray:
 def gaussian_sketch_matrix(seed: int, k: int, n: int, w: int) -> np.ndarray:
     """The dense n x w Gaussian sketching matrix with salt k (see above)."""
     base = mix_int(seed + GOLDEN * (1 + k))
-    idx = (np.arange(n, dtype=np.uint64)[:, None] * np.uint64(w)
-           + np.arange(w, dtype=np.uint64)[None, :])
-    h1 = mix_array(np.uint64(base) ^ (idx * np.uint64(2)))
-    h2 = mix_array(np.uint64(base) ^ (idx * np.uint64(2) + np.uint64(1)))
+    c = np.arange(w, dtype=np.uint64)
+    even = c & ~np.uint64(1)
+    q = np.arange(n, dtype=np.uint64)[:, None] * np.uint64(w) + even[None, :]
+    h1 = mix_array(np.uint64(base) ^ (q * np.uint64(2)))
+    h2 = mix_array(np.uint64(base) ^ (q * np.uint64(2) + np.uint64(1)))
     u1 = ((h1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
     u2 = (h2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    r = np.sqrt(-2.0 * np.log(u1))
+    t = 2.0 * np.pi * u2
+    z = np.where((c % np.uint64(2) == 0)[None, :], r * np.cos(t), r * np.sin(t))
     return round_to_8_bits(z)

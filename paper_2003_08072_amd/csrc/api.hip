@@ -88,6 +88,7 @@ struct skipm_lp_s {
   // Gaussian sketch: Wd = D W_G (n x w), W t for the correction vector, rocBLAS
   double* Wd = nullptr;
   double* gy = nullptr;
+  double* Bsplit = nullptr;  // K-split partial sketches of the Gaussian GEMM
   rocblas_handle blas = nullptr;
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
@@ -565,11 +566,33 @@ int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, d
     launch_gauss_fill(lp->prm.seed, salt, lp->n, lp->w, dscale, is_d2, lp->Wd, lp->n, st);
     SK_CHECK_HIP(hipGetLastError());
     const double one = 1.0, zero = 0.0;
-    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success ||
-        rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, (int)lp->lda,
-                      lp->w, (int)lp->n, &one, (const double*)lp->A, (int)lp->lda, lp->Wd,
-                      (int)lp->n, &zero, B, (int)lp->lda) != rocblas_status_success)
-      return set_error("rocblas_dgemm (Gaussian sketch) failed"), SKIPM_EDEVICE;
+    const int lda = (int)lp->lda, w = lp->w, n = (int)lp->n;
+    const double* A = (const double*)lp->A;
+    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success)
+      return set_error("rocblas_set_stream failed"), SKIPM_EDEVICE;
+    const int ns = gauss_ksplit(lp->lda, w, lp->n);
+    rocblas_status rs;
+    if (ns <= 1) {
+      rs = rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, lda, w, n,
+                         &one, A, lda, lp->Wd, n, &zero, B, lda);
+    } else {
+      // K split in ns slices (one batched GEMM, enough tiles for the GPU), the
+      // remainder of n added into slice 0, then the slices summed in order
+      const int64_t lw = lp->lda * (int64_t)w;
+      if (!lp->Bsplit) SK_TRY(dalloc(lp, &lp->Bsplit, ns * lw));
+      const int kc = n / ns, rem = n - ns * kc;
+      rs = rocblas_dgemm_strided_batched(lp->blas, rocblas_operation_none, rocblas_operation_none,
+                                         lda, w, kc, &one, A, lda, (int64_t)kc * lda, lp->Wd, n,
+                                         kc, &zero, lp->Bsplit, lda, lw, ns);
+      if (rs == rocblas_status_success && rem > 0)
+        rs = rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, lda, w, rem,
+                           &one, A + (int64_t)ns * kc * lda, lda, lp->Wd + (int64_t)ns * kc, n,
+                           &one, lp->Bsplit, lda);
+      if (rs == rocblas_status_success) launch_sum_slices(lp->Bsplit, ns, lw, B, st);
+    }
+    if (rs != rocblas_status_success)
+      return set_error("rocblas GEMM (Gaussian sketch) failed"), SKIPM_EDEVICE;
+    SK_CHECK_HIP(hipGetLastError());
     return SKIPM_OK;
   }
   SK_TRY(hash_items(lp, salt, st));
@@ -1003,9 +1026,11 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   add(8 * 8 * (int64_t)std::max(std::max(std::max(nblk_Ap, nblk_vec), nblk_csc), 64));
   add(8 * S_NSLOTS);
   add(4 * I_NINTS);
-  if (prm->sketch == SKIPM_SKETCH_GAUSSIAN) {  // D W_G and (D W_G) t
+  if (prm->sketch == SKIPM_SKETCH_GAUSSIAN) {  // D W_G, (D W_G) t, K-split slices
     add(8 * n * w);
     add(8 * n);
+    const int ns = gauss_ksplit(lda, w, n);
+    if (ns > 1) add(8 * ns * lda * w);
   }
   // correction-vector buffers (allocated at the first direction)
   add(8 * lda * w);

@@ -164,6 +164,10 @@ int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode);
 // Gaussian sketch (dense A): Wd = D W_G, n x w column-major with leading dim ldw
 void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const double* dscale,
                        int is_d2, double* Wd, int64_t ldw, hipStream_t st);
+// out[i] = sum over the ns slices part[s lw + i] (fixed order)
+void launch_sum_slices(const double* part, int ns, int64_t lw, double* out, hipStream_t st);
+// K-split of the Gaussian sketch GEMM: number of slices for m x w x n
+int gauss_ksplit(int64_t lda, int64_t w, int64_t n);
 void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t n, int s,
                          const double* dscale, int is_d2, const int32_t* ptr,
                          const int32_t* perm, const int8_t* sign, int w, double* B,

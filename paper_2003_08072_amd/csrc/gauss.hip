@@ -4,10 +4,11 @@
 // GEMM, B = A Wd (rocBLAS, FP64 on the matrix cores), and the correction
 // vector's W t is one GEMV, (W_G t)_j = (Wd t)_j / d_j.
 //
-// Entry (j, c) with salt k (the same definition as the reference generator):
-//   base = mix(seed + G (1 + k)), h1 = mix(base ^ 2(jw + c)), h2 = mix(base ^ (2(jw + c) + 1))
-//   u1 = ((h1 >> 11) + 1) 2^-53, u2 = (h2 >> 11) 2^-53
-//   z = sqrt(-2 ln u1) cos(2 pi u2), rounded to an 8-bit significand (ties to even)
+// Entries (j, c), (j, c + 1), c even, with salt k (one Box-Muller pair; the
+// same definition as the reference generator):
+//   base = mix(seed + G (1 + k)), q = jw + c, h1 = mix(base ^ 2q), h2 = mix(base ^ (2q + 1))
+//   u1 = ((h1 >> 11) + 1) 2^-53, u2 = (h2 >> 11) 2^-53, r = sqrt(-2 ln u1), t = 2 pi u2
+//   W_jc = r cos t, W_j,c+1 = r sin t, each rounded to an 8-bit significand (ties to even)
 #include "common.h"
 
 namespace skipm {
@@ -23,31 +24,54 @@ __device__ __forceinline__ uint64_t gmix(uint64_t z) {
   return z;
 }
 
-__device__ __forceinline__ double gauss_entry(uint64_t base, uint64_t idx) {
-  const uint64_t h1 = gmix(base ^ (2 * idx));
-  const uint64_t h2 = gmix(base ^ (2 * idx + 1));
-  const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
-  const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
-  const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+__device__ __forceinline__ double round8(double z) {
   int e = 0;
   const double m = frexp(z, &e);
   return ldexp(rint(ldexp(m, 8)), e - 8);
 }
 
-// Wd[j + c ldw] = d_j W_G[j, c]; one thread per (j, c), j fastest
+// Wd[j + c ldw] = d_j W_G[j, c]; one thread per (j, pair of columns), j fastest
 __global__ __launch_bounds__(256) void k_gauss_fill(uint64_t base, int64_t n, int64_t w,
                                                     const double* __restrict__ dscale, int is_d2,
                                                     double* __restrict__ Wd, int64_t ldw) {
-  const int64_t total = n * w;
+  const int64_t npair = (w + 1) / 2;
+  const int64_t total = n * npair;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t c = e / n, j = e - c * n;
+    const int64_t cp = e / n, j = e - cp * n;
+    const int64_t c = 2 * cp;
+    const uint64_t q = (uint64_t)j * (uint64_t)w + (uint64_t)c;
+    const uint64_t h1 = gmix(base ^ (2 * q));
+    const uint64_t h2 = gmix(base ^ (2 * q + 1));
+    const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    const double t = 2.0 * M_PI * u2;
     const double dj = is_d2 ? sqrt(dscale[j]) : dscale[j];
-    Wd[j + c * ldw] = dj * gauss_entry(base, (uint64_t)j * (uint64_t)w + (uint64_t)c);
+    Wd[j + c * ldw] = dj * round8(r * cos(t));
+    if (c + 1 < w) Wd[j + (c + 1) * ldw] = dj * round8(r * sin(t));
+  }
+}
+
+// out[i] = sum over s of part[s lw + i], s in order
+__global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int ns,
+                                                    int64_t lw, double* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lw; i += stride) {
+    double s = 0;
+    for (int q = 0; q < ns; ++q) s += part[(int64_t)q * lw + i];
+    out[i] = s;
   }
 }
 
 }  // namespace
+
+void launch_sum_slices(const double* part, int ns, int64_t lw, double* out, hipStream_t st) {
+  int64_t blocks = (lw + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)blocks), dim3(256), 0, st, part, ns, lw, out);
+}
 
 void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const double* dscale,
                        int is_d2, double* Wd, int64_t ldw, hipStream_t st) {
@@ -58,11 +82,20 @@ void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const dou
   z ^= z >> 27;
   z *= 0x94D049BB133111EBull;
   z ^= z >> 31;
-  int64_t blocks = (n * w + 255) / 256;
+  int64_t blocks = (n * ((w + 1) / 2) + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_gauss_fill, dim3((unsigned)blocks), dim3(256), 0, st, z, n, w, dscale,
                      is_d2, Wd, ldw);
+}
+
+int gauss_ksplit(int64_t lda, int64_t w, int64_t n) {
+  // enough 128 x 128 output tiles for the whole GPU (~512), slices of >= 1024
+  const int64_t tiles = ((lda + 127) / 128) * ((w + 127) / 128);
+  int64_t s = 512 / (tiles > 0 ? tiles : 1);
+  if (s > 16) s = 16;
+  if (s > n / 1024) s = n / 1024;
+  return s < 1 ? 1 : (int)s;
 }
 
 }  // namespace skipm

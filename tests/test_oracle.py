@@ -377,9 +377,12 @@ def test_gaussian_sketch_entries_independent_and_salted():
     assert abs(np.corrcoef(W0.ravel(), W1.ravel())[0, 1]) < lim
     assert abs(np.corrcoef(W0[:, :-1].ravel(), W0[:, 1:].ravel())[0, 1]) < lim
     assert abs(np.corrcoef(W0[:-1].ravel(), W0[1:].ravel())[0, 1]) < lim
-    # a different shape indexes the same stream: entry (j, c) is base ^ 2 (j w + c)
+    # a different number of rows indexes the same stream: pair (j, c) is base ^ 2 (j w + c)
     Wn = gaussian_sketch_matrix(7, 0, 600, 400)
     assert np.array_equal(Wn[:300], W0)
+    # the two entries of a Box-Muller pair are uncorrelated and each N(0, 1)
+    assert abs(np.corrcoef(W0[:, 0::2].ravel(), W0[:, 1::2].ravel())[0, 1]) < 2 * lim
+    assert abs(W0[:, 1::2].var() - 1.0) < 0.03
 
 
 def test_gaussian_sketch_spectrum_within_marchenko_pastur(small_lp):
@@ -416,6 +419,8 @@ def test_planted_mistake_in_gaussian_scale_fails_the_variance_pin():
     u1 = ((h1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
     u2 = (h2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     bad = np.sqrt(-np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    good = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    assert abs(good.var() - 1.0) < 0.02
     assert abs(bad.var() - 1.0) > 0.3
 
 
