@@ -17,3 +17,4 @@ from .planted import (  # noqa: F401
     sketch_seed,
     CONFIGS,
 )
+from .svm import SvmLP, svm_lp, svm_shape_lp, SVM_SHAPES  # noqa: F401

@@ -88,3 +88,53 @@ def test_device_generators_plant_an_optimum_on_cpu():
     assert np.array_equal(colidx[last], np.arange(sp.n)) and np.all(vals[last] == 1.0)
     Asp = ssp.csr_matrix((vals.astype(np.float64), colidx, rowptr), shape=(sp.m, sp.n))
     _check_device_planted(Asp, sp, 12)
+
+
+# ---------------------------------------------------------------------------
+# l1-SVM stand-in LPs (App. D.1)
+# ---------------------------------------------------------------------------
+
+def test_svm_lp_structure():
+    from lpgen import SVM_SHAPES, svm_lp
+    for dens in (1.0, 0.02):
+        lp = svm_lp(12, 80, density=dens, seed=4)
+        A = lp.A.toarray() if sp.issparse(lp.A) else lp.A
+        N = 80
+        assert A.shape == (12, 2 * N + 1)          # m x (2N + 1)
+        X = lp.X.toarray() if sp.issparse(lp.X) else lp.X
+        assert np.all(X >= 0) and np.all(np.abs(lp.y) == 1)
+        assert np.count_nonzero(lp.y > 0) == 6     # the upper half by score is class +1
+        assert np.array_equal(A[:, :N], lp.y[:, None] * X)
+        assert np.array_equal(A[:, N:2 * N], -A[:, :N])
+        assert np.array_equal(A[:, 2 * N], lp.y)
+        assert np.array_equal(lp.b, np.ones(12))
+        assert np.array_equal(lp.c, np.r_[np.ones(2 * N), 0.0])
+        assert np.all((X != 0).sum(axis=1) >= 1)
+    again = svm_lp(12, 80, density=0.02, seed=4)
+    assert (again.A != svm_lp(12, 80, density=0.02, seed=4).A).nnz == 0
+    assert set(SVM_SHAPES) == {"arcene", "dexter", "drivface", "gene_rna"}
+
+
+def test_svm_oracle_matches_an_independent_lp_solver():
+    """Pin of the oracle on the SVM LPs: HiGHS (scipy's simplex / IPM code,
+    shares nothing with the oracle) gives the same optimal value, and the
+    oracle's solution is an SVM of that l1 norm with every point on its margin."""
+    import scipy.optimize as so
+
+    from lpgen import svm_lp
+    from oracle import ipm as O
+    for m, N, dens in ((20, 300, 1.0), (30, 3000, 0.01)):
+        lp = svm_lp(m, N, density=dens, seed=1)
+        ref = so.linprog(lp.c, A_eq=lp.A, b_eq=lp.b, bounds=(0, None), method="highs")
+        assert ref.status == 0
+        A = lp.A.toarray() if sp.issparse(lp.A) else lp.A
+        X = lp.X.toarray() if sp.issparse(lp.X) else lp.X
+        for prm in (O.IPMParams(solver="sketch", sketch="gaussian", w=2 * m, seed=3, eps_gap=1e-9),
+                    O.IPMParams(solver="sketch", w=4 * m, s_nnz=2, seed=3, eps_gap=1e-9)):
+            r = O.ipm(A, lp.b, lp.c, prm)
+            assert r.status == "optimal", (m, N, prm.sketch, r.status)
+            assert abs(r.obj_p - ref.fun) <= 1e-8 * ref.fun
+            wv = r.x[:N] - r.x[N:2 * N]
+            bias = r.x[2 * N]
+            assert np.abs(lp.y * (X @ wv + bias) - 1).max() <= 1e-7
+            assert abs(np.abs(wv).sum() - ref.fun) <= 1e-7 * ref.fun
