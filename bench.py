@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6   # dense FP64 MFMA
 
 # HBM bytes per launch of the fused normal matvec on config 1, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 2.000, the factor a
@@ -56,7 +57,11 @@ def parse():
     ap.add_argument("--inner", default="cg", choices=["cg", "sd", "richardson"],
                     help="solver of Alg. 2 step (c): CG (Alg. 1), steepest descent (Alg. 4), "
                          "Richardson (Alg. 3)")
-    ap.add_argument("--sketch", default="count", choices=["count", "gaussian"],
+    ap.add_argument("--svm", default=None,
+                    help="l1-SVM stand-in LPs of the paper's Table 1 shapes: a name "
+                         "(arcene, dexter, drivface, gene_rna), a comma list or 'all'; one "
+                         "JSON line per shape (Gaussian sketch by default, gap 1e-9)")
+    ap.add_argument("--sketch", default=None, choices=["count", "gaussian"],
                     help="count: block CountSketch (Sec. 2); gaussian: dense W_G (Sec. 5)")
     ap.add_argument("--resketch", type=int, default=1, choices=[0, 1],
                     help="1: fresh W every IPM iteration; 0: one W for the whole solve")
@@ -121,14 +126,15 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_mode(sk, torch, lp, precision, s_nnz, args):
+def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
+    sketch = sketch or args.sketch or "count"
     prec = sk.SKIPM_PREC_MIXED if precision == "mixed" else sk.SKIPM_PREC_FP64
     inner = {"cg": sk.SKIPM_INNER_CG, "sd": sk.SKIPM_INNER_SD,
              "richardson": sk.SKIPM_INNER_RICHARDSON}[args.inner]
     h = sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=s_nnz,
               eps_gap=lp.eps_gap, precision=prec, max_outer=1000, inner=inner,
               resketch=args.resketch, max_cg=5000 if args.inner != "cg" else 500,
-              sketch=sk.SKIPM_SKETCH_GAUSSIAN if args.sketch == "gaussian" else sk.SKIPM_SKETCH_COUNT)
+              sketch=sk.SKIPM_SKETCH_GAUSSIAN if sketch == "gaussian" else sk.SKIPM_SKETCH_COUNT)
     stream = torch.cuda.current_stream()
     res = None
     for _ in range(args.warmup):
@@ -156,9 +162,11 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt_ms, kt_n = h.kernel_time()
+    ks_ms, ks_n = h.sketch_time()
     h.kernel_timing(0)
+    opt = getattr(lp, "opt", None)
     ok = (res.status == 0 and res.rel_gap <= lp.eps_gap
-          and abs(res.obj_p - lp.opt) <= 2 * lp.eps_gap * max(1.0, abs(lp.opt)))
+          and (opt is None or abs(res.obj_p - opt) <= 2 * lp.eps_gap * max(1.0, abs(opt))))
     # the same product launched back to back outside the solve (D^2 of the first
     # IPM iteration; HIP events around `matvec_reps` passes), for comparison.
     # reset() first: a mixed-precision run that fell back to FP64 products is
@@ -174,39 +182,44 @@ def run_mode(sk, torch, lp, precision, s_nnz, args):
         precision=precision, s=s_nnz, ok=bool(ok), status=int(res.status), solves_per_s=args.steps / wall,
         ms_per_solve=1000.0 * wall / args.steps, p50_ms=percentile(lat, 50),
         p99_ms=percentile(lat, 99), ipm_iters=iters[-1], cg_total=cg[-1],
-        rel_gap=res.rel_gap, obj_rel_err=abs(res.obj_p - lp.opt) / max(1.0, abs(lp.opt)),
+        cg_max=res.cg_max, cg_per_ipm=res.cg_total / max(1, res.iters), obj_p=res.obj_p,
+        rel_gap=res.rel_gap,
+        obj_rel_err=None if opt is None else abs(res.obj_p - opt) / max(1.0, abs(opt)),
         rp_rel=res.rp_norm / float(sum(v * v for v in lp.b) ** 0.5),
         matvec_ms=kt_ms, matvec_samples=kt_n, matvec_bytes=mv_bytes,
+        sketch_ms=ks_ms, sketch_samples=ks_n,
         matvec_gbs=mv_bytes / (kt_ms * 1e-3) / 1e9 if kt_n else None,
         matvec_b2b_ms=mv_ms, matvec_b2b_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9)
 
 
-def cpu_baseline(lp, budget):
-    """The oracle (exact-Cholesky IPM, FP64 NumPy/LAPACK) on the host cores on the
-    same LP: one full solve when one IPM iteration times 50 fits in three
-    budgets, else the first IPM iterations, scaled to 40 iterations per solve."""
+def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **prm_kw):
+    """The oracle (FP64 NumPy/LAPACK; by default its exact-Cholesky IPM) on the host
+    cores on the same LP: one full solve when one IPM iteration times 50 fits in
+    three budgets, else the first IPM iterations, scaled to `est_iters`
+    iterations per solve."""
     from oracle import ipm as O
+    A = lp.A if A is None else A
+    prm_kw = dict(solver="exact", eps_gap=lp.eps_gap, **prm_kw) if not prm_kw else \
+        dict(eps_gap=lp.eps_gap, **prm_kw)
     cores = len(os.sched_getaffinity(0))
     # time one iteration first to decide between a full solve and a sample
     t0 = time.perf_counter()
-    prm = O.IPMParams(solver="exact", eps_gap=lp.eps_gap, max_outer=1)
-    O.ipm(lp.A, lp.b, lp.c, prm)
+    O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1, **prm_kw))
     t_iter = time.perf_counter() - t0
     if t_iter * 50 <= 3 * budget:
         t0 = time.perf_counter()
-        r = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap))
+        r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1000, **prm_kw))
         t = time.perf_counter() - t0
         return dict(value=1.0 / t, unit="solves/s", cores=cores, kind="oracle",
-                    sample=f"one full exact-Cholesky IPM solve ({r.iters} iterations, "
+                    sample=f"one full {what} solve ({r.iters} iterations, "
                            f"{t:.2f} s, status {r.status})")
     k = max(1, int(budget / t_iter))
     t0 = time.perf_counter()
-    r = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap, max_outer=k))
+    r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=k, **prm_kw))
     t = time.perf_counter() - t0
     per_iter = t / max(1, r.iters)
-    est_iters = 40
     return dict(value=1.0 / (per_iter * est_iters), unit="solves/s", cores=cores, kind="oracle",
-                sample=f"first {r.iters} IPM iterations timed ({t:.2f} s), scaled to "
+                sample=f"first {r.iters} {what} iterations timed ({t:.2f} s), scaled to "
                        f"{est_iters} iterations per solve")
 
 
@@ -359,6 +372,86 @@ def run_serving(sk, torch, args):
     }
 
 
+# Table 1 of the paper (sketched IPM with preconditioned CG on the real data
+# sets, Gaussian sketch): sketch width, inner iterations, outer iterations.
+# Context for the stand-in workloads, not a target: other data, other machine.
+TABLE1 = {"arcene": (200, 30, 50), "dexter": (500, 39, 39), "drivface": (1000, 50, 42),
+          "gene_rna": (2000, 27, 44)}
+
+
+def run_svm(sk, torch, args):
+    """One JSON line per l1-SVM stand-in shape (App. D.1, Table 1 shapes)."""
+    import dataclasses
+
+    import numpy as np
+    import scipy.sparse as ssp
+
+    from lpgen import SVM_SHAPES, svm_shape_lp
+    names = list(SVM_SHAPES) if args.svm == "all" else args.svm.split(",")
+    sketch = args.sketch or "gaussian"
+    precision = "fp64" if args.precision == "both" else args.precision
+    for name in names:
+        lp = svm_shape_lp(name)
+        lp = dataclasses.replace(lp, eps_gap=1e-9)
+        if sketch == "gaussian" and ssp.issparse(lp.A):
+            lp = dataclasses.replace(lp, A=lp.A.toarray(), fmt="dense")   # W_G needs dense A
+        A_host = lp.A.toarray() if ssp.issparse(lp.A) else np.asarray(lp.A)
+        print(f"[bench] svm {name} {lp.fmt} {lp.m} x {lp.n} {sketch}", file=sys.stderr, flush=True)
+        r = run_mode(sk, torch, lp, precision, args.s, args, sketch=sketch)
+        cpu = None
+        if args.cpu_budget > 0:
+            print(f"[bench] svm {name} cpu baseline", file=sys.stderr, flush=True)
+            cpu = cpu_baseline(lp, args.cpu_budget, A=A_host, what=f"oracle {sketch}-sketch IPM",
+                               est_iters=r["ipm_iters"], solver="sketch", sketch=sketch, w=lp.w,
+                               s_nnz=args.s, seed=lp.seed)
+        w_p, in_p, out_p = TABLE1[name]
+        line = {
+            "metric": "LP solves/s (l1-SVM stand-in, rel. gap 1e-9)",
+            "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_solve"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64"
+            else "f64 (CG products f32)",
+            "data": "synthetic stand-in for the data set (seeded), resident in HBM",
+            "config": {"workload": f"l1-SVM LP, {name} shape: {SVM_SHAPES[name]['m']} points x "
+                                   f"{SVM_SHAPES[name]['N']} features, {lp.fmt} {lp.m} x {lp.n}, "
+                                   f"{sketch} sketch w={lp.w}, rel. gap 1e-9",
+                       "m": lp.m, "n": lp.n, "w": lp.w, "s": args.s, "sketch": sketch,
+                       "precision": precision},
+            "ok": r["ok"], "status": r["status"], "obj": r["obj_p"],
+            "outer_iters": r["ipm_iters"], "inner_per_outer": r["cg_per_ipm"],
+            "inner_max": r["cg_max"],
+            "paper_table1": {"w": w_p, "inner": in_p, "outer": out_p,
+                             "note": "real data set, the paper's machine: context only"},
+            "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+            "cpu_baseline": cpu,
+        }
+        product = {"bound": "hbm", "achieved": r["matvec_gbs"], "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s",
+                   "frac": (r["matvec_gbs"] / HBM_PEAK_GBS) if r["matvec_gbs"] else None,
+                   "traffic": None,
+                   "kernel": "k_colpass (fused normal matvec A D^2 A^T u)"
+                   if lp.fmt == "dense" else "k_csc_dot + k_csr_seg + k_csr_fold",
+                   "avg_ms": r["matvec_ms"], "samples": r["matvec_samples"],
+                   "bytes_per_launch": r["matvec_bytes"]}
+        if sketch == "gaussian" and r["sketch_samples"]:
+            # at these shapes the sketch GEMM B = A (D W_G) dominates the solve:
+            # 2 m n w FP64 flops per IPM iteration against the FP64 MFMA peak
+            flops = 2.0 * lp.m * lp.n * lp.w
+            tfs = flops / (r["sketch_ms"] * 1e-3) / 1e12
+            line["roofline"] = {"bound": "mfma", "achieved": tfs, "peak": FP64_PEAK_TFS,
+                                "unit": "TFLOP/s", "frac": tfs / FP64_PEAK_TFS, "traffic": None,
+                                "kernel": "rocBLAS FP64 GEMM B = A (D W_G) (K-split batched, "
+                                          "with k_sum_slices)",
+                                "avg_ms": r["sketch_ms"], "samples": r["sketch_samples"],
+                                "flops_per_launch": flops,
+                                "timing": "HIP events around the GEMM calls of every IPM "
+                                          "iteration of the timed solves"}
+            line["roofline_cg_product"] = product
+        else:
+            line["roofline"] = product
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -375,6 +468,9 @@ def main():
     from lpgen import config_lp
 
     sk.load()
+    if args.svm:
+        run_svm(sk, torch, args)
+        return
     if args.config == 3:
         print(json.dumps(run_batch(sk, torch, args)), flush=True)
         return
@@ -421,7 +517,7 @@ def main():
                                f"{'FP64' if lp.a_dtype == 'f64' else 'FP32'} planted LP, "
                                f"sketch w={lp.w}, s={args.s}, rel. gap {lp.eps_gap:g}",
                    "m": lp.m, "n": lp.n, "w": lp.w, "s": args.s,
-                   "precision": head["precision"], "inner": args.inner, "sketch": args.sketch,
+                   "precision": head["precision"], "inner": args.inner, "sketch": args.sketch or "count",
                    "resketch": args.resketch},
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],

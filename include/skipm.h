@@ -228,6 +228,13 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every);
 /* Mean duration (ms, host) of the sampled products and their number. */
 int lp_kernel_time(skipm_lp_t lp, double* avg_ms, int64_t* samples);
 
+/* While lp_kernel_timing is on (every > 0), a second HIP event pair brackets
+ * the sketch product B = A D W of each IPM iteration (Alg. 2 step (a)): for
+ * the Gaussian sketch the FP64 GEMM with its slice sum, after the fill of
+ * D W_G; for the count sketch the sketch kernel.  Mean duration (ms, host)
+ * and the number of samples since timing was last switched on. */
+int lp_sketch_time(skipm_lp_t lp, double* avg_ms, int64_t* samples);
+
 /* One iteration of Alg. 2 on the handle's iterate (steps a-g), or nothing if
  * the stopping test already holds (info->converged = 1).  info: host, may be NULL. */
 int ipm_step(skipm_lp_t lp, skipm_step_info* info, hipStream_t stream);

@@ -110,6 +110,7 @@ SIGNATURES = {
     "lp_device_bytes": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "lp_kernel_timing": (C.c_int, [_VP, C.c_int32]),
     "lp_kernel_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "lp_sketch_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lp_solve_batch": (C.c_int, [C.POINTER(_VP), C.c_int32, C.POINTER(Result), C.c_int32]),
     "srv_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.c_int32]),
     "srv_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP,
@@ -395,6 +396,12 @@ class LP:
         """(mean ms of the sampled products, number of samples)."""
         ms, n = C.c_double(), C.c_int64()
         _check(self._lib.lp_kernel_time(self.handle, C.byref(ms), C.byref(n)), "lp_kernel_time")
+        return float(ms.value), int(n.value)
+
+    def sketch_time(self):
+        """(mean ms of the timed sketch products B = A D W, number of samples)."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.lp_sketch_time(self.handle, C.byref(ms), C.byref(n)), "lp_sketch_time")
         return float(ms.value), int(n.value)
 
     def device_bytes(self) -> int:

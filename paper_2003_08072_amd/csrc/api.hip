@@ -100,6 +100,11 @@ struct skipm_lp_s {
   std::vector<int> kt_iter;       // CG iteration of each pending pair
   double kt_sum_ms = 0;
   int64_t kt_count = 0;
+  // event pair around the sketch product of every IPM iteration while timing is on
+  hipEvent_t ks_ev[2] = {nullptr, nullptr};
+  bool ks_pending = false;
+  double ks_sum_ms = 0;
+  int64_t ks_count = 0;
 };
 
 namespace {
@@ -571,6 +576,8 @@ int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, d
     if (rocblas_set_stream(lp->blas, st) != rocblas_status_success)
       return set_error("rocblas_set_stream failed"), SKIPM_EDEVICE;
     const int ns = gauss_ksplit(lp->lda, w, lp->n);
+    const bool timed = lp->kt_every > 0 && lp->ks_ev[0] && !lp->ks_pending &&
+                       hipEventRecord(lp->ks_ev[0], st) == hipSuccess;
     rocblas_status rs;
     if (ns <= 1) {
       rs = rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, lda, w, n,
@@ -593,9 +600,12 @@ int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, d
     if (rs != rocblas_status_success)
       return set_error("rocblas GEMM (Gaussian sketch) failed"), SKIPM_EDEVICE;
     SK_CHECK_HIP(hipGetLastError());
+    if (timed) lp->ks_pending = hipEventRecord(lp->ks_ev[1], st) == hipSuccess;
     return SKIPM_OK;
   }
   SK_TRY(hash_items(lp, salt, st));
+  const bool timed = lp->kt_every > 0 && lp->ks_ev[0] && !lp->ks_pending &&
+                     hipEventRecord(lp->ks_ev[0], st) == hipSuccess;
   if (lp->fmt == SKIPM_CSR)
     launch_sketch_csc(lp->sp, lp->s, dscale, is_d2, lp->bptr, lp->perm, lp->sign, lp->w, B,
                       lp->lda, st);
@@ -603,7 +613,20 @@ int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, d
     launch_sketch_dense(lp->A, lp->a_dtype, lp->lda, lp->m, lp->n, lp->s, dscale, is_d2,
                         lp->bptr, lp->perm, lp->sign, lp->w, B, lp->lda, st);
   SK_CHECK_HIP(hipGetLastError());
+  if (timed) lp->ks_pending = hipEventRecord(lp->ks_ev[1], st) == hipSuccess;
   return SKIPM_OK;
+}
+
+// adds the pending sketch-product sample once its end event has completed
+void ks_harvest(skipm_lp_s* lp) {
+  if (!lp->ks_pending) return;
+  float ms = 0;
+  if (hipEventQuery(lp->ks_ev[1]) == hipSuccess &&
+      hipEventElapsedTime(&ms, lp->ks_ev[0], lp->ks_ev[1]) == hipSuccess) {
+    lp->ks_sum_ms += ms;
+    ++lp->ks_count;
+    lp->ks_pending = false;
+  }
 }
 
 int epilogue(skipm_lp_s* lp, hipStream_t st) {
@@ -893,6 +916,7 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
   SK_TRY(sketch_into(lp, lp->d2, 1, salt, lp->B, st));
   int its = 0;
   SK_TRY(solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st));
+  ks_harvest(lp);  // the CG's host checks have waited past the sketch
   const double f0 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
   const double f1 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ]));
   lp->prev_cg = its;
@@ -1049,10 +1073,25 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every) {
     lp->kt_ev.resize(2 * kKtPairs, nullptr);
     for (auto& e : lp->kt_ev) SK_CHECK_HIP(hipEventCreate(&e));
   }
+  if (every > 0 && !lp->ks_ev[0]) {
+    SK_CHECK_HIP(hipEventCreate(&lp->ks_ev[0]));
+    SK_CHECK_HIP(hipEventCreate(&lp->ks_ev[1]));
+  }
   lp->kt_every = every;
   lp->kt_iter.clear();
   lp->kt_sum_ms = 0;
   lp->kt_count = 0;
+  lp->ks_pending = false;
+  lp->ks_sum_ms = 0;
+  lp->ks_count = 0;
+  return SKIPM_OK;
+}
+
+int lp_sketch_time(skipm_lp_t lp, double* avg_ms, int64_t* samples) {
+  if (!lp || !avg_ms || !samples) return set_error("null argument"), SKIPM_EINVAL;
+  ks_harvest(lp);
+  *samples = lp->ks_count;
+  *avg_ms = lp->ks_count ? lp->ks_sum_ms / (double)lp->ks_count : 0.0;
   return SKIPM_OK;
 }
 
@@ -1074,6 +1113,8 @@ int lp_destroy(skipm_lp_t lp) {
   hipSetDevice(lp->device);
   for (void* p : lp->allocs) hipFree(p);
   for (hipEvent_t e : lp->kt_ev)
+    if (e) hipEventDestroy(e);
+  for (hipEvent_t e : lp->ks_ev)
     if (e) hipEventDestroy(e);
   if (lp->blas) rocblas_destroy_handle(lp->blas);
   if (lp->hsc) hipHostFree(lp->hsc);
