@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=120,
                     help="config 4: requests taken from the head of the arrival trace")
     ap.add_argument("--rate", type=float, default=200.0, help="config 4: arrivals per second")
+    ap.add_argument("--find-rate", action="store_true",
+                    help="config 4: also bisect for the largest sustainable arrival rate")
+    ap.add_argument("--rate-steps", type=int, default=4,
+                    help="config 4 --find-rate: bisection steps")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0,
                     help="config 4: device memory the server may admit against")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
@@ -177,6 +181,15 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
     h.normal_matvec(u, reps=3)
     mv_ms = h.normal_matvec_timed(u, reps=args.matvec_reps)
     mv_bytes = matvec_bytes(lp, precision)
+    # cold: one product right after 512 MB of unrelated traffic (twice the
+    # 256 MB Infinity Cache), so A cannot be served from the memory-side cache
+    flush = torch.zeros(512 << 20, dtype=torch.uint8, device="cuda")
+    cold = []
+    for _ in range(5):
+        flush.add_(1)
+        cold.append(h.normal_matvec_timed(u, reps=1))
+    del flush
+    cold_ms = percentile(cold, 50)
     h.close()
     return dict(
         precision=precision, s=s_nnz, ok=bool(ok), status=int(res.status), solves_per_s=args.steps / wall,
@@ -189,7 +202,8 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         matvec_ms=kt_ms, matvec_samples=kt_n, matvec_bytes=mv_bytes,
         sketch_ms=ks_ms, sketch_samples=ks_n,
         matvec_gbs=mv_bytes / (kt_ms * 1e-3) / 1e9 if kt_n else None,
-        matvec_b2b_ms=mv_ms, matvec_b2b_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9)
+        matvec_b2b_ms=mv_ms, matvec_b2b_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9,
+        matvec_cold_ms=cold_ms, matvec_cold_gbs=mv_bytes / (cold_ms * 1e-3) / 1e9)
 
 
 def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **prm_kw):
@@ -321,6 +335,65 @@ def cpu_baseline_batch(budget):
                        f"distribution), full exact-Cholesky solves, {t_used:.1f} s")
 
 
+def serve_trace(sk, torch, args, trace, lps, scale=1.0):
+    """Replays `trace` (arrival times multiplied by `scale`) in real time against
+    a fresh request server; returns the per-request records and the stats."""
+    budget = int(args.hbm_budget_gb * 1e9)
+    srv = sk.Server(budget, slots=args.workers)
+    tickets = []
+    start = time.perf_counter()
+    s_start = srv.now()
+    for req, lp in zip(trace, lps):
+        delay = req["t"] * scale - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed,
+                                  s=args.s, eps_gap=lp.eps_gap, max_outer=1000))
+    done = [srv.wait(t)[0] for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    lat = [d.latency * 1000.0 for d in done]
+    queue_ms = [(d.t_start - d.t_submit) * 1000.0 for d in done]
+    service_ms = [(d.t_done - d.t_start) * 1000.0 for d in done]
+    span = max(d.t_done for d in done) - s_start
+    ok = [_ok(d.result, lp) for d, lp in zip(done, lps)]
+    return dict(solves_per_s=len(done) / span, span_s=span, all_ok=all(ok), n_ok=int(sum(ok)),
+                p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99),
+                queue_p50_ms=percentile(queue_ms, 50), queue_p99_ms=percentile(queue_ms, 99),
+                service_p50_ms=percentile(service_ms, 50),
+                service_p99_ms=percentile(service_ms, 99),
+                peak_hbm_in_use_gb=stats["peak_in_use"] / 1e9)
+
+
+def find_rate(sk, torch, args, trace, lps, base_rate, capacity):
+    """Largest arrival rate at which the replayed trace keeps a bounded tail:
+    p99 latency (arrival to result) at most twice the p99 at a light load of a
+    quarter of `capacity` (the throughput measured under overload).
+    Bisection on log(rate) between capacity / 4 and capacity."""
+    def trial(rate, bound):
+        r = serve_trace(sk, torch, args, trace, lps, scale=base_rate / rate)
+        ok = bound is None or r["p99_ms"] <= bound
+        print(f"[bench] rate {rate:.3g}/s: {r['solves_per_s']:.3g} solves/s, p99 "
+              f"{r['p99_ms']:.0f} ms, queue p99 {r['queue_p99_ms']:.0f} ms -> "
+              f"{'within' if ok else 'above'} the bound", file=sys.stderr, flush=True)
+        return ok, dict(rate=rate, sustained=ok, **r)
+    lo, hi = capacity / 4.0, capacity
+    trials = []
+    _, r = trial(lo, None)
+    trials.append(r)
+    bound = 2.0 * r["p99_ms"]
+    ok, r = trial(hi, bound)
+    trials.append(r)
+    if ok:
+        return hi, bound, trials
+    for _ in range(args.rate_steps):
+        mid = math.sqrt(lo * hi)
+        ok, r = trial(mid, bound)
+        trials.append(r)
+        lo, hi = (mid, hi) if ok else (lo, mid)
+    return lo, bound, trials
+
+
 def run_serving(sk, torch, args):
     """Config 4: the head of the Poisson request trace, replayed in real time
     against the request server (FIFO admission by device footprint).  Problem
@@ -334,42 +407,29 @@ def run_serving(sk, torch, args):
     torch.cuda.synchronize()
     print(f"[bench] {len(lps)} requests generated in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
-    budget = int(args.hbm_budget_gb * 1e9)
-    srv = sk.Server(budget, slots=args.workers)
-    tickets = []
-    start = time.perf_counter()
-    s_start = srv.now()
-    for req, lp in zip(trace, lps):
-        delay = req["t"] - (time.perf_counter() - start)
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(srv.submit(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed,
-                                  s=args.s, eps_gap=lp.eps_gap, max_outer=1000))
-    done = [srv.wait(t)[0] for t in tickets]
-    stats = srv.stats()
-    srv.close()
-    lat = [d.latency * 1000.0 for d in done]
-    queue_ms = [(d.t_start - d.t_submit) * 1000.0 for d in done]
-    span = max(d.t_done for d in done) - s_start
-    ok = [_ok(d.result, lp) for d, lp in zip(done, lps)]
-    return {
-        "metric": METRIC, "value": len(done) / span, "unit": "solves/s", "n_gpus": 1,
-        "steps": 1, "warmup": 0, "ms_per_step": 1000.0 * span, "higher_is_better": True,
+    r = serve_trace(sk, torch, args, trace, lps)
+    line = {
+        "metric": METRIC, "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1000.0 * r["span_s"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (A values f32)",
         "data": "synthetic planted LPs generated on the device (seeded)",
-        "config": {"workload": f"config 4: first {len(done)} requests of the Poisson trace "
+        "config": {"workload": f"config 4: first {len(lps)} requests of the Poisson trace "
                                f"({args.rate:g}/s), 50/50 dense FP32 / 1% CSR, w=4m, "
                                f"s={args.s}, {args.workers} slots, budget "
                                f"{args.hbm_budget_gb:g} GB",
-                   "requests": len(done), "rate": args.rate, "slots": args.workers,
+                   "requests": len(lps), "rate": args.rate, "slots": args.workers,
                    "s": args.s},
-        "all_ok": all(ok), "n_ok": int(sum(ok)),
-        "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-        "queue_p50_ms": percentile(queue_ms, 50), "queue_p99_ms": percentile(queue_ms, 99),
         "offered_span_s": trace[-1]["t"],
-        "peak_hbm_in_use_gb": stats["peak_in_use"] / 1e9,
         "roofline": None, "cpu_baseline": None,
     }
+    line.update({k: v for k, v in r.items() if k not in ("solves_per_s", "span_s")})
+    if args.find_rate:
+        best, bound, trials = find_rate(sk, torch, args, trace, lps, args.rate,
+                                        r["solves_per_s"])
+        line["max_sustainable_rate"] = best
+        line["sustainable_p99_bound_ms"] = bound
+        line["rate_trials"] = trials
+    return line
 
 
 # Table 1 of the paper (sketched IPM with preconditioned CG on the real data
@@ -534,7 +594,8 @@ def main():
                                "(hipExtLaunchKernelGGL) on every 8th CG product of the "
                                "timed solves",
                      "bytes_per_launch": mv["matvec_bytes"],
-                     "back_to_back_gbs": mv["matvec_b2b_gbs"]},
+                     "back_to_back_gbs": mv["matvec_b2b_gbs"],
+                     "cold_gbs": mv["matvec_cold_gbs"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

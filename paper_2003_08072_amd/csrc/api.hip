@@ -292,6 +292,11 @@ constexpr int kKtPairs = 64;
 
 // Takes an event pair for a timing sample of the product of CG iteration
 // `iter` when sampling is on; returns the pair index or -1.
+// Timing-only events: no system-scope fence (cache write-back and invalidate)
+// when they are recorded, so they do not add that cost to the interval they
+// bracket.  Results are never read through them (the stream is synchronised).
+constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
+
 int kt_take(skipm_lp_s* lp, int iter) {
   if (lp->kt_every <= 0 || iter % lp->kt_every != 0) return -1;
   const int q = (int)lp->kt_iter.size();
@@ -1071,11 +1076,11 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every) {
   SK_CHECK_HIP(hipSetDevice(lp->device));
   if (every > 0 && lp->kt_ev.empty()) {
     lp->kt_ev.resize(2 * kKtPairs, nullptr);
-    for (auto& e : lp->kt_ev) SK_CHECK_HIP(hipEventCreate(&e));
+    for (auto& e : lp->kt_ev) SK_CHECK_HIP(hipEventCreateWithFlags(&e, kTimingEvent));
   }
   if (every > 0 && !lp->ks_ev[0]) {
-    SK_CHECK_HIP(hipEventCreate(&lp->ks_ev[0]));
-    SK_CHECK_HIP(hipEventCreate(&lp->ks_ev[1]));
+    SK_CHECK_HIP(hipEventCreateWithFlags(&lp->ks_ev[0], kTimingEvent));
+    SK_CHECK_HIP(hipEventCreateWithFlags(&lp->ks_ev[1], kTimingEvent));
   }
   lp->kt_every = every;
   lp->kt_iter.clear();
@@ -1484,8 +1489,8 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   if (lp->fmt == SKIPM_CSR) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
-      SK_CHECK_HIP(hipEventCreate(&e0));
-      SK_CHECK_HIP(hipEventCreate(&e1));
+      SK_CHECK_HIP(hipEventCreateWithFlags(&e0, kTimingEvent));
+      SK_CHECK_HIP(hipEventCreateWithFlags(&e1, kTimingEvent));
       SK_CHECK_HIP(hipEventRecord(e0, st));
     }
     for (int r = 0; r < reps; ++r) SK_TRY(normal_sparse(lp, lp->cd, 1.0, nullptr, 0.0, out, nullptr, st));
@@ -1511,8 +1516,8 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
-    SK_CHECK_HIP(hipEventCreate(&e0));
-    SK_CHECK_HIP(hipEventCreate(&e1));
+    SK_CHECK_HIP(hipEventCreateWithFlags(&e0, kTimingEvent));
+    SK_CHECK_HIP(hipEventCreateWithFlags(&e1, kTimingEvent));
     SK_CHECK_HIP(hipEventRecord(e0, st));
   }
   for (int r = 0; r < reps; ++r) SK_TRY(run_colpass(cp, st));
