@@ -1,4 +1,4 @@
-// C ABI of libskipm and the host driver of the IPM (Alg. 2 with Alg. 1 inside).
+// C ABI of libskipm and the host-side control of the IPM (Alg. 2 with Alg. 1 inside).
 //
 // One IPM iteration, all on the handle's stream:
 //   prologue pass over A  -> r_d, d^2, r_p, p (eq. pdef), ||r||, c^T x, b^T y
