@@ -16,7 +16,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, 64x64 tiles of the lower
 // triangle, mirrored to the upper triangle.  G is mp x mp, column-major.
+//
+// On the FP64 matrix cores: v_mfma_f64_16x16x4 takes, in lane l, A[l%16][l/16]
+// of a 16x4 block and B[l/16][l%16] of a 4x16 block, and accumulates
+// D[l/16 + 4r][l%16] in element r of the lane's four-double accumulator.  The
+// four waves of a workgroup own 16 rows of the 64x64 tile each (four 16x16
+// blocks); 16 columns of B for both row ranges are staged in LDS per step.
 // ---------------------------------------------------------------------------
+typedef double dacc4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int64_t ldb,
                                               int64_t m, int64_t w, double* __restrict__ Gpart,
                                               int64_t mp, int64_t cols_per_split) {
@@ -33,8 +41,11 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
   const int64_t i0 = (int64_t)ti * 64, k0 = (int64_t)tk * 64;
   const int64_t cb = (int64_t)ks * cols_per_split;
   const int64_t ce = cb + cols_per_split < w ? cb + cols_per_split : w;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4] = {};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  dacc4 acc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = (dacc4)0.0;
   for (int64_t c = cb; c < ce; c += 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -51,28 +62,28 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
     }
     __syncthreads();
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) {
-      double a[4], b[4];
+    for (int s = 0; s < 4; ++s) {
+      const double a = Ai[4 * s + lk][16 * wv + li];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = Ai[cc][ty * 4 + q];
-        b[q] = Ak[cc][tx * 4 + q];
+      for (int jb = 0; jb < 4; ++jb) {
+        const double b = Ak[4 * s + lk][16 * jb + li];
+        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
       }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
     }
     __syncthreads();
   }
+  // element (i, k) of the tile, mirrored; on a diagonal tile only i >= k is
+  // written (with its mirror), so every entry has exactly one writer
   double* G = Gpart + (int64_t)ks * mp * mp;
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t i = i0 + ty * 4 + p, k = k0 + tx * 4 + q;
-      G[i + k * mp] = acc[p][q];
-      G[k + i * mp] = acc[p][q];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 16 * wv + lk + 4 * r, k = k0 + 16 * jb + li;
+      if (ti != tk || i >= k) {
+        G[i + k * mp] = acc[jb][r];
+        G[k + i * mp] = acc[jb][r];
+      }
     }
 }
 
