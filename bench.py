@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # dense FP64 MFMA
+INFINITY_CACHE_BYTES = 256 << 20
 
 # HBM bytes per launch of the fused normal matvec on config 1, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 2.000, the factor a
@@ -595,7 +596,11 @@ def main():
                                "timed solves",
                      "bytes_per_launch": mv["matvec_bytes"],
                      "back_to_back_gbs": mv["matvec_b2b_gbs"],
-                     "cold_gbs": mv["matvec_cold_gbs"]},
+                     "cold_gbs": mv["matvec_cold_gbs"],
+                     # the product's working set against the 256 MiB Infinity Cache
+                     # (memory-side cache in front of HBM): at or under it, part of
+                     # the bytes can be served from the cache
+                     "cache_resident": mv["matvec_bytes"] <= INFINITY_CACHE_BYTES},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
