@@ -15,6 +15,7 @@
 //   step pass + finalize   -> alpha_max, alpha (Alg. 2 steps e, f)
 //   update pass            -> (x, y, s) (step g), mu
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -92,6 +93,7 @@ struct skipm_lp_s {
   rocblas_handle blas = nullptr;
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
+  int64_t small_cg_bytes = 0;  // dense CG in one workgroup when A's CG copy is at most this
   std::vector<void*> allocs;
   // sampled HIP-event timing of the CG's normal-equation product (lp_kernel_timing):
   // event pairs around every kt_every-th product, harvested at the CG's host checks
@@ -442,9 +444,49 @@ int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, cons
   return SKIPM_OK;
 }
 
+// Small dense LPs: the whole CG in one workgroup (one launch, one host read).
+// Returns 1 if it ran, 0 if this LP takes the multi-workgroup path.
+int pcg_small(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
+              int* its, int* fact_fail, hipStream_t st) {
+  if (lp->fmt != SKIPM_DENSE || lp->small_cg_bytes <= 0) return 0;
+  const int ta = lp->mixed ? SKIPM_F32 : lp->a_dtype;
+  const int64_t bytes = lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4);
+  if (bytes > lp->small_cg_bytes) return 0;
+  SmallCg a;
+  a.A = lp->mixed ? (const void*)lp->A32 : lp->A;
+  a.lda = lp->lda;
+  a.m = lp->m;
+  a.n = lp->n;
+  a.d2 = lp->d2;
+  a.Qi = lp->G;
+  a.mp = lp->mp;
+  a.rhs = rhs;
+  a.x = xsol;
+  a.r = lp->cr;
+  a.z = lp->cz;
+  a.d = lp->cd;
+  a.sc = lp->sc;
+  a.is = lp->is;
+  a.tol = tol;
+  a.max_it = max_it;
+  a.inner = lp->prm.inner;
+  if (launch_cg_small(a, ta, st) != 0) return 0;
+  if (hipGetLastError() != hipSuccess) return set_error("small CG launch failed"), SKIPM_EDEVICE;
+  if (sync_read(lp, st) != SKIPM_OK) return SKIPM_EDEVICE;
+  const int32_t* hi = host_ints(lp);
+  *fact_fail = hi[I_FACT_FAIL] ? 1 : 0;
+  *its = hi[I_CG_ITERS];
+  return 1;
+}
+
 // CG on A D^2 A^T dy = rhs preconditioned by Q^{-1}; returns iterations in *its.
 int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
             int first_chunk, int* its, int* fact_fail, hipStream_t st) {
+  {
+    const int rc = pcg_small(lp, rhs, xsol, tol, max_it, its, fact_fail, st);
+    if (rc < 0) return rc;
+    if (rc == 1) return SKIPM_OK;
+  }
   SK_TRY(qinv_apply(lp, rhs, lp->cw, nullptr, st));
   launch_cg_init(lp->m, rhs, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr, 0, lp->sc,
                  lp->is, tol, max_it, 0, st);
@@ -1293,6 +1335,12 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cd, mp);
   ALLOC(lp->cd2, mp);
   lp->cg_nf = csr ? csr_fold_nblk(m) : finish_nblk(m);
+  {
+    // one-workgroup CG for small dense LPs; SKIPM_CG_SMALL_BYTES overrides the
+    // size limit of A's CG copy (0 turns it off)
+    lp->small_cg_bytes = 1 << 20;
+    if (const char* e = getenv("SKIPM_CG_SMALL_BYTES")) lp->small_cg_bytes = atoll(e);
+  }
   lp->cg_nd = colpass_nblk_dot(mp, m, SKIPM_F64);
   ALLOC(lp->cgred, lp->cg_nf + 2 * (int64_t)lp->cg_nd);
   ALLOC(lp->cq, mp);

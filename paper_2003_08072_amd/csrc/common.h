@@ -156,6 +156,30 @@ struct ColPass {
 };
 enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
 int launch_colpass(ColPass& a, hipStream_t st);
+
+// A whole CG solve in one workgroup (small dense LPs): A (lda x n, element
+// type given to the launcher), D^2 (n), Q^{-1} (mp x mp), right-hand side
+// (m); the solution goes to x, the final r, z, d to r, z, d (each may be
+// null), the scalars and counters to the same slots as the fused CG.
+struct SmallCg {
+  const void* A = nullptr;
+  int64_t lda = 0, m = 0, n = 0;
+  const double* d2 = nullptr;
+  const double* Qi = nullptr;
+  int64_t mp = 0;
+  const double* rhs = nullptr;
+  double* x = nullptr;
+  double* r = nullptr;
+  double* z = nullptr;
+  double* d = nullptr;
+  double* sc = nullptr;
+  int32_t* is = nullptr;
+  double tol = 0;
+  int max_it = 0;
+  int inner = SKIPM_INNER_CG;
+};
+// Returns -1 (and launches nothing) for shapes it does not cover.
+int launch_cg_small(const SmallCg& a, int ta, hipStream_t st);
 // workgroups of a pass (each writes one partial of nacc * m entries)
 int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode);
 

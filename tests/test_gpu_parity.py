@@ -14,7 +14,9 @@ Every case prints its name before touching the GPU.  Tolerances:
   * final objective vs the planted optimum and the exact oracle: the stopping
     tolerance eps_gap; KKT residuals <= 1e-8 ||b||, ||c||.
 """
+import contextlib
 import math
+import os
 import sys
 
 import numpy as np
@@ -47,6 +49,24 @@ def sk():
     import paper_2003_08072_amd as _sk
     _sk.load()
     return _sk
+
+
+@contextlib.contextmanager
+def cg_path(path):
+    """LPs created inside take the one-workgroup CG ('small', the default for
+    A up to 1 MiB) or the multi-workgroup fused CG ('multi')."""
+    old = os.environ.get("SKIPM_CG_SMALL_BYTES")
+    if path == "multi":
+        os.environ["SKIPM_CG_SMALL_BYTES"] = "0"
+    else:
+        os.environ.pop("SKIPM_CG_SMALL_BYTES", None)
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("SKIPM_CG_SMALL_BYTES", None)
+        else:
+            os.environ["SKIPM_CG_SMALL_BYTES"] = old
 
 
 def mid_iterate(lp, iters):
@@ -117,13 +137,14 @@ def cg_case():
     return lp, x, s
 
 
+@pytest.mark.parametrize("path", ["small", "multi"])
 @pytest.mark.parametrize("t", [1, 3, 8])
-def test_pcg_fixed_iterations_match_alg1(torch, sk, cg_case, t):
+def test_pcg_fixed_iterations_match_alg1(torch, sk, cg_case, t, path):
     lp, x, s = cg_case
-    say(f"pcg fixed t={t}")
+    say(f"pcg fixed t={t} {path}")
     d2 = x / s
     p = np.random.default_rng(t).standard_normal(lp.m)
-    with sk.LP(lp.A, lp.b, lp.c, seed=31, s=2) as h:
+    with cg_path(path), sk.LP(lp.A, lp.b, lp.c, seed=31, s=2) as h:
         dy, info = h.pcg(d2, p, 4, tol=0.0, max_it=t)
         dy = dy.cpu().numpy()
     assert info.iters == t
@@ -136,6 +157,7 @@ def test_pcg_fixed_iterations_match_alg1(torch, sk, cg_case, t):
 
 @pytest.mark.parametrize("inner,t,fmt", [("sd", 1, "dense"), ("sd", 6, "dense"),
                                          ("richardson", 1, "dense"), ("richardson", 6, "dense"),
+                                         ("sd", 6, "dense-multi"), ("richardson", 6, "dense-multi"),
                                          ("sd", 6, "csr"), ("richardson", 6, "csr")])
 def test_inner_solvers_fixed_iterations_match_oracle(torch, sk, cg_case, inner, t, fmt):
     """Steepest descent (App. B, Alg. 4) and Richardson (App. A, Alg. 3) in place
@@ -147,7 +169,8 @@ def test_inner_solvers_fixed_iterations_match_oracle(torch, sk, cg_case, inner, 
     d2 = x / s
     p = np.random.default_rng(40 + t).standard_normal(lp.m)
     A = ssp.csr_matrix(lp.A) if fmt == "csr" else lp.A
-    with sk.LP(A, lp.b, lp.c, seed=33, s=8, w=lp.n, inner=code) as h:
+    with cg_path("multi" if fmt == "dense-multi" else "small"), \
+            sk.LP(A, lp.b, lp.c, seed=33, s=8, w=lp.n, inner=code) as h:
         dy, info = h.pcg(d2, p, 2, tol=0.0, max_it=t)
         dy = dy.cpu().numpy()
     assert info.iters == t
@@ -381,6 +404,38 @@ def test_solve_f32_values(torch, sk):
     lp = dense_planted(60, 3000, rng=np.random.default_rng(4), a_dtype="f32")
     say("solve f32-valued 60 x 3000")
     with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", s=2) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_small_and_multi_workgroup_cg_agree(torch, sk, prec):
+    """The one-workgroup CG and the fused multi-workgroup CG are the same
+    iteration (their fixed-iteration iterates agree to 1e-9 in the test above);
+    full solves both meet the bar.  Their IPM trajectories are not compared
+    step by step: a CG that stops at a tolerance can stop one iteration apart
+    on rounding, and at s = 1 that changes later steps (iteration counts are
+    parity unpinned), so the counts only have to be close."""
+    lp = config_lp(0)
+    say(f"small vs multi-workgroup CG, config 0, {prec}")
+    pr = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
+    out = {}
+    for path in ("small", "multi"):
+        with cg_path(path), sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap,
+                                  precision=pr) as h:
+            out[path] = h.solve()
+    a, b = out["small"], out["multi"]
+    check_solution(lp, a, lp.eps_gap)
+    check_solution(lp, b, lp.eps_gap)
+    assert abs(a.iters - b.iters) <= max(3, b.iters // 10), (a.iters, b.iters)
+    assert abs(a.cg_total - b.cg_total) <= 0.15 * b.cg_total, (a.cg_total, b.cg_total)
+    assert abs(a.obj_p - b.obj_p) <= 2 * lp.eps_gap * abs(b.obj_p)
+
+
+def test_solve_mixed_precision_small(torch, sk):
+    lp = dense_planted(60, 2000, rng=np.random.default_rng(16))
+    say("solve mixed precision 60 x 2000 (one-workgroup CG on the FP32 copy)")
+    with sk.LP(lp.A, lp.b, lp.c, s=2, precision=sk.SKIPM_PREC_MIXED) as h:
         res = h.solve()
     check_solution(lp, res, 1e-6)
 
