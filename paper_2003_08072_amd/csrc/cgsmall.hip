@@ -80,7 +80,6 @@ __global__ __launch_bounds__(kNT) void k_cg_small(SmallCg a) {
   __shared__ double sx[LV], sr[LV], sz[LV], sd[LV], sq[LV];
   __shared__ double wbuf[kNW * LROWS];
   __shared__ double red[kNW][2];
-  __shared__ double bc[2];
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / G, lg = lane % G;
@@ -241,7 +240,6 @@ __global__ __launch_bounds__(kNT) void k_cg_small(SmallCg a) {
     ++k;
     stop = k >= a.max_it || rz <= tol2 || !(rz > 0);
   }
-  (void)bc;
   for (int i = threadIdx.x; i < m; i += kNT) {
     a.x[i] = sx[i];
     if (a.r) a.r[i] = sr[i];
