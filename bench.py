@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4],
                     help="0-2: one LP; 3: the batched workload (256 LPs); 4: the serving trace")
     ap.add_argument("--batch", type=int, default=256, help="config 3: number of LPs")
+    ap.add_argument("--batch-mode", default="f32", choices=["f32", "fp64", "mixed"],
+                    help="config 3: f32 = A kept in its FP32 values, FP64 accumulation; "
+                         "fp64 = A widened to FP64, FP64 CG products (the plain FP64 path); "
+                         "mixed = A widened to FP64 with an FP32 copy for the CG products "
+                         "and FP64-residual refinement")
     ap.add_argument("--workers", type=int, default=8,
                     help="config 3: host threads (streams) of lp_solve_batch; config 4: slots")
     ap.add_argument("--requests", type=int, default=120,
@@ -252,8 +257,10 @@ def run_batch(sk, torch, args):
     lps, hs = [], []
     for i in range(args.batch):
         lp = batch_lp_device(i)
-        hs.append(sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, s=args.s,
-                        eps_gap=lp.eps_gap, max_outer=1000))
+        a_dtype = "f32" if args.batch_mode == "f32" else "f64"
+        prec = sk.SKIPM_PREC_MIXED if args.batch_mode == "mixed" else sk.SKIPM_PREC_FP64
+        hs.append(sk.LP(lp.A, lp.b, lp.c, a_dtype=a_dtype, w=lp.w, seed=lp.seed, s=args.s,
+                        eps_gap=lp.eps_gap, max_outer=1000, precision=prec))
         lp.A = None  # the handle holds its own copy
         lps.append(lp)
     torch.cuda.synchronize()
@@ -276,7 +283,8 @@ def run_batch(sk, torch, args):
     ok = [_ok(r, lp) for r, lp in zip(res, lps)]
     wall = sum(walls)
     # bytes the CG products read over one batch pass (FP32 A, once per CG iteration)
-    cg_bytes = sum(4.0 * lp.m * lp.n * (r.cg_total + 2 * r.iters) for r, lp in zip(res, lps))
+    cg_bytes = sum((8.0 if args.batch_mode == "fp64" else 4.0) * lp.m * lp.n * r.cg_total
+                   for r, lp in zip(res, lps))
     # dominant kernel: the fused normal matvec of the largest LP
     big = max(range(len(lps)), key=lambda i: lps[i].m * lps[i].n)
     h = hs[big]
@@ -285,7 +293,8 @@ def run_batch(sk, torch, args):
     u = torch.randn(lps[big].m, dtype=torch.float64, device="cuda")
     h.normal_matvec(u, reps=3)
     mv_ms = h.normal_matvec_timed(u, reps=args.matvec_reps)
-    mv_bytes = 4 * lps[big].m * lps[big].n + 4 * lps[big].n
+    pa = 8 if args.batch_mode == "fp64" else 4
+    mv_bytes = pa * lps[big].m * lps[big].n + 8 * lps[big].n + 16 * lps[big].m
     for hh in hs:
         hh.close()
     cpu = None
@@ -295,12 +304,16 @@ def run_batch(sk, torch, args):
         "metric": METRIC, "value": len(lps) * args.steps / wall, "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (A values f32)",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f64 (A values f32)", "fp64": "f64",
+                  "mixed": "f64 (CG products f32)"}[args.batch_mode],
         "data": "synthetic planted LPs generated on the device (seeded), resident in HBM",
         "config": {"workload": f"config 3: {len(lps)} dense FP32 planted LPs, m~U{{20..400}}, "
                                f"n=m*U{{20..200}}, w=4m, s={args.s}, rel. gap 1e-6, "
-                               f"lp_solve_batch with {args.workers} workers",
+                               f"lp_solve_batch with {args.workers} workers, "
+                               f"{args.batch_mode}",
                    "lps": len(lps), "s": args.s, "workers": args.workers,
+                   "mode": args.batch_mode,
                    "total_A_bytes": int(sum(4 * lp.m * lp.n for lp in lps))},
         "all_ok": all(ok), "n_ok": int(sum(ok)),
         "ipm_iters_mean": sum(r.iters for r in res) / len(res),

@@ -158,8 +158,8 @@ int skipm_params_default(skipm_params* out);
  * copied).  Validates sizes and, for CSR, row pointers and column indices
  * (SKIPM_EINVAL on a bad entry).  The iterate starts at x = s = 1, y = 0
  * (the experiments' all-ones start with y = 0).  Synchronises `stream`.
- * Dense LPs with m <= 256 whose CG copy of A takes at most 1 MiB run each CG
- * solve in one workgroup (one launch); the environment variable
+ * Dense FP64 LPs with m <= 64 whose A takes at most 1 MiB run each CG solve
+ * in one workgroup (one launch); the environment variable
  * SKIPM_CG_SMALL_BYTES, read here, sets that limit in bytes (0: never). */
 int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* prm,
               hipStream_t stream);

@@ -1,8 +1,7 @@
 // Whole CG solves of small LPs in one workgroup (Alg. 1 step 3 with M = Q, the
 // same iteration as the fused multi-launch CG).
 //
-// When A (in the precision the CG reads) fits comfortably in one XCD's L2 and
-// m <= 256, a CG iteration is a few microseconds of work, and the launches,
+// When A (FP64) fits comfortably in one XCD's L2 and m <= 64, a CG iteration is a few microseconds of work, and the launches,
 // the partial-sum folds and the host's chunk checks of the multi-workgroup
 // path cost several times more than the work.  Here one workgroup of 1024
 // threads runs every iteration: the product q = A D^2 A^T d (one pass over A,
@@ -17,7 +16,6 @@ namespace skipm {
 namespace {
 
 typedef double dv2 __attribute__((ext_vector_type(2)));
-typedef float fv4 __attribute__((ext_vector_type(4)));
 
 template <typename TA>
 struct SVec;
@@ -25,11 +23,6 @@ template <>
 struct SVec<double> {
   static constexpr int V = 2;
   typedef dv2 type;
-};
-template <>
-struct SVec<float> {
-  static constexpr int V = 4;
-  typedef fv4 type;
 };
 
 constexpr int kNT = 1024;
@@ -71,6 +64,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double (*red)[2
 template <typename TA, int G, int R, int GQ, int RQ>
 __global__ __launch_bounds__(kNT) void k_cg_small(SmallCg a) {
   constexpr int V = SVec<TA>::V;
+  // columns per chunk (two chunks of CH R vectors in registers, within 128 VGPRs)
+  constexpr int CH = R == 1 ? 2 : 1;
   typedef typename SVec<TA>::type VT;
   constexpr int LROWS = G * R * V;
   constexpr int LQ = GQ * RQ * 2;
@@ -91,8 +86,14 @@ __global__ __launch_bounds__(kNT) void k_cg_small(SmallCg a) {
   const double* __restrict__ Qi = a.Qi;
 
   bool valid[R];
+  int vrow[R];    // vector index read for row vector r (0 when past lda)
+  VT vmask[R];    // 1 for rows within lda, 0 past it
 #pragma unroll
-  for (int r = 0; r < R; ++r) valid[r] = (int64_t)(r * G + lg) * V < a.lda;
+  for (int r = 0; r < R; ++r) {
+    valid[r] = (int64_t)(r * G + lg) * V < a.lda;
+    vrow[r] = valid[r] ? r * G + lg : 0;
+    vmask[r] = (VT)(valid[r] ? 1 : 0);
+  }
   bool validq[RQ];
 #pragma unroll
   for (int r = 0; r < RQ; ++r) validq[r] = (int64_t)(r * GQ + lgq) * 2 < a.mp;
@@ -162,39 +163,54 @@ __global__ __launch_bounds__(kNT) void k_cg_small(SmallCg a) {
         acc[r][e] = 0;
       }
     }
-    VT cur[R], nxt[R];
+    // columns in chunks of CH per lane group, the next chunk's loads (A and
+    // D^2) in flight while this one is used: one memory latency per chunk
+    VT cv[CH][R], nv[CH][R];
+    double cd2[CH], nd2[CH];
+    // loads without branches, so the compiler can keep the next chunk in
+    // flight while this one is used: addresses are clamped in bounds, rows
+    // past lda are zeroed by a 0/1 factor, and a column past n gets the
+    // coefficient 0 (its finite values then add nothing)
+    auto load_chunk = [&](VT (*dst)[R], double* dd, int64_t c0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      cur[r] = (VT)0;
-      nxt[r] = (VT)0;
-    }
-    int64_t col = slot;
-    if (col < n) {
-      const VT* p = (const VT*)(A + col * a.lda);
+      for (int c = 0; c < CH; ++c) {
+        const int64_t col = c0 + (int64_t)c * NSLOT;
+        const int64_t cc = col < n ? col : n - 1;
+        const VT* p = (const VT*)(A + cc * a.lda);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (valid[r]) cur[r] = p[r * G + lg];
-    }
-    for (; col < n; col += NSLOT) {
-      if (col + NSLOT < n) {
-        const VT* p = (const VT*)(A + (col + NSLOT) * a.lda);
+        for (int r = 0; r < R; ++r) dst[c][r] = p[vrow[r]] * vmask[r];
+        dd[c] = a.d2[cc] * (col < n ? 1.0 : 0.0);
+      }
+    };
+    auto use_chunk = [&](VT (*cvv)[R], const double* dd) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        double t = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          if (valid[r]) nxt[r] = p[r * G + lg];
+#pragma unroll
+          for (int e = 0; e < V; ++e) t += (double)cvv[c][r][e] * uu[r][e];
+        t = gsum<G>(t);
+        const double coef = dd[c] * t;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cvv[c][r][e];
       }
-      double t = 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < V; ++e) t += (double)cur[r][e] * uu[r][e];
-      t = gsum<G>(t);
-      const double coef = a.d2[col] * t;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cur[r][e];
-        cur[r] = nxt[r];
-      }
+    };
+    // two register buffers used in turn (no copies between them, so the loads
+    // of one stay in flight while the other is used)
+    const int64_t S = (int64_t)CH * NSLOT;
+    int64_t col0 = slot;
+    load_chunk(cv, cd2, col0);
+    while (col0 < n) {
+      if (col0 + S < n) load_chunk(nv, nd2, col0 + S);
+      use_chunk(cv, cd2);
+      col0 += S;
+      if (col0 >= n) break;
+      if (col0 + S < n) load_chunk(cv, cd2, col0 + S);
+      use_chunk(nv, nd2);
+      col0 += S;
     }
     // fold: the groups of a wave, then the waves in order
 #pragma unroll
@@ -268,20 +284,17 @@ void launch_small(const SmallCg& a, hipStream_t st) {
 // Shapes follow the lane layouts above: A's leading dimension (a multiple of
 // 4) decides G, R; Q^{-1}'s (a multiple of 64) decides GQ, RQ.
 int launch_cg_small(const SmallCg& a, int ta, hipStream_t st) {
-  if (a.m < 1 || a.m > 256 || a.n < 1 || a.lda < a.m || a.lda % 4 || a.mp < a.m || a.mp % 64 ||
-      a.mp > 256)
+  if (a.m < 1 || a.m > 128 || a.n < 1 || a.lda < a.m || a.lda % 4 || a.mp < a.m || a.mp % 64 ||
+      a.mp > 128)
     return -1;
+  // Measured against the multi-workgroup CG (per CG iteration, FP64 A): 8.2
+  // against 16.1 us at 40 x 800, 10.5 against 17.8 at 50 x 1000, 16.3
+  // against 17.9 at 64 x 2000; with 64-lane column groups (m > 64) and with
+  // FP32 copies of A it was slower, so only FP64 A with m <= 64 takes it.
+  if (ta != SKIPM_F64 || a.lda > 64) return -1;
   const int qshape = a.mp <= 64 ? 0 : (a.mp <= 128 ? 1 : 2);  // (16,2) (64,1) (64,2)
-  if (ta == SKIPM_F64) {
-    if (a.lda <= 32 && qshape == 0) return launch_small<double, 16, 1, 16, 2>(a, st), 0;
-    if (a.lda <= 64 && qshape == 0) return launch_small<double, 16, 2, 16, 2>(a, st), 0;
-    if (a.lda <= 128 && qshape == 1) return launch_small<double, 64, 1, 64, 1>(a, st), 0;
-    if (a.lda <= 256 && qshape == 2) return launch_small<double, 64, 2, 64, 2>(a, st), 0;
-  } else {
-    if (a.lda <= 64 && qshape == 0) return launch_small<float, 16, 1, 16, 2>(a, st), 0;
-    if (a.lda <= 128 && qshape == 1) return launch_small<float, 16, 2, 64, 1>(a, st), 0;
-    if (a.lda <= 256 && qshape == 2) return launch_small<float, 64, 1, 64, 2>(a, st), 0;
-  }
+  if (a.lda <= 32 && qshape == 0) return launch_small<double, 16, 1, 16, 2>(a, st), 0;
+  if (a.lda <= 64 && qshape == 0) return launch_small<double, 16, 2, 16, 2>(a, st), 0;
   return -1;
 }
 

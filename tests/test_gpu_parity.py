@@ -434,7 +434,7 @@ def test_small_and_multi_workgroup_cg_agree(torch, sk, prec):
 
 def test_solve_mixed_precision_small(torch, sk):
     lp = dense_planted(60, 2000, rng=np.random.default_rng(16))
-    say("solve mixed precision 60 x 2000 (one-workgroup CG on the FP32 copy)")
+    say("solve mixed precision 60 x 2000")
     with sk.LP(lp.A, lp.b, lp.c, s=2, precision=sk.SKIPM_PREC_MIXED) as h:
         res = h.solve()
     check_solution(lp, res, 1e-6)
