@@ -526,3 +526,55 @@ def test_solve_config2_full_size(torch, sk):
                max_outer=1000) as h:
         res = h.solve()
     check_solution(lp, res, lp.eps_gap)
+
+
+# ---------------------------------------------------------------------------
+# degenerate and failing problems
+# ---------------------------------------------------------------------------
+
+def _no_optimum_lp(kind):
+    rng = np.random.default_rng(5)
+    m, n = 20, 200
+    if kind == "infeasible":   # A > 0 elementwise, b < 0: no x >= 0 has A x = b
+        A = np.abs(rng.standard_normal((m, n)))
+        b = -np.ones(m)
+        c = rng.uniform(0.5, 1.5, n)
+    else:                      # A (e0 + e1) = 0 and c (e0 + e1) < 0: cost unbounded below
+        A = rng.standard_normal((m, n))
+        A[:, 1] = -A[:, 0]
+        b = A @ rng.uniform(0.5, 1.0, n)
+        c = np.ones(n)
+        c[:2] = -1.0
+    return A, b, c
+
+
+@pytest.mark.parametrize("kind", ["infeasible", "unbounded"])
+def test_solve_without_an_optimum_reports_failure(torch, sk, kind):
+    """The method assumes an optimum exists (its theorem starts from a point
+    that dominates one); without one the solve must end with an error status
+    (not converged, stalled, non-finite or rank loss), like the oracle."""
+    A, b, c = _no_optimum_lp(kind)
+    say(f"solve a {kind} LP (20 x 200, max_outer 60)")
+    with sk.LP(A, b, c, s=2, seed=4, max_outer=60) as h:
+        res = h.solve()
+    assert res.status in (sk.SKIPM_ENOTCONV, sk.SKIPM_ESTALL, sk.SKIPM_ENAN, sk.SKIPM_ERANK), res
+    ref = O.ipm(A, b, c, O.IPMParams(solver="exact", max_outer=60))
+    assert ref.status != "optimal"
+
+
+def test_solve_square_lp(torch, sk):
+    """n = m: the feasible set is the single point A^{-1} b."""
+    lp = dense_planted(24, 24, rng=np.random.default_rng(24), eps_gap=1e-8)
+    say("solve square 24 x 24")
+    with sk.LP(lp.A, lp.b, lp.c, w=4 * 24, seed=2, s=2, eps_gap=1e-8) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-8)
+
+
+def test_iteration_cap_reports_not_converged(torch, sk):
+    lp = config_lp(0)
+    say("config 0 with max_outer = 3")
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap, max_outer=3) as h:
+        res = h.solve()
+    assert res.status == sk.SKIPM_ENOTCONV
+    assert res.iters == 3
