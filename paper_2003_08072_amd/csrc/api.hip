@@ -852,19 +852,24 @@ int v_solve(skipm_lp_s* lp, int* its, double* rel_out, hipStream_t st) {
   launch_fill_f64(lp->tw, 0.0, lp->w, st);
   launch_copy_f64(lp->rv, lp->g, lp->m, st);
   launch_norm2(lp->g, lp->m, lp->sc, S_V_GG, st);
-  SK_TRY(sync_read(lp, st));
-  const double gg = lp->hsc[S_V_GG];
   *its = 0;
   *rel_out = 0.0;
-  if (!(gg > 0.0)) return SKIPM_OK;
   int K = 0;
   double rel_prev = 1.0;
+  // ||g||^2 is read with the first step's residual (one host read fewer); a
+  // zero (or non-finite) g gives t = 0 without refinement, as if tested first
   for (int step = 0; step < max_steps; ++step) {
     SK_TRY(pinv_apply(lp, K, st));
     launch_axpy(lp->tw, lp->tq, 1.0, lp->w, st);
     SK_TRY(true_residual(lp, st));
     SK_CHECK_HIP(hipGetLastError());
     SK_TRY(sync_read(lp, st));
+    const double gg = lp->hsc[S_V_GG];
+    if (!(gg > 0.0)) {
+      launch_fill_f64(lp->tw, 0.0, lp->w, st);
+      SK_CHECK_HIP(hipGetLastError());
+      return SKIPM_OK;
+    }
     const double rel = sqrt(std::max(0.0, lp->hsc[S_V_RR]) / gg);
     *its = step + 1;
     *rel_out = rel;
