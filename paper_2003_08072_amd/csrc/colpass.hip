@@ -494,21 +494,25 @@ __global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int
                                                 double* __restrict__ out,
                                                 const int32_t* __restrict__ done) {
   __shared__ double tile[16][17];
-  if (done && *done) return;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + tx;
+  // The first 16 partials per thread are requested at once and before the
+  // done flag is read: addresses clamped in bounds, no branches around the
+  // loads (so they are all in flight together); terms past nblk are scaled
+  // by 0.  Added in block order.
+  const int64_t ic = i < m ? i : m - 1;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int b = ty + 16 * q < nblk ? ty + 16 * q : nblk - 1;
+    v[q] = (double)part[(int64_t)b * ldp + off + ic];
+  }
+  if (done && *done) return;
   double acc = 0;
   if (i < m) {
-    // eight loads in flight per thread, added in block order
-    int b = ty;
-    for (; b + 7 * 16 < nblk; b += 8 * 16) {
-      double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = (double)part[(int64_t)(b + 16 * q) * ldp + off + i];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc += v[q];
-    }
-    for (; b < nblk; b += 16) acc += (double)part[(int64_t)b * ldp + off + i];
+    for (int q = 0; q < 16; ++q) acc += v[q] * (ty + 16 * q < nblk ? 1.0 : 0.0);
+    for (int b = ty + 256; b < nblk; b += 16) acc += (double)part[(int64_t)b * ldp + off + i];
   }
   tile[ty][tx] = acc;
   __syncthreads();
@@ -532,20 +536,22 @@ __global__ __launch_bounds__(256) void k_finish_dot(const double* __restrict__ p
                                                     double* __restrict__ dq_out,
                                                     const int32_t* __restrict__ done) {
   __shared__ double tile[16][17];
-  if (done && *done) return;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + tx;
+  // as in k_finish: 16 partials per thread in flight before the done flag
+  const int64_t ic = i < m ? i : m - 1;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int b = ty + 16 * q < nblk ? ty + 16 * q : nblk - 1;
+    v[q] = part[(int64_t)b * ldp + ic];
+  }
+  if (done && *done) return;
   double acc = 0;
   if (i < m) {
-    int b = ty;
-    for (; b + 7 * 16 < nblk; b += 8 * 16) {
-      double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(b + 16 * q) * ldp + i];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc += v[q];
-    }
-    for (; b < nblk; b += 16) acc += part[(int64_t)b * ldp + i];
+    for (int q = 0; q < 16; ++q) acc += v[q] * (ty + 16 * q < nblk ? 1.0 : 0.0);
+    for (int b = ty + 256; b < nblk; b += 16) acc += part[(int64_t)b * ldp + i];
   }
   tile[ty][tx] = acc;
   __syncthreads();
