@@ -330,7 +330,18 @@ __global__ __launch_bounds__(256) void k_csr_fold(const double* __restrict__ seg
   if (i < m) {
     const int64_t b = segptr[i], e = segptr[i + 1];
     double acc = 0;
-    for (int64_t s = b + lane; s < e; s += 64) acc += segsum[s];
+    // eight loads in flight per lane (rows with many segments, such as a
+    // dense row, would otherwise wait out one load latency per term); each
+    // lane still adds its terms in segment order
+    int64_t s = b + lane;
+    for (; s + 7 * 64 < e; s += 8 * 64) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = segsum[s + 64 * q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += t[q];
+    }
+    for (; s < e; s += 64) acc += segsum[s];
     acc = wsum(acc);
     v = scale * acc;
     if (add) v += beta * add[i];
