@@ -355,11 +355,17 @@ __global__ __launch_bounds__(256) void k_csr_fold(const double* __restrict__ seg
 }
 
 // Sketch from CSC: one wave per bucket accumulates B[:, b] in LDS, column by
-// column in item order (the lanes of one step touch distinct rows).
+// column in item order (the lanes of one step touch distinct rows).  The
+// items' metadata (column, coefficient, column range) is fetched 64 items at
+// a time, one per lane, and the first 64 entries of the next column are
+// requested while the current one is added, so a bucket's columns do not
+// wait out three load latencies each.  The order of the additions is the
+// plain item-by-item order.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_csc_sketch(const int32_t* __restrict__ colptr,
                                                     const int32_t* __restrict__ rowidx,
                                                     const TV* __restrict__ cval, int64_t m,
+                                                    int64_t nnz,
                                                     int s, const double* __restrict__ dsc,
                                                     int is_d2, const int32_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ perm,
@@ -374,15 +380,47 @@ __global__ __launch_bounds__(256) void k_csc_sketch(const int32_t* __restrict__ 
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   const int beg = ptr[bkt], end = ptr[bkt + 1];
-  for (int it = beg; it < end; ++it) {
-    const int item = perm[it];
-    const int64_t j = item / s;
-    const double dj = dsc[j];
-    const double coef = (double)sign[item] * (is_d2 ? sqrt(dj) : dj);
-    const int64_t cb = colptr[j], ce = colptr[j + 1];
-    for (int64_t k = cb + lane; k < ce; k += 64) acc[rowidx[k]] += coef * (double)cval[k];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int it0 = beg; it0 < end; it0 += 64) {
+    const int itl = it0 + lane;
+    long long cb_l = 0, ce_l = 0;
+    double coef_l = 0.0;
+    if (itl < end) {
+      const int item = perm[itl];
+      const int64_t j = item / s;
+      const double dj = dsc[j];
+      coef_l = (double)sign[item] * (is_d2 ? sqrt(dj) : dj);
+      cb_l = colptr[j];
+      ce_l = colptr[j + 1];
+    }
+    const int cnt = end - it0 < 64 ? end - it0 : 64;
+    // entry cb + lane of column q (an in-bounds index when the column is shorter)
+    auto head = [&](int q, int32_t& r, TV& v) -> bool {
+      const int64_t cb = __shfl(cb_l, q), ce = __shfl(ce_l, q);
+      const int64_t k = cb + lane;
+      const bool in = k < ce;
+      const int64_t kc = in ? k : (nnz > 0 ? nnz - 1 : 0);
+      r = rowidx[kc];
+      v = cval[kc];
+      return in;
+    };
+    int32_t r0 = 0;
+    TV v0 = 0;
+    bool in0 = head(0, r0, v0);
+    for (int q = 0; q < cnt; ++q) {
+      const int64_t cb = __shfl(cb_l, q), ce = __shfl(ce_l, q);
+      const double coef = __shfl(coef_l, q);
+      int32_t r1 = 0;
+      TV v1 = 0;
+      bool in1 = false;
+      if (q + 1 < cnt) in1 = head(q + 1, r1, v1);
+      if (in0) acc[r0] += coef * (double)v0;
+      for (int64_t k = cb + 64 + lane; k < ce; k += 64) acc[rowidx[k]] += coef * (double)cval[k];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      r0 = r1;
+      v0 = v1;
+      in0 = in1;
+    }
   }
   double* out = B + (int64_t)bkt * ldb;
   for (int64_t i = lane; i < ldb; i += 64) out[i] = acc[i];
@@ -527,10 +565,12 @@ void launch_sketch_csc(const SparseA& A, int s, const double* dscale, int is_d2,
   const unsigned g = (unsigned)((w + 3) / 4);
   if (A.vdt == SKIPM_F64)
     hipLaunchKernelGGL(k_csc_sketch<double>, dim3(g), dim3(256), lds, st, A.colptr, A.rowidx,
-                       (const double*)A.cval, A.m, s, dscale, is_d2, ptr, perm, sign, w, B, ldb);
+                       (const double*)A.cval, A.m, A.nnz, s, dscale, is_d2, ptr, perm, sign, w,
+                       B, ldb);
   else
     hipLaunchKernelGGL(k_csc_sketch<float>, dim3(g), dim3(256), lds, st, A.colptr, A.rowidx,
-                       (const float*)A.cval, A.m, s, dscale, is_d2, ptr, perm, sign, w, B, ldb);
+                       (const float*)A.cval, A.m, A.nnz, s, dscale, is_d2, ptr, perm, sign, w,
+                       B, ldb);
 }
 
 int csc_dot_nblk(int64_t n) {
