@@ -436,6 +436,10 @@ __global__ __launch_bounds__(NT) void k_sketch(const TA* __restrict__ A, int64_t
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int e = 0; e < V; ++e) acc[r][e] = 0;
+    // The items' metadata (column, coefficient) is fetched G items at a time,
+    // one per lane of the group, and handed round with shuffles; only the
+    // column loads are left on the chain, one column requested ahead.  The
+    // columns are added in item order.
     const int beg = ptr[b], end = ptr[b + 1];
     VT cur[R], nxt[R];
 #pragma unroll
@@ -443,35 +447,41 @@ __global__ __launch_bounds__(NT) void k_sketch(const TA* __restrict__ A, int64_t
       cur[r] = (VT)0;
       nxt[r] = (VT)0;
     }
-    int it = beg;
-    int64_t j = 0;
-    if (it < end) {
-      j = perm[it] / s;
-      const VT* p = (const VT*)(A + j * lda);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (valid[r]) cur[r] = p[r * G + lg];
-    }
-    while (it < end) {
-      const int item = perm[it];
-      const double dj = dsc[item / s];
-      const double coef = (double)sign[item] * (is_d2 ? sqrt(dj) : dj);
-      const int nit = it + 1;
-      if (nit < end) {
-        const int64_t nj = perm[nit] / s;
-        const VT* p = (const VT*)(A + nj * lda);
+    for (int it0 = beg; it0 < end; it0 += G) {
+      const int itl = it0 + lg;
+      long long jl = 0;
+      double coefl = 0.0;
+      if (itl < end) {
+        const int item = perm[itl];
+        jl = item / s;
+        const double dj = dsc[jl];
+        coefl = (double)sign[item] * (is_d2 ? sqrt(dj) : dj);
+      }
+      const int cnt = end - it0 < G ? end - it0 : G;
+      {
+        const long long j0 = __shfl(jl, 0, G);
+        const VT* p = (const VT*)(A + j0 * lda);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          if (valid[r]) nxt[r] = p[r * G + lg];
+          if (valid[r]) cur[r] = p[r * G + lg];
       }
+      for (int q = 0; q < cnt; ++q) {
+        const double coef = __shfl(coefl, q, G);
+        if (q + 1 < cnt) {
+          const long long jn = __shfl(jl, q + 1, G);
+          const VT* p = (const VT*)(A + jn * lda);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (valid[r])
+          for (int r = 0; r < R; ++r)
+            if (valid[r]) nxt[r] = p[r * G + lg];
+        }
 #pragma unroll
-          for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cur[r][e];
+        for (int r = 0; r < R; ++r)
+          if (valid[r])
 #pragma unroll
-      for (int r = 0; r < R; ++r) cur[r] = nxt[r];
-      it = nit;
+            for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cur[r][e];
+#pragma unroll
+        for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+      }
     }
     double* out = B + (int64_t)b * ldb;
 #pragma unroll
