@@ -147,8 +147,7 @@ int validate_params(const skipm_params& p, int64_t m, int64_t n) {
 }
 
 int sync_read(skipm_lp_s* lp, hipStream_t st) {
-  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
-  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc + S_NSLOTS, lp->is, I_NINTS * sizeof(int32_t),
+  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t),
                               hipMemcpyDeviceToHost, st));
   SK_CHECK_HIP(hipStreamSynchronize(st));
   return SKIPM_OK;
@@ -1394,8 +1393,10 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   }
   ALLOC(lp->red,
         (int64_t)std::max(std::max(std::max(lp->nblk_Ap, lp->nblk_vec), lp->nblk_csc), 64) * 8);
-  ALLOC(lp->sc, S_NSLOTS);
-  ALLOC(lp->is, I_NINTS);
+  // the FP64 slots and the int32 slots in one allocation, laid out as the
+  // host mirror hsc, so a host read is one copy
+  ALLOC(lp->sc, S_NSLOTS + (I_NINTS + 1) / 2);
+  lp->is = (int32_t*)(lp->sc + S_NSLOTS);
 #undef ALLOC
   if (hipHostMalloc((void**)&lp->hsc, S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t)) !=
       hipSuccess) {
