@@ -6,9 +6,11 @@
 //   hash + bucket sort     -> W of step (a)
 //   sketch pass over A     -> B = A D W (Alg. 1 step 1)
 //   Gram + Cholesky        -> Q^{-1} = (B B^T)^{-1} = L^{-T} L^{-1}
-//   CG, per iteration: normal pass over A (one read), partial sum, Q^{-1} GEMV,
-//       single-workgroup update; chunks of iterations are enqueued and the host
-//       reads the done flag once per chunk
+//   CG, per iteration: normal pass over A (one read; it also takes the stop
+//       test, beta and d_k), partial sums with d^T q, and the Q^{-1} pass that
+//       takes alpha and updates x, r, z; chunks of iterations are enqueued and
+//       the host reads the done flag once per chunk (dense FP64 LPs with
+//       m <= 64: the whole CG in one workgroup)
 //   epilogue pass over A   -> ds (eq. delshat), g = A D^2 A^T dy - p
 //   t = (A D W)^+ g by refinement on the true residual g - B t (FP64)
 //   direction pass         -> v (eq. compv), dx (eq. delxhat), step sums

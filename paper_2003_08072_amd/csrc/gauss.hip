@@ -30,26 +30,36 @@ __device__ __forceinline__ double round8(double z) {
   return ldexp(rint(ldexp(m, 8)), e - 8);
 }
 
-// Wd[j + c ldw] = d_j W_G[j, c]; one thread per (j, pair of columns), j fastest
+// Wd[j + c ldw] = d_j W_G[j, c].  Thread j of the x grid owns row j (coalesced
+// stores down each column) and kFillPairs column pairs per y block, so no
+// index division; sin(2 pi u2), cos(2 pi u2) come from one sincospi of 2 u2
+// (2 u2 is exact), which needs no range reduction of a rounded 2 pi u2.
+constexpr int kFillPairs = 8;
+
 __global__ __launch_bounds__(256) void k_gauss_fill(uint64_t base, int64_t n, int64_t w,
                                                     const double* __restrict__ dscale, int is_d2,
                                                     double* __restrict__ Wd, int64_t ldw) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double dj = is_d2 ? sqrt(dscale[j]) : dscale[j];
   const int64_t npair = (w + 1) / 2;
-  const int64_t total = n * npair;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t cp = e / n, j = e - cp * n;
-    const int64_t c = 2 * cp;
-    const uint64_t q = (uint64_t)j * (uint64_t)w + (uint64_t)c;
-    const uint64_t h1 = gmix(base ^ (2 * q));
-    const uint64_t h2 = gmix(base ^ (2 * q + 1));
-    const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
-    const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
-    const double r = sqrt(-2.0 * log(u1));
-    const double t = 2.0 * M_PI * u2;
-    const double dj = is_d2 ? sqrt(dscale[j]) : dscale[j];
-    Wd[j + c * ldw] = dj * round8(r * cos(t));
-    if (c + 1 < w) Wd[j + (c + 1) * ldw] = dj * round8(r * sin(t));
+  const uint64_t row = (uint64_t)j * (uint64_t)w;
+  for (int64_t p0 = (int64_t)blockIdx.y * kFillPairs; p0 < npair;
+       p0 += (int64_t)gridDim.y * kFillPairs) {
+    const int64_t p1 = p0 + kFillPairs < npair ? p0 + kFillPairs : npair;
+    for (int64_t cp = p0; cp < p1; ++cp) {
+      const int64_t c = 2 * cp;
+      const uint64_t q = row + (uint64_t)c;
+      const uint64_t h1 = gmix(base ^ (2 * q));
+      const uint64_t h2 = gmix(base ^ (2 * q + 1));
+      const double u1 = ((double)(h1 >> 11) + 1.0) * 0x1.0p-53;
+      const double u2 = (double)(h2 >> 11) * 0x1.0p-53;
+      const double r = sqrt(-2.0 * log(u1));
+      double sn, cs;
+      sincospi(2.0 * u2, &sn, &cs);
+      Wd[j + c * ldw] = dj * round8(r * cs);
+      if (c + 1 < w) Wd[j + (c + 1) * ldw] = dj * round8(r * sn);
+    }
   }
 }
 
@@ -82,11 +92,12 @@ void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const dou
   z ^= z >> 27;
   z *= 0x94D049BB133111EBull;
   z ^= z >> 31;
-  int64_t blocks = (n * ((w + 1) / 2) + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_gauss_fill, dim3((unsigned)blocks), dim3(256), 0, st, z, n, w, dscale,
-                     is_d2, Wd, ldw);
+  if (n <= 0 || w <= 0) return;
+  const int64_t bx = (n + 255) / 256;
+  int64_t by = ((w + 1) / 2 + kFillPairs - 1) / kFillPairs;
+  if (by > 65535) by = 65535;  // the y loop covers the rest
+  hipLaunchKernelGGL(k_gauss_fill, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, st, z, n, w,
+                     dscale, is_d2, Wd, ldw);
 }
 
 int gauss_ksplit(int64_t lda, int64_t w, int64_t n) {
