@@ -74,7 +74,7 @@ typedef struct skipm_lp_s* skipm_lp_t;
  * copies everything into library-owned buffers, so the caller may free them
  * after lp_create returns. */
 typedef struct {
-  int64_t m;               /* rows (constraints), 1 <= m <= n */
+  int64_t m;               /* rows (constraints), 1 <= m <= min(n, 2048) */
   int64_t n;               /* columns (variables) */
   int64_t nnz;             /* CSR only: number of stored entries */
   int32_t format;          /* SKIPM_DENSE or SKIPM_CSR */

@@ -1029,7 +1029,7 @@ int skipm_params_default(skipm_params* out) {
 int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* out) {
   if (!prob || !prm || !out) return set_error("null argument"), SKIPM_EINVAL;
   const int64_t m = prob->m, n = prob->n;
-  if (m < 1 || n < m || m > 2048) return set_error("need 1 <= m <= min(n, 2048)"), SKIPM_EINVAL;
+  if (m < 1 || n < m || m > kMaxM) return set_error("need 1 <= m <= min(n, 2048)"), SKIPM_EINVAL;
   SK_TRY(validate_params(*prm, m, n));
   const bool csr = prob->format == SKIPM_CSR;
   const bool f64 = prob->a_dtype == SKIPM_F64;
@@ -1214,7 +1214,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   const int64_t lda_in = prob->lda > 0 ? prob->lda : m;
   if (!csr && lda_in < m) return set_error("lda < m"), SKIPM_EINVAL;
   SK_TRY(validate_params(*prm, m, n));
-  if (m > 2048) return set_error("m <= 2048 is supported"), SKIPM_EINVAL;
+  if (m > kMaxM) return set_error("m <= 2048 is supported"), SKIPM_EINVAL;
   if (prm->sketch == SKIPM_SKETCH_GAUSSIAN && (csr || prob->a_dtype != SKIPM_F64))
     return set_error("the Gaussian sketch needs dense FP64 A"), SKIPM_EINVAL;
 

@@ -601,12 +601,16 @@ Shape pick_shape(int64_t lda, int V) {
 }
 
 // Block size from an estimate of the VGPRs a lane needs (u and accumulators in
-// the compute type, four 16-byte column buffers, ~32 for addressing): 1024
-// threads need <= 128 VGPRs, 512 threads <= 256.  DOT passes write no partial
-// sums, so they use small blocks and many of them.
+// the compute type, four 16-byte column buffers, ~32 for addressing, ~32 more
+// for the prologue's per-column terms, 8 more when FP32 columns are widened to
+// FP64): 1024 threads need <= 128 VGPRs, 512 threads <= 256.  The estimate
+// puts every instantiation that the compiler would have to spill to scratch
+// at the smaller block.  DOT passes write no partial sums, so they use small
+// blocks and many of them.
 constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
   const int nacc = mode == COL_PROLOGUE ? 2 : (mode == COL_DOT ? 0 : 1);
-  const int est = (1 + nacc) * R * V * tc_bytes / 4 + 16 * R + 32;
+  const int est = (1 + nacc) * R * V * tc_bytes / 4 + 16 * R + 32 +
+                  (mode == COL_PROLOGUE ? 32 : 0) + (V == 4 && tc_bytes == 8 ? 8 : 0);
   if (mode == COL_DOT) return 256;
   return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
@@ -625,10 +629,13 @@ template <typename TA, typename TC, int MODE>
 int dispatch(const Args& a, int nblk, hipStream_t st, hipEvent_t e0 = nullptr,
              hipEvent_t e1 = nullptr) {
   const Shape sh = pick_shape(a.lda, Vec<TA>::V);
-#define SK_CASE(GG, RR)                                              \
-  if (sh.G == GG && sh.R == RR) {                                    \
-    launch_one<TA, TC, MODE, GG, RR>(a, nblk, st, e0, e1);           \
-    return 0;                                                        \
+  // shapes that only columns longer than kMaxM would select are not built
+#define SK_CASE(GG, RR)                                                   \
+  if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                          \
+    if (sh.G == GG && sh.R == RR) {                                       \
+      launch_one<TA, TC, MODE, GG, RR>(a, nblk, st, e0, e1);              \
+      return 0;                                                           \
+    }                                                                     \
   }
   SK_CASE(16, 1) SK_CASE(16, 2)
   SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
@@ -654,10 +661,12 @@ void sketch_dispatch(const TA* A, int64_t lda, int s, const double* d2, int is_d
                      const int32_t* ptr, const int32_t* perm, const int8_t* sign, int w,
                      double* B, int64_t ldb, hipStream_t st) {
   const Shape sh = pick_shape(lda, Vec<TA>::V);
-#define SK_CASE(GG, RR)                                                              \
-  if (sh.G == GG && sh.R == RR) {                                                    \
-    launch_sketch_one<TA, GG, RR>(A, lda, s, d2, is_d2, ptr, perm, sign, w, B, ldb, st); \
-    return;                                                                          \
+#define SK_CASE(GG, RR)                                                                  \
+  if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                                         \
+    if (sh.G == GG && sh.R == RR) {                                                      \
+      launch_sketch_one<TA, GG, RR>(A, lda, s, d2, is_d2, ptr, perm, sign, w, B, ldb, st); \
+      return;                                                                            \
+    }                                                                                    \
   }
   SK_CASE(16, 1) SK_CASE(16, 2)
   SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)

@@ -31,6 +31,10 @@ void set_error(const std::string& msg);
   } while (0)
 
 constexpr int kWave = 64;
+// Largest m (rows of A) the library takes: the column passes keep a column of
+// up to this many rows in one lane group's registers, the sparse passes keep
+// an m-vector in LDS.
+constexpr int64_t kMaxM = 2048;
 
 // ---------------------------------------------------------------------------
 // device scalar slots (one FP64 array per handle)

@@ -18,7 +18,7 @@ namespace skipm {
 
 namespace {
 
-constexpr int kMaxRowsLds = 2048;
+constexpr int kMaxRowsLds = (int)kMaxM;
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll

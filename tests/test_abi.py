@@ -140,6 +140,25 @@ def test_footprint_is_host_only_and_grows_with_the_problem():
         sk.footprint(sk.Problem(m=10, n=5, format=sk.SKIPM_DENSE, a_dtype=sk.SKIPM_F64))
 
 
+def test_largest_m_is_2048():
+    """m <= 2048 (a 2048-row column fits one lane group's registers in the
+    column passes, an m-vector the sparse passes' LDS); 2049 is rejected before
+    any device call, for both formats, by lp_create and lp_footprint."""
+    lib = sk.load()
+    prm = sk.default_params()
+    h = ctypes.c_void_p()
+    for fmt in (sk.SKIPM_DENSE, sk.SKIPM_CSR):
+        prob = sk.Problem(m=2049, n=10_000, nnz=20_000, format=fmt, a_dtype=sk.SKIPM_F32,
+                          a_vals=1, a_rowptr=1, a_colidx=1, b=1, c=1)
+        assert lib.lp_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(prm), None) == \
+            sk.SKIPM_EINVAL
+        assert b"2048" in lib.skipm_last_error()
+        with pytest.raises(sk.SkipmError):
+            sk.footprint(prob)
+        prob.m = 2048
+        assert sk.footprint(prob) > 0
+
+
 def test_batch_and_server_validate_arguments_without_a_device():
     lib = sk.load()
     res = (sk.Result * 1)()

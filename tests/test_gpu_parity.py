@@ -400,6 +400,32 @@ def test_solve_config0_block_sketch(torch, sk, s_nnz):
     check_solution(lp, res, lp.eps_gap)
 
 
+@pytest.mark.parametrize("fmt,prec", [("dense-f64", "fp64"), ("dense-f64", "mixed"),
+                                      ("dense-f32", "fp64"), ("csr", "fp64")])
+def test_solve_at_the_largest_m(torch, sk, fmt, prec):
+    """m = 2048, the largest m the library takes: the column passes hold a whole
+    2048-row column in one lane group (FP64: 16 registers' worth of 16-byte
+    loads per lane), the sparse passes an m-vector in LDS, the factorisation
+    64 panels."""
+    m = 2048
+    rng = np.random.default_rng(m)
+    kw = {}
+    if fmt == "csr":
+        from lpgen import csr_planted
+        lp = csr_planted(m, 12 * m, 0.004, rng=rng)
+        kw = dict(a_dtype="f32", max_outer=1000)
+    else:
+        dt = "f32" if fmt == "dense-f32" else "f64"
+        lp = dense_planted(m, 3 * m, rng=rng, a_dtype=dt)
+        if dt == "f32":
+            kw = dict(a_dtype="f32")
+    precision = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
+    say(f"solve at the largest m: {fmt} {lp.m} x {lp.n}, {prec}, s=2")
+    with sk.LP(lp.A, lp.b, lp.c, s=2, seed=5, precision=precision, **kw) as h:
+        res = h.solve()
+    check_solution(lp, res, 1e-6)
+
+
 def test_solve_f32_values(torch, sk):
     lp = dense_planted(60, 3000, rng=np.random.default_rng(4), a_dtype="f32")
     say("solve f32-valued 60 x 3000")
