@@ -100,13 +100,30 @@ void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const dou
                      dscale, is_d2, Wd, ldw);
 }
 
+// Number of K slices for B = A Wd: the GEMM's 128 x 128 output tiles times the
+// slices is the workgroup count, and with T tiles on 256 CUs the last round
+// of workgroups runs on T s mod 256 CUs only.  Take the s (at most 32, slices
+// of at least 1024 columns) whose workgroups fill the rounds best, T s / (256
+// ceil(T s / 256)), among those with at least 512 workgroups (two per CU) when
+// there are such; ties go to the fewer slices (less to sum afterwards).
 int gauss_ksplit(int64_t lda, int64_t w, int64_t n) {
-  // enough 128 x 128 output tiles for the whole GPU (~512), slices of >= 1024
   const int64_t tiles = ((lda + 127) / 128) * ((w + 127) / 128);
-  int64_t s = 512 / (tiles > 0 ? tiles : 1);
-  if (s > 16) s = 16;
-  if (s > n / 1024) s = n / 1024;
-  return s < 1 ? 1 : (int)s;
+  int64_t smax = n / 1024;
+  if (smax > 32) smax = 32;
+  if (smax <= 1 || tiles <= 0) return 1;
+  const bool can_fill = tiles * smax >= 512;
+  int best = 1;
+  double best_eff = -1.0;
+  for (int64_t s = 1; s <= smax; ++s) {
+    const int64_t wg = tiles * s;
+    if (can_fill && wg < 512) continue;
+    const double eff = (double)wg / (256.0 * (double)((wg + 255) / 256));
+    if (eff > best_eff + 1e-12) {
+      best_eff = eff;
+      best = (int)s;
+    }
+  }
+  return best;
 }
 
 }  // namespace skipm
