@@ -42,7 +42,7 @@ struct skipm_lp_s {
   int fmt = SKIPM_DENSE, a_dtype = SKIPM_F64;
   int64_t lda = 0, mp = 0;
   skipm_params prm{};
-  int w = 0, s = 1, nb = 32;
+  int w = 0, s = 1;
   bool mixed = false;
   // device buffers
   void* A = nullptr;
@@ -268,7 +268,7 @@ int factor(skipm_lp_s* lp, double shift, hipStream_t st) {
   if (shift > 0) launch_shift_diag(lp->G, lp->mp, lp->m, shift, st);
   launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
   launch_fill_f64(lp->Xb, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
-  launch_spd_inverse(lp->G, lp->Xb, lp->Ct, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  launch_spd_inverse(lp->G, lp->Xb, lp->Ct, lp->mp, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -803,7 +803,7 @@ int true_residual(skipm_lp_s* lp, hipStream_t st) {
 int spd_inverse_checked(skipm_lp_s* lp, double* Gm, double* Xm, hipStream_t st) {
   launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
   launch_fill_f64(Xm, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
-  launch_spd_inverse(Gm, Xm, lp->Ct, lp->mp, lp->nb, lp->is + I_FACT_FAIL, st);
+  launch_spd_inverse(Gm, Xm, lp->Ct, lp->mp, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
 }
@@ -814,11 +814,11 @@ int build_vround(skipm_lp_s* lp, int K, hipStream_t st) {
   const int64_t mp = lp->mp, mm = mp * mp;
   if (K == 1) {
     launch_copy_f64(lp->M1, lp->Xb, mm, st);  // M1 = X0
-    launch_trmm(lp->Xb, mp, lp->nb, lp->B, lp->lda, lp->m, lp->w, lp->B1, lp->lda, lp->lda, st);
+    launch_trmm(lp->Xb, mp, lp->B, lp->lda, lp->m, lp->w, lp->B1, lp->lda, lp->lda, st);
     launch_gram(lp->B1, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, mp, st);
   } else {
-    launch_trmm(lp->Xv, mp, lp->nb, lp->B1, lp->lda, lp->m, lp->w, lp->B2, lp->lda, lp->lda, st);
-    launch_trmm(lp->Xv, mp, lp->nb, lp->M1, mp, mp, mp, lp->M2, mp, mp, st);  // M2 = X1 M1
+    launch_trmm(lp->Xv, mp, lp->B1, lp->lda, lp->m, lp->w, lp->B2, lp->lda, lp->lda, st);
+    launch_trmm(lp->Xv, mp, lp->M1, mp, mp, mp, lp->M2, mp, mp, st);  // M2 = X1 M1
     launch_gram(lp->B2, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, mp, st);
   }
   launch_gram_finish(lp->Gpart, lp->ksplit, lp->m, mp, lp->Gv, st);
@@ -1232,7 +1232,6 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   lp->mixed = prm->precision == SKIPM_PREC_MIXED && !csr;
   lp->lda = round_up(m, 4);
   lp->mp = round_up(m, 64);
-  lp->nb = chol_block(lp->mp);
   const int64_t mp = lp->mp, lda = lp->lda, w = lp->w;
 
   int rc = SKIPM_OK;
@@ -1360,7 +1359,6 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->tw, w);
   ALLOC(lp->tq, w);
   ALLOC(lp->B, lda * w);
-  lp->nb = chol_block(mp);
   {
     const int T = (int)(mp / 64);
     const int ntiles = T * (T + 1) / 2;

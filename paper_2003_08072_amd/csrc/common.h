@@ -263,15 +263,14 @@ void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpa
                  int ksplit, int64_t mp, hipStream_t st);
 void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, double* G,
                         hipStream_t st);
-int chol_block(int64_t mp);
-// G (mp x mp, SPD) -> G^{-1} in place via Cholesky; Xb: mp x mp scratch (holds L^{-1})
-void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int nb, int32_t* fail,
+// G (mp x mp, SPD, mp a multiple of 64) -> G^{-1} in place via Cholesky; Xb: mp x mp
+// (holds L^{-1}), Ct: mp x mp scratch
+void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int32_t* fail,
                         hipStream_t st);
 void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t st);
 // Out = X In, X block-lower-triangular mp x mp
-void launch_trmm(const double* X, int64_t mp, int nb, const double* In, int64_t ldin,
-                 int64_t nrows, int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out,
-                 hipStream_t st);
+void launch_trmm(const double* X, int64_t mp, const double* In, int64_t ldin, int64_t nrows,
+                 int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out, hipStream_t st);
 void launch_shift_trace(double* G, int64_t mp, int64_t m, double c, hipStream_t st);
 // sc[slot] = ||u||^2 over m entries (single workgroup)
 void launch_norm2(const double* u, int64_t m, double* sc, int slot, hipStream_t st);

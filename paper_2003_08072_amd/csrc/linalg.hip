@@ -475,41 +475,28 @@ void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, 
                      mp, G);
 }
 
-int chol_block(int64_t mp) { return mp > 0 ? 32 : 32; }  // mp is a multiple of 64
+// Cholesky block (panel width) of every factorisation: mp is a multiple of 64,
+// so of 32; 32 x 32 FP64 tiles keep a panel's rows in one wave's registers.
+constexpr int kNb = 32;
 
-void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int nb, int32_t* fail,
+void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int32_t* fail,
                         hipStream_t st) {
-  const int T = (int)(mp / nb);
+  const int T = (int)(mp / kNb);
   for (int k = 0; k < T; ++k) {
     const int rest = T - k - 1;
-    if (nb == 32) {
-      hipLaunchKernelGGL(k_chol_panel<32>, dim3(rest + 1), dim3(32), 0, st, G, Xb, mp, k, fail);
-      if (rest > 0)
-        hipLaunchKernelGGL(k_chol_update<32>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
-                           mp, k);
-    } else {
-      hipLaunchKernelGGL(k_chol_panel<64>, dim3(rest + 1), dim3(64), 0, st, G, Xb, mp, k, fail);
-      if (rest > 0)
-        hipLaunchKernelGGL(k_chol_update<64>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
-                           mp, k);
-    }
+    hipLaunchKernelGGL(k_chol_panel<kNb>, dim3(rest + 1), dim3(kNb), 0, st, G, Xb, mp, k, fail);
+    if (rest > 0)
+      hipLaunchKernelGGL(k_chol_update<kNb>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
+                         mp, k);
   }
   // X = L^{-1}: log2(T) levels of two launches each
   for (int half = 1; half < T; half *= 2) {
     const dim3 grid(half, half, (T + 2 * half - 1) / (2 * half));
-    if (nb == 32) {
-      hipLaunchKernelGGL(k_trinv_c<32>, grid, dim3(256), 0, st, G, Xb, Ct, mp, half, T);
-      hipLaunchKernelGGL(k_trinv_x<32>, grid, dim3(256), 0, st, Ct, Xb, mp, half, T);
-    } else {
-      hipLaunchKernelGGL(k_trinv_c<64>, grid, dim3(256), 0, st, G, Xb, Ct, mp, half, T);
-      hipLaunchKernelGGL(k_trinv_x<64>, grid, dim3(256), 0, st, Ct, Xb, mp, half, T);
-    }
+    hipLaunchKernelGGL(k_trinv_c<kNb>, grid, dim3(256), 0, st, G, Xb, Ct, mp, half, T);
+    hipLaunchKernelGGL(k_trinv_x<kNb>, grid, dim3(256), 0, st, Ct, Xb, mp, half, T);
   }
   const int npairs = T * (T + 1) / 2;
-  if (nb == 32)
-    hipLaunchKernelGGL(k_xtx<32>, dim3(npairs), dim3(256), 0, st, Xb, G, mp, T);
-  else
-    hipLaunchKernelGGL(k_xtx<64>, dim3(npairs), dim3(256), 0, st, Xb, G, mp, T);
+  hipLaunchKernelGGL(k_xtx<kNb>, dim3(npairs), dim3(256), 0, st, Xb, G, mp, T);
 }
 
 void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t st) {
@@ -517,17 +504,12 @@ void launch_shift_diag(double* G, int64_t mp, int64_t m, double rel, hipStream_t
                      rel);
 }
 
-void launch_trmm(const double* X, int64_t mp, int nb, const double* In, int64_t ldin,
-                 int64_t nrows, int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out,
-                 hipStream_t st) {
-  const int T = (int)(mp / nb);
-  const unsigned gy = (unsigned)((ncols + nb - 1) / nb);
-  if (nb == 32)
-    hipLaunchKernelGGL(k_trmm<32>, dim3(T, gy), dim3(256), 0, st, X, mp, In, ldin, nrows, ncols,
-                       Out, ldout, nrows_out);
-  else
-    hipLaunchKernelGGL(k_trmm<64>, dim3(T, gy), dim3(256), 0, st, X, mp, In, ldin, nrows, ncols,
-                       Out, ldout, nrows_out);
+void launch_trmm(const double* X, int64_t mp, const double* In, int64_t ldin, int64_t nrows,
+                 int64_t ncols, double* Out, int64_t ldout, int64_t nrows_out, hipStream_t st) {
+  const int T = (int)(mp / kNb);
+  const unsigned gy = (unsigned)((ncols + kNb - 1) / kNb);
+  hipLaunchKernelGGL(k_trmm<kNb>, dim3(T, gy), dim3(256), 0, st, X, mp, In, ldin, nrows, ncols,
+                     Out, ldout, nrows_out);
 }
 
 void launch_shift_trace(double* G, int64_t mp, int64_t m, double c, hipStream_t st) {
