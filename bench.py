@@ -212,6 +212,20 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         matvec_cold_ms=cold_ms, matvec_cold_gbs=mv_bytes / (cold_ms * 1e-3) / 1e9)
 
 
+def host_threads():
+    """Threads the oracle runs on: its BLAS/LAPACK pool (numpy's own loops are
+    single-threaded), bounded by the cores this process may use."""
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [p["num_threads"] for p in threadpool_info() if p.get("user_api") == "blas"]
+        if pools:
+            return max(1, min(cores, max(pools)))
+    except Exception:
+        pass
+    return cores
+
+
 def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **prm_kw):
     """The oracle (FP64 NumPy/LAPACK; by default its exact-Cholesky IPM) on the host
     cores on the same LP: one full solve when one IPM iteration times 50 fits in
@@ -221,7 +235,7 @@ def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **
     A = lp.A if A is None else A
     prm_kw = dict(solver="exact", eps_gap=lp.eps_gap, **prm_kw) if not prm_kw else \
         dict(eps_gap=lp.eps_gap, **prm_kw)
-    cores = len(os.sched_getaffinity(0))
+    cores = host_threads()
     # time one iteration first to decide between a full solve and a sample
     t0 = time.perf_counter()
     O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1, **prm_kw))
@@ -335,7 +349,7 @@ def cpu_baseline_batch(budget):
     the batched workload, in index order, until `budget` seconds are spent."""
     from lpgen import batch_lp
     from oracle import ipm as O
-    cores = len(os.sched_getaffinity(0))
+    cores = host_threads()
     t_used, done, i = 0.0, 0, 0
     while t_used < budget and i < 64:
         lp = batch_lp(i)
