@@ -488,6 +488,90 @@ def test_solve_is_deterministic_and_resettable(torch, sk):
     assert r1.obj_p == r2.obj_p and r1.obj_d == r2.obj_d
 
 
+@pytest.fixture(scope="module")
+def cfg1():
+    """The 500 x 100000 FP64 LP the bench times, and a positive D^2 with a
+    10^4 spread (what mid-solve iterates give the products)."""
+    lp = config_lp(1)
+    rng = np.random.default_rng(101)
+    x = rng.uniform(0.1, 10.0, lp.n)
+    s = rng.uniform(0.1, 10.0, lp.n)
+    return lp, x, s
+
+
+def test_sketch_at_full_size(torch, sk, cfg1):
+    """k_sketch at the bench's shape (n = 100000 items in 2000 buckets, s = 1)
+    against the oracle's hash turned into W."""
+    lp, x, s = cfg1
+    say("sketch at full size (500 x 100000, w=2000, s=1)")
+    d = np.sqrt(x / s)
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed) as h:
+        B = h.sketch(d, 3).cpu().numpy()
+    W = sketch_matrix(lp.seed, 3, 1, lp.n, lp.w)
+    AD = lp.A * d
+    Bref = np.asarray((W.T @ AD.T).T)
+    bound = np.asarray((abs(W).T @ abs(AD).T).T)
+    kmax = int(np.diff(W.tocsc().indptr).max())
+    assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_normal_product_at_full_size(torch, sk, cfg1, prec):
+    """The fused product A D^2 A^T u at the bench's shape and launch
+    configuration (FP64 A, or its FP32 copy with FP64 accumulation in mixed
+    precision) against the oracle's normal matrix of the same A; D^2 = x / s is
+    what the prologue of one IPM step from (x, y, s) leaves behind."""
+    lp, x, s = cfg1
+    say(f"normal product at full size, {prec}")
+    rng = np.random.default_rng(102)
+    y = rng.standard_normal(lp.m)
+    u = rng.standard_normal(lp.m)
+    precision = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, s=2, precision=precision) as h:
+        h.set_iterate(x, y, s)
+        h.step()
+        q = h.normal_matvec(u).cpu().numpy()
+    A = lp.A if prec == "fp64" else lp.A.astype(np.float32).astype(np.float64)
+    d2 = x / s
+    ref = O.normal_matrix(A, d2) @ u
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(u)))
+    assert np.all(np.abs(q - ref) <= 2 * (lp.m + lp.n) * EPS * bound)
+
+
+def test_pcg_at_full_size_matches_alg1(torch, sk, cfg1):
+    """Three FP64 CG iterations at the bench's shape (the fused three-launch CG
+    the solve runs) against Alg. 1 on the split system."""
+    lp, x, s = cfg1
+    say("pcg fixed t=3 at full size (FP64, s=1)")
+    d2 = x / s
+    p = np.random.default_rng(103).standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed) as h:
+        dy, info = h.pcg(d2, p, 6, tol=0.0, max_it=3)
+        dy = dy.cpu().numpy()
+    assert info.iters == 3
+    W = sketch_matrix(lp.seed, 6, 1, lp.n, lp.w)
+    ref = O.sketch_pcg(lp.A * np.sqrt(d2), p, W, t=3)
+    assert np.linalg.norm(dy - ref.dy) <= 1e-9 * np.linalg.norm(ref.dy)
+    assert info.f0_norm == pytest.approx(ref.f_norms[0], rel=1e-10)
+
+
+def test_mixed_pcg_at_full_size_matches_cholesky(torch, sk, cfg1):
+    """The mixed-precision CG (FP32 copy of A in the products, FP64 residual
+    refinement) at the bench's shape, run to 1e-12, against the oracle's
+    Cholesky solve of the same normal equations (kappa 2 here).  Solving with
+    the FP32-rounded A alone would leave a relative error of 6e-9; the bound
+    asks for the FP64 solution."""
+    lp, x, s = cfg1
+    say("mixed pcg to 1e-12 at full size vs Cholesky")
+    d2 = x / s
+    p = np.random.default_rng(104).standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, precision=sk.SKIPM_PREC_MIXED) as h:
+        dy, info = h.pcg(d2, p, 6, tol=1e-12, max_it=1000)
+        dy = dy.cpu().numpy()
+    ref = np.linalg.solve(O.normal_matrix(lp.A, d2), p)
+    assert np.linalg.norm(dy - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 def test_solve_config1_full_size(torch, sk):
     lp = config_lp(1)
     say("solve config 1 (500 x 100000 FP64, w=2000, s=1)")
