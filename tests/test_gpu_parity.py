@@ -21,6 +21,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from lpgen import config_lp, dense_planted
 from oracle import ipm as O
@@ -585,7 +586,6 @@ def test_solve_config1_full_size(torch, sk):
 # ---------------------------------------------------------------------------
 
 def test_csr_rejects_bad_structure(torch, sk):
-    import scipy.sparse as sp
     say("csr validation")
     lp = dense_planted(4, 30, rng=np.random.default_rng(1))
     A = sp.csr_matrix(lp.A)
@@ -628,6 +628,48 @@ def test_csr_and_dense_agree(torch, sk):
     bound = np.asarray((abs(W).T @ abs(lp.A.toarray() * np.sqrt(d2)).T).T)
     for kind in ("csr", "dense"):
         assert np.all(np.abs(out[kind][2] - Bref) <= 64 * EPS * bound + 1e-300)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    lp = config_lp(2)
+    rng = np.random.default_rng(201)
+    return lp, rng.uniform(0.1, 10.0, lp.n), rng.uniform(0.1, 10.0, lp.n)
+
+
+def test_csr_sketch_at_full_size(torch, sk, cfg2):
+    """k_csc_sketch at config 2's shape (1000 x 1000000, ~2e6 non-zeros, 4000
+    buckets) against the oracle's W."""
+    lp, x, s = cfg2
+    say("csr sketch at full size (1000 x 1000000, w=4000, s=1)")
+    d = np.sqrt(x / s)
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed) as h:
+        B = h.sketch(d, 2).cpu().numpy()
+    W = sketch_matrix(lp.seed, 2, 1, lp.n, lp.w)
+    AD = lp.A @ sp.diags(d)
+    Bref = np.asarray((AD @ W).todense())
+    bound = np.asarray((abs(AD) @ abs(W)).todense())
+    kmax = int(np.diff(W.tocsc().indptr).max())
+    assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
+
+
+def test_csr_normal_product_at_full_size(torch, sk, cfg2):
+    """The sparse product (column pass over the CSC copy, row pass over the CSR
+    segments, fold) at config 2's shape against the oracle's normal matrix."""
+    lp, x, s = cfg2
+    say("csr normal product at full size")
+    rng = np.random.default_rng(202)
+    y = rng.standard_normal(lp.m)
+    u = rng.standard_normal(lp.m)
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed, s=2) as h:
+        h.set_iterate(x, y, s)
+        h.step()
+        q = h.normal_matvec(u).cpu().numpy()
+    d2 = x / s
+    ref = O.normal_matrix(lp.A, d2) @ u
+    absA = abs(lp.A)
+    bound = absA @ (d2 * (absA.T @ np.abs(u)))
+    assert np.all(np.abs(q - ref) <= 2 * (lp.m + lp.n) * EPS * bound)
 
 
 def test_solve_config2_full_size(torch, sk):
