@@ -197,7 +197,10 @@ def test_solve_with_inner_solver(torch, sk, inner):
 # Gaussian sketch W_G (Sec. 5)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("m,n,w,k", [(37, 500, 148, 0), (64, 2000, 256, 5), (5, 64, 20, 2)])
+# the last two take the K-split GEMM (19 and 12 slices, each with a ragged
+# remainder of columns added into the first slice)
+@pytest.mark.parametrize("m,n,w,k", [(37, 500, 148, 0), (64, 2000, 256, 5), (5, 64, 20, 2),
+                                     (100, 20001, 200, 1), (300, 12345, 600, 4)])
 def test_gaussian_sketch_apply(torch, sk, m, n, w, k):
     from oracle.sketch import gaussian_sketch_matrix
     say(f"gaussian sketch m={m} n={n} w={w} k={k}")
