@@ -28,10 +28,10 @@ FP64_PEAK_TFS = 78.6   # dense FP64 MFMA
 INFINITY_CACHE_BYTES = 256 << 20
 
 # HBM bytes per launch of the fused normal matvec on config 1, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 2.000, the factor a
+# FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 1.9999, the factor a
 # 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
 # current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
-MEASURED_TRAFFIC = {(1, "mixed"): 202_001_602, (1, "fp64"): 403_380_805}
+MEASURED_TRAFFIC = {(1, "mixed"): 202_111_272, (1, "fp64"): 404_061_010}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 

@@ -73,7 +73,7 @@ struct skipm_lp_s {
   int32_t *bucket = nullptr, *perm = nullptr, *perm_raw = nullptr, *bptr = nullptr,
           *bcnt = nullptr, *bcur = nullptr;
   int8_t* sign = nullptr;
-  void* part = nullptr;
+  double* part = nullptr;  // column-pass partial sums
   double* red = nullptr;
   double* sc = nullptr;
   int32_t* is = nullptr;
@@ -239,9 +239,9 @@ int prologue(skipm_lp_s* lp, hipStream_t st) {
   cp.d2_out = lp->d2;
   SK_TRY(run_colpass(cp, st));
   // r_p = A x - b ; p = b - A (sigma mu / s + d2 r_d)
-  launch_finish(lp->part, SKIPM_F64, 2 * lp->mp, 0, cp.nblk, lp->m, 1.0, lp->b, -1.0, lp->rp,
+  launch_finish(lp->part, 2 * lp->mp, 0, cp.nblk, lp->m, 1.0, lp->b, -1.0, lp->rp,
                 nullptr, st);
-  launch_finish(lp->part, SKIPM_F64, 2 * lp->mp, lp->mp, cp.nblk, lp->m, -1.0, lp->b, 1.0, lp->p,
+  launch_finish(lp->part, 2 * lp->mp, lp->mp, cp.nblk, lp->m, -1.0, lp->b, 1.0, lp->p,
                 nullptr, st);
   launch_prologue_finalize(lp->m, lp->rp, lp->b, lp->y, lp->red, cp.nblk, lp->sc,
                            lp->origin_pending, st);
@@ -404,7 +404,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   cp.cg.sc = lp->sc;
   cp.cg.is = lp->is;
   SK_TRY(run_colpass(cp, st));
-  if (launch_finish_dot(lp->part, cp.tc, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
+  if (launch_finish_dot(lp->part, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
       lp->cg_nf)
     return set_error("fused CG: finish shape mismatch"), SKIPM_EINVAL;
   SK_TRY(cg_close_pass(lp, xsol, iter, dk, pdq, prz, done, st));
@@ -525,7 +525,7 @@ int normal_residual_fp64(skipm_lp_s* lp, const double* rhs, const double* x, hip
     cp.u = x;
     cp.d2 = lp->d2;
     SK_TRY(run_colpass(cp, st));
-    launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, rhs, 1.0, lp->rt,
+    launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, -1.0, rhs, 1.0, lp->rt,
                   nullptr, st);
   }
   SK_TRY(qinv_apply(lp, lp->rt, lp->uv1, nullptr, st));
@@ -696,7 +696,7 @@ int epilogue(skipm_lp_s* lp, hipStream_t st) {
   cp.ds_out = lp->ds;
   SK_TRY(run_colpass(cp, st));
   // g = A D^2 A^T dy - p
-  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, 1.0, lp->p, -1.0, lp->g, nullptr,
+  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, 1.0, lp->p, -1.0, lp->g, nullptr,
                 st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
@@ -741,7 +741,7 @@ int tri_apply(skipm_lp_s* lp, const double* Mat, const double* u, double* out, h
   cp.ldp = lp->mp;
   cp.nblk = 0;
   SK_TRY(run_colpass(cp, st));
-  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr,
+  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr,
                 st);
   return SKIPM_OK;
 }
@@ -794,7 +794,7 @@ int true_residual(skipm_lp_s* lp, hipStream_t st) {
   cp.ldp = lp->mp;
   cp.nblk = lp->nblk_B;
   SK_TRY(run_colpass(cp, st));
-  launch_finish(lp->part, SKIPM_F64, lp->mp, 0, cp.nblk, lp->m, -1.0, lp->g, 1.0, lp->rv, nullptr,
+  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, -1.0, lp->g, 1.0, lp->rv, nullptr,
                 st);
   launch_norm2(lp->rv, lp->m, lp->sc, S_V_RR, st);
   return SKIPM_OK;
@@ -1387,9 +1387,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_B * mp);
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A32 * mp);
     pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
-    double* pp = nullptr;
-    ALLOC(pp, pe);
-    lp->part = pp;
+    ALLOC(lp->part, pe);
   }
   ALLOC(lp->red,
         (int64_t)std::max(std::max(std::max(lp->nblk_Ap, lp->nblk_vec), lp->nblk_csc), 64) * 8);
@@ -1576,7 +1574,7 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   }
   for (int r = 0; r < reps; ++r) SK_TRY(run_colpass(cp, st));
   if (ms) SK_CHECK_HIP(hipEventRecord(e1, st));
-  launch_finish(lp->part, cp.tc, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr, st);
+  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, 1.0, nullptr, 0.0, out, nullptr, st);
   SK_CHECK_HIP(hipGetLastError());
   if (ms) {
     float tot = 0;

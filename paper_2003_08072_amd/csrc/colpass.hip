@@ -75,16 +75,6 @@ struct Args {
   CgFuse cg;
 };
 
-// Sum of v[0..n) over a wave in a fixed order (lane strides, then a butterfly).
-__device__ __forceinline__ double wave_sum_strided(const double* __restrict__ v, int n, int stride,
-                                                   int lane) {
-  double s = 0;
-  for (int p = lane; p < n; p += 64) s += v[(int64_t)p * stride];
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
-  return s;
-}
-
 template <typename TA, typename TC, int G, int R, int MODE, int NT>
 __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   constexpr int V = Vec<TA>::V;
@@ -101,7 +91,6 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   __shared__ TC lbuf[kOneStep ? NW * LROWS : NACC1 * LROWS];
   __shared__ double sred[NW][4];
 
-  if (a.done && *a.done) return;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / G, lg = lane % G;
   const int slot = wid * NGW + grp;
@@ -139,24 +128,83 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
 
   const bool cg = a.cg.on != 0;
   const bool cg_dir = cg && MODE == COL_NORMAL && a.cg.k > 0;
+  // CG close pass: d, r, q, z, x at the slot's first column are requested
+  // with the column itself (a slot of that pass owns at most one column; a
+  // later one loads its own)
+  const int64_t col_first = col;
+  double pf_d = 0, pf_r = 0, pf_q = 0, pf_z = 0, pf_x = 0;
+  if (MODE == COL_DOT && cg) {
+    const int64_t jc = col < a.n ? col : a.n - 1;
+    pf_d = a.cg.d[jc];
+    pf_r = a.cg.r[jc];
+    pf_q = a.cg.q[jc];
+    pf_z = a.cg.zz[jc];
+    pf_x = a.cg.x[jc];
+  }
   TC uu[R][V];
   double dold[R][V];
   TC acc1[R][V], acc2[R][V];
+  // u, or z_k and d_{k-1} when the pass opens a CG iteration (d_k is formed
+  // once beta_k is known).  Every load is unconditional and in bounds (rows
+  // past lda read row 0; u[0] stands in for z and d when no CG iteration
+  // opens), so no branch or select splits them from the column loads; values
+  // of rows past lda are never used.
+  double zraw[R][V];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t row0 = (int64_t)(r * G + lg) * V;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      if (cg_dir) {  // z_k and d_{k-1}; d_k is formed once beta_k is known
-        uu[r][e] = valid[r] ? (TC)a.cg.z[row0 + e] : (TC)0;
-        dold[r][e] = valid[r] ? a.cg.d_old[row0 + e] : 0.0;
-      } else {
-        uu[r][e] = (valid[r] && MODE != COL_AXPY) ? u[row0 + e] : (TC)0;
-        dold[r][e] = 0;
+      const int64_t idx = valid[r] ? row0 + e : 0;
+      uu[r][e] = MODE != COL_AXPY ? u[idx] : (TC)0;
+      zraw[r][e] = 0.0;
+      dold[r][e] = 0.0;
+      if constexpr (MODE == COL_NORMAL) {
+        const int64_t zi = cg_dir ? idx : 0;
+        zraw[r][e] = (cg_dir ? a.cg.z : (const double*)a.u)[zi];
+        dold[r][e] = (cg_dir ? a.cg.d_old : (const double*)a.u)[zi];
       }
       acc1[r][e] = 0;
       acc2[r][e] = 0;
     }
+  }
+  // the partial sums the pass opens with (r^T z, r^T r of the last iteration,
+  // or d^T q of this one), requested by wave 0 with the first columns: up to
+  // kPre per lane here, any further ones in a loop below
+  constexpr int kPre = 8;
+  const bool cg_open = cg && MODE == COL_NORMAL && a.cg.k > 0;
+  const bool cg_close = cg && MODE == COL_DOT;
+  const double* pv = cg_open ? a.cg.prz : (cg_close ? a.cg.pdq : nullptr);
+  const int pn = cg_open ? a.cg.np : (cg_close ? a.cg.nf : 0);
+  const int pst = cg_open ? 2 : 1;
+  double pre0[kPre], pre1[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    pre0[q] = 0.0;
+    pre1[q] = 0.0;
+  }
+  if (wid == 0 && pn > 0) {
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int p = lane + 64 * q;
+      const int pc = p < pn ? p : pn - 1;
+      pre0[q] = pv[(int64_t)pc * pst];
+      pre1[q] = pv[(int64_t)pc * pst + (cg_open ? 1 : 0)];  // unused unless cg_open
+    }
+  }
+  // the done flag of a finished CG is read only now, so that its latency
+  // overlaps that of the loads above (all in bounds)
+  if (a.done && *a.done) return;
+  // an empty asm "redefines" the prefetched partials here, so that their sums
+  // below stay below the done check (the compiler would otherwise start them
+  // early, and the wait for those loads would come before the flag's load)
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) asm volatile("" : "+v"(pre0[q]), "+v"(pre1[q]));
+  if (cg_dir) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int e = 0; e < V; ++e) uu[r][e] = (TC)zraw[r][e];
   }
 
   // fused CG bookkeeping at the start of the pass (every block computes the
@@ -166,12 +214,22 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   if (cg && (MODE == COL_NORMAL || MODE == COL_DOT)) {
     const int64_t k = a.cg.k;
     if (wid == 0) {
+      // sum over p = lane, lane + 64, ... in that order, then a butterfly
       double s0 = 0, s1 = 0;
-      if (MODE == COL_NORMAL && k > 0) {
-        s0 = wave_sum_strided(a.cg.prz, a.cg.np, 2, lane);
-        s1 = wave_sum_strided(a.cg.prz + 1, a.cg.np, 2, lane);
-      } else if (MODE == COL_DOT) {
-        s0 = wave_sum_strided(a.cg.pdq, a.cg.nf, 1, lane);
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) {
+        const bool in = lane + 64 * q < pn;
+        s0 += in ? pre0[q] : 0.0;
+        s1 += in && cg_open ? pre1[q] : 0.0;
+      }
+      for (int p = lane + 64 * kPre; p < pn; p += 64) {
+        s0 += pv[(int64_t)p * pst];
+        if (cg_open) s1 += pv[(int64_t)p * pst + 1];
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
       }
       if (lane == 0) {
         cgs[0] = s0;
@@ -245,10 +303,11 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
       } else if (MODE == COL_DOT) {
         if (cg) {
           if (lg == 0) {  // w_j = (Q^{-1} q)_j: update x, r, z at j
-            const double dj = a.cg.d[col];
-            const double rj = a.cg.r[col] - cg_alpha * a.cg.q[col];
-            const double zj = a.cg.zz[col] - cg_alpha * (double)dot;
-            a.cg.x[col] += cg_alpha * dj;
+            const bool pf = col == col_first;
+            const double dj = pf ? pf_d : a.cg.d[col];
+            const double rj = (pf ? pf_r : a.cg.r[col]) - cg_alpha * (pf ? pf_q : a.cg.q[col]);
+            const double zj = (pf ? pf_z : a.cg.zz[col]) - cg_alpha * (double)dot;
+            a.cg.x[col] = (pf ? pf_x : a.cg.x[col]) + cg_alpha * dj;
             a.cg.r[col] = rj;
             a.cg.zz[col] = zj;
             cg_pz += rj * zj;
@@ -744,11 +803,6 @@ int launch_colpass(ColPass& c, hipStream_t st) {
       case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, st); break;
       case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, st); break;
     }
-  } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F32) {
-    switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<float, float, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
-      case COL_DOT: rc = dispatch<float, float, COL_DOT>(a, nblk, st); break;
-    }
   }
   return rc;
 }
@@ -769,26 +823,20 @@ void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t 
 
 int finish_nblk(int64_t m) { return (int)((m + 15) / 16); }
 
-int launch_finish_dot(const void* part, int tc, int64_t ldp, int nblk, int64_t m,
-                      const double* dvec, double* out, double* dq_out, const int32_t* done,
-                      hipStream_t st) {
-  if (tc != SKIPM_F64) return -1;
+int launch_finish_dot(const double* part, int64_t ldp, int nblk, int64_t m, const double* dvec,
+                      double* out, double* dq_out, const int32_t* done, hipStream_t st) {
   const int blocks = finish_nblk(m);
-  hipLaunchKernelGGL(k_finish_dot, dim3(blocks), dim3(256), 0, st, (const double*)part, ldp, nblk,
-                     m, dvec, out, dq_out, done);
+  hipLaunchKernelGGL(k_finish_dot, dim3(blocks), dim3(256), 0, st, part, ldp, nblk, m, dvec, out,
+                     dq_out, done);
   return blocks;
 }
 
-void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,
+void launch_finish(const double* part, int64_t ldp, int64_t off, int nblk, int64_t m,
                    double scale, const double* add, double beta, double* out,
                    const int32_t* done, hipStream_t st) {
   const unsigned blocks = (unsigned)((m + 15) / 16);
-  if (tc == SKIPM_F64)
-    hipLaunchKernelGGL(k_finish<double>, dim3(blocks), dim3(256), 0, st, (const double*)part,
-                       ldp, off, nblk, m, scale, add, beta, out, done);
-  else
-    hipLaunchKernelGGL(k_finish<float>, dim3(blocks), dim3(256), 0, st, (const float*)part, ldp,
-                       off, nblk, m, scale, add, beta, out, done);
+  hipLaunchKernelGGL(k_finish<double>, dim3(blocks), dim3(256), 0, st, part, ldp, off, nblk, m,
+                     scale, add, beta, out, done);
 }
 
 }  // namespace skipm

@@ -135,7 +135,7 @@ struct ColPass {
   int mode;                 // see COL_* below
   const void* A;            // column-major, element type ta
   int ta;                   // SKIPM_F64 / SKIPM_F32
-  int tc;                   // accumulate in SKIPM_F64 / SKIPM_F32
+  int tc;                   // accumulation type: SKIPM_F64 (the only one built)
   int64_t lda, m, n;
   const void* u;            // m-vector (type tc) for the column dots
   const double* x;          // per-column inputs (FP64)
@@ -204,12 +204,11 @@ void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t 
 // sum of partials along the block axis: out[i] = scale*sum_b part[b][off+i] + beta*add[i]
 // launch_finish plus, per workgroup of 16 rows, the partial sum of dvec_i out_i
 // (dq_out[blockIdx]); returns the number of workgroups
-int launch_finish_dot(const void* part, int tc, int64_t ldp, int nblk, int64_t m,
-                      const double* dvec, double* out, double* dq_out, const int32_t* done,
-                      hipStream_t st);
+int launch_finish_dot(const double* part, int64_t ldp, int nblk, int64_t m, const double* dvec,
+                      double* out, double* dq_out, const int32_t* done, hipStream_t st);
 int finish_nblk(int64_t m);
 int colpass_nblk_dot(int64_t lda, int64_t n, int ta);
-void launch_finish(const void* part, int tc, int64_t ldp, int64_t off, int nblk, int64_t m,
+void launch_finish(const double* part, int64_t ldp, int64_t off, int nblk, int64_t m,
                    double scale, const double* add, double beta, double* out,
                    const int32_t* done, hipStream_t st);
 
