@@ -144,11 +144,10 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   TC uu[R][V];
   double dold[R][V];
   TC acc1[R][V], acc2[R][V];
-  // u, or z_k and d_{k-1} when the pass opens a CG iteration (d_k is formed
-  // once beta_k is known).  Every load is unconditional and in bounds (rows
-  // past lda read row 0; u[0] stands in for z and d when no CG iteration
-  // opens), so no branch or select splits them from the column loads; values
-  // of rows past lda are never used.
+  // u, and z_k and d_{k-1} when the pass opens a CG iteration (d_k is formed
+  // once beta_k is known).  Every load is in bounds (rows past lda read row
+  // 0; their values are never used) and no select waits on a loaded value
+  // before the done check below.
   double zraw[R][V];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -157,15 +156,20 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
     for (int e = 0; e < V; ++e) {
       const int64_t idx = valid[r] ? row0 + e : 0;
       uu[r][e] = MODE != COL_AXPY ? u[idx] : (TC)0;
-      zraw[r][e] = 0.0;
-      dold[r][e] = 0.0;
-      if constexpr (MODE == COL_NORMAL) {
-        const int64_t zi = cg_dir ? idx : 0;
-        zraw[r][e] = (cg_dir ? a.cg.z : (const double*)a.u)[zi];
-        dold[r][e] = (cg_dir ? a.cg.d_old : (const double*)a.u)[zi];
-      }
       acc1[r][e] = 0;
       acc2[r][e] = 0;
+    }
+  }
+  if (cg_dir) {  // z and d are read (and defined) only when a CG iteration opens
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t row0 = (int64_t)(r * G + lg) * V;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int64_t idx = valid[r] ? row0 + e : 0;
+        zraw[r][e] = a.cg.z[idx];
+        dold[r][e] = a.cg.d_old[idx];
+      }
     }
   }
   // the partial sums the pass opens with (r^T z, r^T r of the last iteration,
