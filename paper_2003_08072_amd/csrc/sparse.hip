@@ -164,26 +164,71 @@ template <typename TV, int MODE>
 __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
   __shared__ double us[kMaxRowsLds];
   __shared__ double sred[4][2];
-  if (a.done && *a.done) return;
-  if (MODE == COL_NORMAL && a.cg.on && a.cg.k > 0) {
-    // the same sums in the same order in every workgroup: the same decision
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x < 64) {
-      double s0 = 0, s1 = 0;
-      for (int p = lane; p < a.cg.np; p += 64) {
-        s0 += a.cg.prz[2 * p];
-        s1 += a.cg.prz[2 * p + 1];
-      }
+  const int lane = threadIdx.x & 63;
+  const bool cg_open = MODE == COL_NORMAL && a.cg.on && a.cg.k > 0;
+  // Everything the pass starts from is requested before the done flag is
+  // read, so that the start waits one memory latency: the range of the
+  // thread's first column, the m-vector entries it stages into LDS (u, or z_k
+  // and d_{k-1} when a CG iteration opens), and the partial sums r^T z, r^T r
+  // (wave 0; up to kPre per lane, any further ones in a loop below).  Every
+  // index is clamped in bounds; clamped values are never used.
+  const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j0c = j0 < a.n ? j0 : a.n - 1;
+  const int64_t cb0 = a.colptr[j0c], ce0 = a.colptr[j0c + 1];
+  // (the first kSt * 256 rows; rows beyond are staged in a loop below)
+  constexpr int kSt = 4;
+  double st0[kSt], st1[kSt];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        s0 += __shfl_xor(s0, off, 64);
-        s1 += __shfl_xor(s1, off, 64);
-      }
-      if (lane == 0) {
-        sred[0][0] = s0;
-        sred[0][1] = s1;
-      }
+  for (int q = 0; q < kSt; ++q) {
+    const int64_t i = threadIdx.x + 256 * q;
+    const int64_t ic = i < a.m ? i : 0;
+    if (cg_open) {
+      st0[q] = a.cg.z[ic];
+      st1[q] = a.cg.d_old[ic];
+    } else {
+      st0[q] = a.u[ic];
     }
+  }
+  // wave 0 of a pass that opens a CG iteration requests the partial sums
+  // (up to kPre per lane; any further ones in a loop) before it reads the
+  // done flag, and sums them in the order p = lane, lane + 64, ..., then a
+  // butterfly: the same sums in the same order in every workgroup, hence the
+  // same decision
+  if (cg_open && threadIdx.x < 64) {
+    constexpr int kPre = 4;
+    const int pn = a.cg.np;
+    double pre0[kPre], pre1[kPre];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int p = lane + 64 * q;
+      const int pc = p < pn ? p : pn - 1;
+      pre0[q] = a.cg.prz[2 * (int64_t)pc];
+      pre1[q] = a.cg.prz[2 * (int64_t)pc + 1];
+    }
+    if (a.done && *a.done) return;
+    double s0 = 0, s1 = 0;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const bool in = lane + 64 * q < pn;
+      s0 += in ? pre0[q] : 0.0;
+      s1 += in ? pre1[q] : 0.0;
+    }
+    for (int p = lane + 64 * kPre; p < pn; p += 64) {
+      s0 += a.cg.prz[2 * p];
+      s1 += a.cg.prz[2 * p + 1];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+    }
+    if (lane == 0) {
+      sred[0][0] = s0;
+      sred[0][1] = s1;
+    }
+  }
+  if (a.done && *a.done) return;
+  if (cg_open) {
     __syncthreads();
     const int64_t k = a.cg.k;
     double* sc = a.cg.sc;
@@ -202,13 +247,27 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
       if (stop) is[I_CG_DONE] = 1;
     }
     if (stop) return;
-    for (int64_t i = threadIdx.x; i < a.m; i += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kSt; ++q) {
+      const int64_t i = threadIdx.x + 256 * q;
+      if (i < a.m) {
+        const double di = st0[q] + beta * st1[q];
+        us[i] = di;
+        if (blockIdx.x == 0) a.cg.d_new[i] = di;
+      }
+    }
+    for (int64_t i = threadIdx.x + 256 * kSt; i < a.m; i += 256) {
       const double di = a.cg.z[i] + beta * a.cg.d_old[i];
       us[i] = di;
       if (blockIdx.x == 0) a.cg.d_new[i] = di;
     }
   } else {
-    for (int64_t i = threadIdx.x; i < a.m; i += blockDim.x) us[i] = a.u[i];
+#pragma unroll
+    for (int q = 0; q < kSt; ++q) {
+      const int64_t i = threadIdx.x + 256 * q;
+      if (i < a.m) us[i] = st0[q];
+    }
+    for (int64_t i = threadIdx.x + 256 * kSt; i < a.m; i += 256) us[i] = a.u[i];
   }
   __syncthreads();
   const TV* __restrict__ cv = (const TV*)a.cval;
@@ -219,8 +278,8 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
   }
   double r0 = 0, r1 = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-    const int64_t b = a.colptr[j], e = a.colptr[j + 1];
+  for (int64_t j = j0; j < a.n; j += stride) {
+    const int64_t b = j == j0 ? cb0 : a.colptr[j], e = j == j0 ? ce0 : a.colptr[j + 1];
     double t = 0;
     for (int64_t k = b; k < e; ++k) t += (double)cv[k] * us[a.rowidx[k]];
     if (MODE == COL_NORMAL) {
@@ -273,11 +332,11 @@ __global__ __launch_bounds__(256) void k_csr_seg(const int32_t* __restrict__ col
                                                  const double* __restrict__ coef2,
                                                  double* __restrict__ segsum,
                                                  const int32_t* __restrict__ done) {
-  if (done && *done) return;
   const int lane = threadIdx.x & 63;
   const int64_t s = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (s >= nseg) return;
-  const int64_t b = seg_start[s], e = seg_end[s];
+  const int64_t b = seg_start[s], e = seg_end[s];  // requested before the done flag is read
+  if (done && *done) return;
   double acc1 = 0, acc2 = 0;
   // four non-zeros per lane per trip: their indices and values are loaded
   // first, then the four gathers are in flight together; the products are
@@ -323,12 +382,14 @@ __global__ __launch_bounds__(256) void k_csr_fold(const double* __restrict__ seg
                                                   double* __restrict__ dq_out,
                                                   const int32_t* __restrict__ done) {
   __shared__ double dq[4];
-  if (done && *done) return;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + wid;
+  const int64_t ic = i < m ? i : m - 1;
+  const int64_t sb = segptr[ic], se = segptr[ic + 1];  // requested before the done flag is read
+  if (done && *done) return;
   double v = 0;
   if (i < m) {
-    const int64_t b = segptr[i], e = segptr[i + 1];
+    const int64_t b = sb, e = se;
     double acc = 0;
     // eight loads in flight per lane (rows with many segments, such as a
     // dense row, would otherwise wait out one load latency per term); each
