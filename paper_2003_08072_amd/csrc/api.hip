@@ -82,6 +82,7 @@ struct skipm_lp_s {
   int64_t k = 0;
   int64_t hashed_k = -1;
   int prev_cg = 8;
+  double last_rel_gap = HUGE_VAL;  // relative gap at the last stopping test
   int origin_pending = 1;
   int small_steps = 0;
   double bnorm = 0, cnorm = 0;
@@ -936,10 +937,27 @@ StopState stop_test(skipm_lp_s* lp, double bnorm, double cnorm) {
 int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cnorm,
                   hipStream_t st) {
   SK_TRY(prologue(lp, st));
-  SK_TRY(sync_read(lp, st));
+  // Far from convergence the stopping test's slots are read at the CG's first
+  // host check: the sketch, the factorisation and the CG are queued behind
+  // the prologue without a host round trip of their own (none of them writes
+  // those slots), and a failure there counts only if the iterate has not
+  // converged.  Once the last relative gap is within 16 eps_gap (mu shrinks
+  // by at most 1 - alpha (1 - sigma) >= 1/2 per step, so the test can pass
+  // only then) the test is read first, so the final iteration queues nothing.
+  const bool defer = lp->last_rel_gap > 16.0 * lp->prm.eps_gap;
+  const int64_t salt = lp->prm.resketch ? lp->k : 0;
+  int its = 0;
+  int rc = SKIPM_OK;
+  if (defer) {
+    rc = sketch_into(lp, lp->d2, 1, salt, lp->B, st);
+    if (rc == SKIPM_OK)
+      rc = solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st);
+  }
+  if (!defer || rc != SKIPM_OK) SK_TRY(sync_read(lp, st));
   // the prologue's x^T s is the same quantity as the update's; S_XS holds the
   // value of the current iterate
   const StopState ss = stop_test(lp, bnorm, cnorm);
+  lp->last_rel_gap = ss.nan ? HUGE_VAL : ss.rel_gap;
   if (info) {
     memset(info, 0, sizeof(*info));
     info->mu = ss.mu;
@@ -965,10 +983,12 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
     if (info) info->converged = 1;
     return SKIPM_OK;
   }
-  const int64_t salt = lp->prm.resketch ? lp->k : 0;
-  SK_TRY(sketch_into(lp, lp->d2, 1, salt, lp->B, st));
-  int its = 0;
-  SK_TRY(solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st));
+  if (!defer) {
+    SK_TRY(sketch_into(lp, lp->d2, 1, salt, lp->B, st));
+    SK_TRY(solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st));
+  } else if (rc != SKIPM_OK) {
+    return rc;
+  }
   ks_harvest(lp);  // the CG's host checks have waited past the sketch
   const double f0 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
   const double f1 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ]));
@@ -1183,6 +1203,7 @@ int lp_reset(skipm_lp_t lp, hipStream_t st) {
   launch_fill_f64(lp->y, 0.0, lp->mp, st);
   lp->k = 0;
   lp->prev_cg = 8;
+  lp->last_rel_gap = HUGE_VAL;
   lp->origin_pending = 1;
   lp->small_steps = 0;
   if (lp->demoted) {
@@ -1446,6 +1467,7 @@ int lp_set_iterate(skipm_lp_t lp, const double* x, const double* y, const double
   launch_copy_f64(lp->x, x, lp->n, st);
   launch_copy_f64(lp->y, y, lp->m, st);
   launch_copy_f64(lp->sv, s, lp->n, st);
+  lp->last_rel_gap = HUGE_VAL;
   if (reset_origin) {
     lp->origin_pending = 1;
     lp->k = 0;
