@@ -241,12 +241,20 @@ def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **
     O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1, **prm_kw))
     t_iter = time.perf_counter() - t0
     if t_iter * 50 <= 3 * budget:
-        t0 = time.perf_counter()
-        r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1000, **prm_kw))
-        t = time.perf_counter() - t0
-        return dict(value=1.0 / t, unit="solves/s", cores=cores, kind="oracle",
-                    sample=f"one full {what} solve ({r.iters} iterations, "
-                           f"{t:.2f} s, status {r.status})")
+        # whole solves, repeated while they fit in the budget (a small LP's
+        # single solve is too short to time alone)
+        t, solves, r = 0.0, 0, None
+        while solves == 0 or (t < budget and solves < 1000):
+            t0 = time.perf_counter()
+            r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=1000, **prm_kw))
+            t += time.perf_counter() - t0
+            solves += 1
+            if t * (solves + 1) / solves > 3 * budget:
+                break
+        what_s = "one full" if solves == 1 else f"{solves} full"
+        return dict(value=solves / t, unit="solves/s", cores=cores, kind="oracle",
+                    sample=f"{what_s} {what} solve{'s' if solves > 1 else ''} "
+                           f"({r.iters} iterations each, {t:.2f} s, status {r.status})")
     k = max(1, int(budget / t_iter))
     t0 = time.perf_counter()
     r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=k, **prm_kw))
@@ -587,6 +595,15 @@ def main():
             speedup[f"s{s_nnz}"] = a["solves_per_s"] / b["solves_per_s"]
     print("[bench] cpu baseline", file=sys.stderr, flush=True)
     cpu = cpu_baseline(lp, args.cpu_budget) if args.cpu_budget > 0 else None
+    cpu1 = None
+    if args.cpu_budget > 0 and args.config in (0, 1):
+        # the same oracle with its BLAS held to one thread (half the budget)
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                cpu1 = cpu_baseline(lp, args.cpu_budget / 2)
+        except ImportError:
+            cpu1 = None
     mv = dict(head)
     timing = ("HIP events stamped with the kernel's start and end (hipExtLaunchKernelGGL) on "
               "every 8th CG product of the timed solves")
@@ -635,6 +652,7 @@ def main():
                      # the bytes can be served from the cache
                      "cache_resident": mv["matvec_bytes"] <= INFINITY_CACHE_BYTES},
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
     }
     print(json.dumps(line), flush=True)
 
