@@ -254,7 +254,8 @@ def cpu_baseline(lp, budget, A=None, what="exact-Cholesky IPM", est_iters=40, **
         what_s = "one full" if solves == 1 else f"{solves} full"
         return dict(value=solves / t, unit="solves/s", cores=cores, kind="oracle",
                     sample=f"{what_s} {what} solve{'s' if solves > 1 else ''} "
-                           f"({r.iters} iterations each, {t:.2f} s, status {r.status})")
+                           f"({r.iters} iterations{' each' if solves > 1 else ''}, {t:.2f} s, "
+                           f"status {r.status})")
     k = max(1, int(budget / t_iter))
     t0 = time.perf_counter()
     r = O.ipm(A, lp.b, lp.c, O.IPMParams(max_outer=k, **prm_kw))
