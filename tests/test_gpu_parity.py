@@ -492,6 +492,27 @@ def test_solve_is_deterministic_and_resettable(torch, sk):
     assert r1.obj_p == r2.obj_p and r1.obj_d == r2.obj_d
 
 
+@pytest.mark.parametrize("fresh", [False, True])
+def test_step_at_a_converged_iterate_changes_nothing(torch, sk, fresh):
+    """After a solve, one more step finds the stopping test satisfied and
+    leaves the iterate as it is.  With fresh = True the iterate is handed in
+    again (lp_set_iterate), so the step does not know how close it is: it queues
+    the sketch, factorisation and CG before it reads the test, and must still
+    report convergence and leave the iterate untouched."""
+    lp = dense_planted(40, 900, rng=np.random.default_rng(21))
+    say(f"step at a converged iterate (fresh={fresh})")
+    with sk.LP(lp.A, lp.b, lp.c, s=2, seed=4) as h:
+        res = h.solve()
+        assert res.status == 0
+        x, y, s = (v.cpu().numpy() for v in h.get_iterate())
+        if fresh:
+            h.set_iterate(x, y, s, reset_origin=False)
+        info = h.step()
+        x2, y2, s2 = (v.cpu().numpy() for v in h.get_iterate())
+    assert info.converged == 1 and info.status == 0
+    assert np.array_equal(x, x2) and np.array_equal(y, y2) and np.array_equal(s, s2)
+
+
 @pytest.fixture(scope="module")
 def cfg1():
     """The 500 x 100000 FP64 LP the bench times, and a positive D^2 with a
