@@ -182,8 +182,16 @@ int run_colpass(ColPass& cp, hipStream_t st) {
   return SKIPM_OK;
 }
 
+// A pass over A (values of type ta) streams it with non-temporal loads once A
+// is larger than the 256 MiB Infinity Cache; a matrix that fits stays cached.
+constexpr int64_t kStreamBytes = (int64_t)256 << 20;
+int stream_A(const skipm_lp_s* lp, int ta) {
+  return lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4) > kStreamBytes ? 1 : 0;
+}
+
 ColPass colpass_A(skipm_lp_s* lp, int mode) {
   ColPass cp{};
+  cp.nt = stream_A(lp, lp->a_dtype);
   cp.mode = mode;
   cp.A = lp->A;
   cp.ta = lp->a_dtype;
@@ -382,6 +390,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   if (lp->mixed) {  // FP32 copy of A, FP64 accumulation
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
+    cp.nt = stream_A(lp, SKIPM_F32);
     cp.nblk = lp->nblk_A32;
   }
   cp.done = done;
@@ -1586,6 +1595,7 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   if (lp->mixed) {
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
+    cp.nt = stream_A(lp, SKIPM_F32);
     cp.nblk = lp->nblk_A32;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -75,7 +75,7 @@ struct Args {
   CgFuse cg;
 };
 
-template <typename TA, typename TC, int G, int R, int MODE, int NT>
+template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
 __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   constexpr int V = Vec<TA>::V;
   typedef typename Vec<TA>::type VT;
@@ -104,11 +104,15 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   bool valid[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) valid[r] = (int64_t)(r * G + lg) * V < a.lda;
+  // STREAM (a pass over an A larger than the Infinity Cache): non-temporal
+  // loads, which stream from HBM faster than cached ones and leave the caches
+  // to what the small CG kernels reuse every iteration.  A matrix that fits
+  // the cache is read with ordinary loads and stays resident.
   auto load_col = [&](VT* dst, const int64_t col) {
     const VT* p = (const VT*)(A + col * a.lda);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (valid[r]) dst[r] = p[r * G + lg];
+      if (valid[r]) dst[r] = STREAM ? __builtin_nontemporal_load(&p[r * G + lg]) : p[r * G + lg];
   };
   // The first columns are requested before anything else: they depend on
   // nothing, so their latency overlaps the set-up below.  Two columns per trip
@@ -678,25 +682,37 @@ constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
   return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
 
-template <typename TA, typename TC, int MODE, int G, int R>
+template <typename TA, typename TC, int MODE, int G, int R, bool STREAM>
 void launch_one(const Args& a, int nblk, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   constexpr int NT = threads_for(MODE, R, Vec<TA>::V, (int)sizeof(TC));
   if (e0)  // events stamped by the runtime with the kernel's own start and end
-    hipExtLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, e0,
-                          e1, 0, a);
+    hipExtLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT, STREAM>), dim3(nblk), dim3(NT), 0,
+                          st, e0, e1, 0, a);
   else
-    hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT>), dim3(nblk), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT, STREAM>), dim3(nblk), dim3(NT), 0, st,
+                       a);
+}
+
+// the passes over A that may take non-temporal loads (STREAM)
+constexpr bool stream_mode(int mode) {
+  return mode == COL_NORMAL || mode == COL_PROLOGUE || mode == COL_EPILOGUE;
 }
 
 template <typename TA, typename TC, int MODE>
-int dispatch(const Args& a, int nblk, hipStream_t st, hipEvent_t e0 = nullptr,
+int dispatch(const Args& a, int nblk, bool stream, hipStream_t st, hipEvent_t e0 = nullptr,
              hipEvent_t e1 = nullptr) {
   const Shape sh = pick_shape(a.lda, Vec<TA>::V);
   // shapes that only columns longer than kMaxM would select are not built
 #define SK_CASE(GG, RR)                                                   \
   if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                          \
     if (sh.G == GG && sh.R == RR) {                                       \
-      launch_one<TA, TC, MODE, GG, RR>(a, nblk, st, e0, e1);              \
+      if constexpr (stream_mode(MODE)) {                                  \
+        if (stream) {                                                     \
+          launch_one<TA, TC, MODE, GG, RR, true>(a, nblk, st, e0, e1);    \
+          return 0;                                                       \
+        }                                                                 \
+      }                                                                   \
+      launch_one<TA, TC, MODE, GG, RR, false>(a, nblk, st, e0, e1);       \
       return 0;                                                           \
     }                                                                     \
   }
@@ -794,18 +810,22 @@ int launch_colpass(ColPass& c, hipStream_t st) {
   int rc = -1;
   if (c.ta == SKIPM_F64 && c.tc == SKIPM_F64) {
     switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<double, double, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
-      case COL_PROLOGUE: rc = dispatch<double, double, COL_PROLOGUE>(a, nblk, st); break;
-      case COL_EPILOGUE: rc = dispatch<double, double, COL_EPILOGUE>(a, nblk, st); break;
-      case COL_DOT: rc = dispatch<double, double, COL_DOT>(a, nblk, st); break;
-      case COL_AXPY: rc = dispatch<double, double, COL_AXPY>(a, nblk, st); break;
+      case COL_NORMAL:
+        rc = dispatch<double, double, COL_NORMAL>(a, nblk, c.nt, st, c.ev0, c.ev1);
+        break;
+      case COL_PROLOGUE: rc = dispatch<double, double, COL_PROLOGUE>(a, nblk, c.nt, st); break;
+      case COL_EPILOGUE: rc = dispatch<double, double, COL_EPILOGUE>(a, nblk, c.nt, st); break;
+      case COL_DOT: rc = dispatch<double, double, COL_DOT>(a, nblk, c.nt, st); break;
+      case COL_AXPY: rc = dispatch<double, double, COL_AXPY>(a, nblk, c.nt, st); break;
     }
   } else if (c.ta == SKIPM_F32 && c.tc == SKIPM_F64) {
     switch (c.mode) {
-      case COL_NORMAL: rc = dispatch<float, double, COL_NORMAL>(a, nblk, st, c.ev0, c.ev1); break;
-      case COL_PROLOGUE: rc = dispatch<float, double, COL_PROLOGUE>(a, nblk, st); break;
-      case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, st); break;
-      case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, st); break;
+      case COL_NORMAL:
+        rc = dispatch<float, double, COL_NORMAL>(a, nblk, c.nt, st, c.ev0, c.ev1);
+        break;
+      case COL_PROLOGUE: rc = dispatch<float, double, COL_PROLOGUE>(a, nblk, c.nt, st); break;
+      case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, c.nt, st); break;
+      case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, c.nt, st); break;
     }
   }
   return rc;
