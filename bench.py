@@ -31,7 +31,7 @@ INFINITY_CACHE_BYTES = 256 << 20
 # FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 1.9999, the factor a
 # 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
 # current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
-MEASURED_TRAFFIC = {(1, "mixed"): 202_009_499, (1, "fp64"): 403_305_134}
+MEASURED_TRAFFIC = {(1, "mixed"): 202_016_083, (1, "fp64"): 406_259_962}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 
