@@ -183,8 +183,9 @@ int run_colpass(ColPass& cp, hipStream_t st) {
 }
 
 // A pass over A (values of type ta) streams it with non-temporal loads once A
-// is larger than the 256 MiB Infinity Cache; a matrix that fits stays cached.
-constexpr int64_t kStreamBytes = (int64_t)256 << 20;
+// takes most of the 256 MiB Infinity Cache (240 MiB: measured, 200.8 MB read
+// 16 % faster cached, 263 MB 1.6 % faster streamed); a smaller one stays cached.
+constexpr int64_t kStreamBytes = (int64_t)240 << 20;
 int stream_A(const skipm_lp_s* lp, int ta) {
   return lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4) > kStreamBytes ? 1 : 0;
 }

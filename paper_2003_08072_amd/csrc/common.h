@@ -154,8 +154,8 @@ struct ColPass {
   const double* sc;         // device scalar slots
   const int32_t* done;      // optional early-exit flag
   int nblk;                 // filled by the launcher
-  int nt = 0;               // NORMAL/PROLOGUE/EPILOGUE over an A larger than the Infinity
-                            // Cache: non-temporal column loads
+  int nt = 0;               // NORMAL/PROLOGUE/EPILOGUE over an A that takes most of the
+                            // Infinity Cache: non-temporal column loads
   CgFuse cg;                // fused CG bookkeeping (COL_NORMAL, COL_DOT)
   hipEvent_t ev0 = nullptr;  // COL_NORMAL: optional events stamped with the kernel's
   hipEvent_t ev1 = nullptr;  // start and end (sampled timing)
