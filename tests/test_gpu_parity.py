@@ -563,6 +563,27 @@ def test_normal_product_at_full_size(torch, sk, cfg1, prec):
     assert np.all(np.abs(q - ref) <= 2 * (lp.m + lp.n) * EPS * bound)
 
 
+def test_streamed_fp32_product(torch, sk):
+    """The mixed product over an FP32 copy larger than 240 MiB (500 x 130000:
+    260 MB) takes the non-temporal instantiation of the pass; element by
+    element against the oracle's normal matrix of the FP32-rounded A."""
+    m, n = 500, 130_000
+    lp = dense_planted(m, n, rng=np.random.default_rng(130))
+    rng = np.random.default_rng(131)
+    x, s_ = rng.uniform(0.1, 10.0, n), rng.uniform(0.1, 10.0, n)
+    y, u = rng.standard_normal(m), rng.standard_normal(m)
+    say("streamed FP32 product 500 x 130000 (mixed)")
+    with sk.LP(lp.A, lp.b, lp.c, s=2, seed=3, precision=sk.SKIPM_PREC_MIXED) as h:
+        h.set_iterate(x, y, s_)
+        h.step()
+        q = h.normal_matvec(u).cpu().numpy()
+    A = lp.A.astype(np.float32).astype(np.float64)
+    d2 = x / s_
+    ref = O.normal_matrix(A, d2) @ u
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(u)))
+    assert np.all(np.abs(q - ref) <= 2 * (m + n) * EPS * bound)
+
+
 def test_pcg_at_full_size_matches_alg1(torch, sk, cfg1):
     """Three FP64 CG iterations at the bench's shape (the fused three-launch CG
     the solve runs) against Alg. 1 on the split system."""
