@@ -329,7 +329,7 @@ int kt_begin(skipm_lp_s* lp, int iter, hipStream_t st) {
 }
 
 void kt_end(skipm_lp_s* lp, int q, hipStream_t st) {
-  if (q >= 0) hipEventRecord(lp->kt_ev[2 * q + 1], st);
+  if (q >= 0) (void)hipEventRecord(lp->kt_ev[2 * q + 1], st);  // a failed stamp drops the sample
 }
 
 // After a host synchronisation: keep the samples of products that ran (CG
@@ -1193,14 +1193,15 @@ int lp_device_bytes(skipm_lp_t lp, int64_t* out) {
 
 int lp_destroy(skipm_lp_t lp) {
   if (!lp) return SKIPM_OK;
-  hipSetDevice(lp->device);
-  for (void* p : lp->allocs) hipFree(p);
+  // release everything; a failure here has nothing left to report to
+  (void)hipSetDevice(lp->device);
+  for (void* p : lp->allocs) (void)hipFree(p);
   for (hipEvent_t e : lp->kt_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : lp->ks_ev)
-    if (e) hipEventDestroy(e);
-  if (lp->blas) rocblas_destroy_handle(lp->blas);
-  if (lp->hsc) hipHostFree(lp->hsc);
+    if (e) (void)hipEventDestroy(e);
+  if (lp->blas) (void)rocblas_destroy_handle(lp->blas);
+  if (lp->hsc) (void)hipHostFree(lp->hsc);
   delete lp;
   return SKIPM_OK;
 }
@@ -1250,7 +1251,10 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     return set_error("the Gaussian sketch needs dense FP64 A"), SKIPM_EINVAL;
 
   skipm_lp_s* lp = new skipm_lp_s();
-  hipGetDevice(&lp->device);
+  if (hipGetDevice(&lp->device) != hipSuccess) {
+    delete lp;
+    return set_error("hipGetDevice failed"), SKIPM_EDEVICE;
+  }
   lp->m = m;
   lp->n = n;
   lp->fmt = prob->format;
@@ -1584,8 +1588,8 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
       SK_CHECK_HIP(hipEventSynchronize(e1));
       SK_CHECK_HIP(hipEventElapsedTime(&tot, e0, e1));
       *ms = tot / (float)reps;
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
     }
     SK_CHECK_HIP(hipGetLastError());
     return SKIPM_OK;
@@ -1614,8 +1618,8 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
     SK_CHECK_HIP(hipEventSynchronize(e1));
     SK_CHECK_HIP(hipEventElapsedTime(&tot, e0, e1));
     *ms = tot / (float)reps;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
   return SKIPM_OK;
 }

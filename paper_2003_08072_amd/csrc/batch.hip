@@ -70,7 +70,7 @@ int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t wo
       }
       if (res[i].status == SKIPM_OK && rc != SKIPM_OK) res[i].status = rc;
     }
-    hipStreamDestroy(st);
+    (void)hipStreamDestroy(st);
   };
   std::vector<std::thread> pool;
   pool.reserve(nw);
@@ -144,7 +144,7 @@ void skipm_server_s::run(Req* r, hipStream_t st) {
 }
 
 void skipm_server_s::worker_main() {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);
   hipStream_t st = nullptr;
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   for (;;) {
@@ -172,14 +172,14 @@ void skipm_server_s::worker_main() {
     r->info.t_done = now();
     r->info.state = SKIPM_REQ_DONE;
     if (r->ready) {
-      hipEventDestroy(r->ready);
+      (void)hipEventDestroy(r->ready);
       r->ready = nullptr;
     }
     lk.unlock();
     work_cv.notify_all();
     done_cv.notify_all();
   }
-  if (have_stream) hipStreamDestroy(st);
+  if (have_stream) (void)hipStreamDestroy(st);
 }
 
 extern "C" {
@@ -215,7 +215,7 @@ int srv_submit(skipm_server_t srv, const skipm_problem* prob, const skipm_params
   r->x_out = x_out;
   if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(r->ready, producer) != hipSuccess) {
-    if (r->ready) hipEventDestroy(r->ready);
+    if (r->ready) (void)hipEventDestroy(r->ready);
     delete r;
     return set_error("could not record the producer event"), SKIPM_EDEVICE;
   }
@@ -224,7 +224,7 @@ int srv_submit(skipm_server_t srv, const skipm_problem* prob, const skipm_params
   {
     std::lock_guard<std::mutex> g(srv->mu);
     if (srv->stop) {
-      hipEventDestroy(r->ready);
+      (void)hipEventDestroy(r->ready);
       delete r;
       return set_error("server is shutting down"), SKIPM_EINVAL;
     }
@@ -286,7 +286,7 @@ int srv_destroy(skipm_server_t srv) {
   srv->work_cv.notify_all();
   for (auto& th : srv->workers) th.join();
   for (auto& kv : srv->reqs) {
-    if (kv.second->ready) hipEventDestroy(kv.second->ready);
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete kv.second;
   }
   delete srv;
