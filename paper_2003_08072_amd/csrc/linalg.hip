@@ -46,19 +46,31 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
   dacc4 acc[4];
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) acc[jb] = (dacc4)0.0;
-  for (int64_t c = cb; c < ce; c += 16) {
+  // The 16 columns of step c are loaded into registers two steps ahead (the
+  // sets for c + 16 and c + 32 are in flight while step c's MFMAs run); a
+  // thread's four entries per panel, zero outside B.  Three register sets in
+  // a fixed rotation, so every index is static.
+  auto fetch = [&](double (&vi)[4], double (&vk)[4], const int64_t c) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = threadIdx.x + 256 * q;
       const int cc = idx >> 6, rr = idx & 63;
       const int64_t col = c + cc;
-      double vi = 0, vk = 0;
+      vi[q] = 0;
+      vk[q] = 0;
       if (col < ce) {
-        if (i0 + rr < m) vi = B[col * ldb + i0 + rr];
-        if (k0 + rr < m) vk = B[col * ldb + k0 + rr];
+        if (i0 + rr < m) vi[q] = B[col * ldb + i0 + rr];
+        if (k0 + rr < m) vk[q] = B[col * ldb + k0 + rr];
       }
-      Ai[cc][rr] = vi;
-      Ak[cc][rr] = vk;
+    }
+  };
+  auto step = [&](const double (&vi)[4], const double (&vk)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int cc = idx >> 6, rr = idx & 63;
+      Ai[cc][rr] = vi[q];
+      Ak[cc][rr] = vk[q];
     }
     __syncthreads();
 #pragma unroll
@@ -71,6 +83,19 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
       }
     }
     __syncthreads();
+  };
+  double ai[4], ak[4], bi[4], bk[4], ci[4], ck[4];
+  fetch(ai, ak, cb);
+  fetch(bi, bk, cb + 16);
+  for (int64_t c = cb; c < ce; c += 48) {
+    fetch(ci, ck, c + 32);
+    step(ai, ak);
+    if (c + 16 >= ce) break;
+    fetch(ai, ak, c + 48);
+    step(bi, bk);
+    if (c + 32 >= ce) break;
+    fetch(bi, bk, c + 64);
+    step(ci, ck);
   }
   // element (i, k) of the tile, mirrored; on a diagonal tile only i >= k is
   // written (with its mirror), so every entry has exactly one writer
