@@ -278,8 +278,14 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
   }
   double r0 = 0, r1 = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t cb = cb0, ce = ce0;
   for (int64_t j = j0; j < a.n; j += stride) {
-    const int64_t b = j == j0 ? cb0 : a.colptr[j], e = j == j0 ? ce0 : a.colptr[j + 1];
+    // the next column's range is requested before this column is summed
+    const int64_t jn = j + stride < a.n ? j + stride : a.n - 1;
+    const int64_t nb = a.colptr[jn], ne = a.colptr[jn + 1];
+    const int64_t b = cb, e = ce;
+    cb = nb;
+    ce = ne;
     double t = 0;
     for (int64_t k = b; k < e; ++k) t += (double)cv[k] * us[a.rowidx[k]];
     if (MODE == COL_NORMAL) {
