@@ -908,6 +908,12 @@ int finish_step(skipm_lp_s* lp, hipStream_t st) {
       return set_error("rocblas_dgemv (Gaussian sketch) failed"), SKIPM_EDEVICE;
     wt = lp->gy;
   }
+  if (lp->nblk_vec == 1) {
+    launch_step_one(lp->n, lp->m, lp->s, lp->x, lp->y, lp->sv, lp->d2, lp->ds, lp->dy, lp->bucket,
+                    lp->sign, lp->tw, wt, lp->v, lp->dx, lp->sc, st);
+    SK_CHECK_HIP(hipGetLastError());
+    return SKIPM_OK;
+  }
   launch_direction(lp->n, lp->s, lp->x, lp->sv, lp->d2, lp->ds, lp->bucket, lp->sign, lp->tw,
                    wt, lp->v, lp->dx, lp->red, lp->nblk_vec, lp->sc, st);
   launch_reduce_slots(lp->red, lp->nblk_vec, 5, lp->sc, S_A0, 0, st);

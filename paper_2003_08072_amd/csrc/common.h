@@ -311,5 +311,11 @@ void launch_xs_sum(int64_t n, const double* x, const double* s, double* red, int
                    hipStream_t st);
 void launch_sqrt_vec(int64_t n, const double* in, double* out, hipStream_t st);
 int vec_nblk(int64_t n);
+// One-workgroup step tail (direction, step length, update, mu) for
+// vec_nblk(n) == 1; same results as the multi-kernel tail.
+void launch_step_one(int64_t n, int64_t m, int s, double* x, double* y, double* sv,
+                     const double* d2, const double* ds, const double* dy, const int32_t* bucket,
+                     const int8_t* sign, const double* tw, const double* wt, double* v,
+                     double* dx, double* sc, hipStream_t st);
 
 }  // namespace skipm

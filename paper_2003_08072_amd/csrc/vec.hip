@@ -411,6 +411,109 @@ __global__ __launch_bounds__(1024) void k_mu_finalize(const double* __restrict__
   }
 }
 
+// The whole step tail of Alg. 2 (direction, step length, update, mu) in one
+// workgroup, for n <= kVecThreads * 4 where the multi-kernel tail runs one
+// workgroup per phase anyway: the same per-entry arithmetic and the same
+// workgroup sums in the same order as k_direction, k_step_terms,
+// k_step_finalize, k_update and k_mu_finalize, with the one-partial slot
+// reductions (exact copies) dropped and six dependent launches saved.
+__global__ __launch_bounds__(kVecThreads) void k_step_one(
+    int64_t n, int64_t m, int s, double* __restrict__ x, double* __restrict__ y,
+    double* __restrict__ sv, const double* __restrict__ d2, const double* __restrict__ ds,
+    const double* __restrict__ dy, const int32_t* __restrict__ bucket,
+    const int8_t* __restrict__ sign, const double* __restrict__ tw,
+    const double* __restrict__ wt, double* __restrict__ v, double* __restrict__ dx,
+    double* __restrict__ sc) {
+  __shared__ double buf[kVecThreads / 64];
+  __shared__ double alpha_s;
+  const double smu = sc[S_SIGMA] * sc[S_MU];
+  double a0 = 0, a1 = 0, a2 = 0, vs = 0, v2 = 0;
+  for (int64_t j = threadIdx.x; j < n; j += kVecThreads) {
+    const double xj = x[j], sj = sv[j], dsj = ds[j];
+    double vj;
+    if (wt) {
+      vj = sj * wt[j];
+    } else {
+      double acc = 0;
+      for (int r = 0; r < s; ++r) acc += (double)sign[j * s + r] * tw[bucket[j * s + r]];
+      vj = sqrt(xj * sj) * acc;
+    }
+    const double dxj = -xj + smu / sj - d2[j] * dsj - vj / sj;
+    v[j] = vj;
+    dx[j] = dxj;
+    a0 += xj * sj;
+    a1 += xj * dsj + sj * dxj;
+    a2 += dxj * dsj;
+    vs += vj;
+    v2 += vj * vj;
+  }
+  a0 = block_sum<kVecThreads>(a0, buf);
+  a1 = block_sum<kVecThreads>(a1, buf);
+  a2 = block_sum<kVecThreads>(a2, buf);
+  vs = block_sum<kVecThreads>(vs, buf);
+  v2 = block_sum<kVecThreads>(v2, buf);
+  // step terms (each thread reads back the dx entries it wrote)
+  const double g1 = 1.0 - sc[S_GAMMA];
+  const double dn = (double)n;
+  const double ca = g1 * a2 / dn, cb = g1 * a1 / dn, cc = g1 * a0 / dn;
+  double ex = INFINITY, bd = INFINITY;
+  for (int64_t j = threadIdx.x; j < n; j += kVecThreads) {
+    const double xj = x[j], sj = sv[j], dxj = dx[j], dsj = ds[j];
+    const double qa = dxj * dsj - ca;
+    const double qb = xj * dsj + sj * dxj - cb;
+    double qc = xj * sj - cc;
+    if (qc < 0.0) qc = 0.0;
+    ex = fmin(ex, first_exit(qa, qb, qc));
+    if (dxj < 0.0) bd = fmin(bd, -xj / dxj);
+    if (dsj < 0.0) bd = fmin(bd, -sj / dsj);
+  }
+  ex = block_min<kVecThreads>(ex, buf);
+  bd = block_min<kVecThreads>(bd, buf);
+  if (threadIdx.x == 0) {
+    sc[S_A0] = a0;
+    sc[S_A1] = a1;
+    sc[S_A2] = a2;
+    sc[S_VSUM] = vs;
+    sc[S_V2] = v2;
+    sc[S_EXIT] = ex;
+    sc[S_BOUND] = bd;
+    double amax = 1.0;
+    amax = fmin(amax, ex);
+    const double t = dn * sc[S_MU0] * sc[S_ETA];
+    double rc = a0 - t;
+    if (rc < 0.0) rc = 0.0;
+    amax = fmin(amax, first_exit(a2, a1 + t, rc));
+    amax = fmin(amax, (1.0 - sc[S_GUARD]) * bd);
+    double alpha;
+    if (a2 > 0.0) {
+      alpha = -a1 / (2.0 * a2);
+      if (alpha < 0.0) alpha = 0.0;
+      if (alpha > amax) alpha = amax;
+    } else {
+      alpha = (a1 + a2 * amax <= 0.0) ? amax : 0.0;
+    }
+    sc[S_AMAX] = amax;
+    sc[S_ALPHA] = alpha;
+    alpha_s = alpha;
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  double xs = 0;
+  for (int64_t j = threadIdx.x; j < n; j += kVecThreads) {
+    const double xj = x[j] + alpha * dx[j];
+    const double sj = sv[j] + alpha * ds[j];
+    x[j] = xj;
+    sv[j] = sj;
+    xs += xj * sj;
+  }
+  for (int64_t i = threadIdx.x; i < m; i += kVecThreads) y[i] += alpha * dy[i];
+  xs = block_sum<kVecThreads>(xs, buf);
+  if (threadIdx.x == 0) {
+    sc[S_XS] = xs;
+    sc[S_MU] = xs / dn;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ u, int64_t m,
                                                 double* __restrict__ sc, int slot) {
   __shared__ double buf[16];
@@ -541,6 +644,14 @@ void launch_update(int64_t n, int64_t m, double* x, double* y, double* s, const 
 void launch_xs_sum(int64_t n, const double* x, const double* s, double* red, int nblk,
                    hipStream_t st) {
   hipLaunchKernelGGL(k_xs_sum, dim3(nblk), dim3(kVecThreads), 0, st, n, x, s, red);
+}
+
+void launch_step_one(int64_t n, int64_t m, int s, double* x, double* y, double* sv,
+                     const double* d2, const double* ds, const double* dy, const int32_t* bucket,
+                     const int8_t* sign, const double* tw, const double* wt, double* v,
+                     double* dx, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_one, dim3(1), dim3(kVecThreads), 0, st, n, m, s, x, y, sv, d2, ds,
+                     dy, bucket, sign, tw, wt, v, dx, sc);
 }
 
 void launch_mu_finalize(const double* red, int nblk, int64_t n, double* sc, hipStream_t st) {
