@@ -276,8 +276,8 @@ int factor(skipm_lp_s* lp, double shift, hipStream_t st) {
   launch_gram(lp->B, lp->lda, lp->m, lp->w, lp->Gpart, lp->ksplit, lp->mp, st);
   launch_gram_finish(lp->Gpart, lp->ksplit, lp->m, lp->mp, lp->G, st);
   if (shift > 0) launch_shift_diag(lp->G, lp->mp, lp->m, shift, st);
-  launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
-  launch_fill_f64(lp->Xb, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
+  // X = 0 (blocks above the diagonal stay zero) and the failure flag cleared
+  launch_fill_f64_flag(lp->Xb, 0.0, lp->mp * lp->mp, lp->is + I_FACT_FAIL, st);
   launch_spd_inverse(lp->G, lp->Xb, lp->Ct, lp->mp, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
@@ -812,8 +812,7 @@ int true_residual(skipm_lp_s* lp, hipStream_t st) {
 }
 
 int spd_inverse_checked(skipm_lp_s* lp, double* Gm, double* Xm, hipStream_t st) {
-  launch_fill_i32(lp->is + I_FACT_FAIL, 0, 1, st);
-  launch_fill_f64(Xm, 0.0, lp->mp * lp->mp, st);  // blocks above the diagonal stay zero
+  launch_fill_f64_flag(Xm, 0.0, lp->mp * lp->mp, lp->is + I_FACT_FAIL, st);
   launch_spd_inverse(Gm, Xm, lp->Ct, lp->mp, lp->is + I_FACT_FAIL, st);
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
@@ -861,9 +860,7 @@ int v_solve(skipm_lp_s* lp, int* its, double* rel_out, hipStream_t st) {
   const double target = 1e-14;
   const int max_steps = 12;
   lp->vrounds_built = 0;
-  launch_fill_f64(lp->tw, 0.0, lp->w, st);
-  launch_copy_f64(lp->rv, lp->g, lp->m, st);
-  launch_norm2(lp->g, lp->m, lp->sc, S_V_GG, st);
+  launch_v_init(lp->tw, lp->w, lp->rv, lp->g, lp->m, lp->sc, S_V_GG, st);
   *its = 0;
   *rel_out = 0.0;
   int K = 0;

@@ -311,6 +311,11 @@ void launch_xs_sum(int64_t n, const double* x, const double* s, double* red, int
                    hipStream_t st);
 void launch_sqrt_vec(int64_t n, const double* in, double* out, hipStream_t st);
 int vec_nblk(int64_t n);
+// p[0..n) = v and *flag = 0 in one launch.
+void launch_fill_f64_flag(double* p, double v, int64_t n, int32_t* flag, hipStream_t st);
+// tw[0..w) = 0, rv = g (m entries), sc[slot] = ||g||^2.
+void launch_v_init(double* tw, int64_t w, double* rv, const double* g, int64_t m, double* sc,
+                   int slot, hipStream_t st);
 // One-workgroup step tail (direction, step length, update, mu) for
 // vec_nblk(n) == 1; same results as the multi-kernel tail.
 void launch_step_one(int64_t n, int64_t m, int s, double* x, double* y, double* sv,

@@ -59,6 +59,12 @@ __global__ void k_fill_f64(double* p, double v, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
+// k_fill_f64 that also clears one flag (a factorisation's failure flag)
+__global__ void k_fill_f64_flag(double* p, double v, int64_t n, int32_t* flag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -514,6 +520,24 @@ __global__ __launch_bounds__(kVecThreads) void k_step_one(
   }
 }
 
+// Start of the correction-vector refinement: t = 0, r = g, ||g||^2 -> slot
+// (the sum in k_norm2's order).
+__global__ __launch_bounds__(1024) void k_v_init(double* __restrict__ tw, int64_t w,
+                                                 double* __restrict__ rv,
+                                                 const double* __restrict__ g, int64_t m,
+                                                 double* __restrict__ sc, int slot) {
+  __shared__ double buf[16];
+  for (int64_t i = threadIdx.x; i < w; i += 1024) tw[i] = 0.0;
+  double v = 0;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) {
+    const double gi = g[i];
+    rv[i] = gi;
+    v += gi * gi;
+  }
+  v = block_sum<1024>(v, buf);
+  if (threadIdx.x == 0) sc[slot] = v;
+}
+
 __global__ __launch_bounds__(1024) void k_norm2(const double* __restrict__ u, int64_t m,
                                                 double* __restrict__ sc, int slot) {
   __shared__ double buf[16];
@@ -652,6 +676,15 @@ void launch_step_one(int64_t n, int64_t m, int s, double* x, double* y, double* 
                      double* dx, double* sc, hipStream_t st) {
   hipLaunchKernelGGL(k_step_one, dim3(1), dim3(kVecThreads), 0, st, n, m, s, x, y, sv, d2, ds,
                      dy, bucket, sign, tw, wt, v, dx, sc);
+}
+
+void launch_fill_f64_flag(double* p, double v, int64_t n, int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f64_flag, dim3(grid_for(n)), dim3(256), 0, st, p, v, n, flag);
+}
+
+void launch_v_init(double* tw, int64_t w, double* rv, const double* g, int64_t m, double* sc,
+                   int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_v_init, dim3(1), dim3(1024), 0, st, tw, w, rv, g, m, sc, slot);
 }
 
 void launch_mu_finalize(const double* red, int nblk, int64_t n, double* sc, hipStream_t st) {
