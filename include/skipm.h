@@ -44,7 +44,9 @@ extern "C" {
 #define SKIPM_EINVAL   (-1)  /* bad argument (sizes, null pointers, parameter ranges) */
 #define SKIPM_ENOMEM   (-2)  /* device allocation failed */
 #define SKIPM_EDEVICE  (-3)  /* a HIP runtime call failed */
-#define SKIPM_ERANK    (-4)  /* sketch A D W lost rank (Lemma 3's failure event), after re-sketching */
+#define SKIPM_ERANK    (-4)  /* the Gram matrix of the sketch A D W kept a non-positive Cholesky
+                                pivot (Lemma 3's failure event, rank(A D W) < m) through 3 fresh
+                                sketches (new salts) and then 3 growing diagonal shifts */
 #define SKIPM_ENOTCONV (-5)  /* max_outer iterations reached without meeting the stopping test */
 #define SKIPM_ESTALL   (-6)  /* step length below 1e-12 three times in a row */
 #define SKIPM_ENAN     (-7)  /* non-finite iterate */
@@ -66,7 +68,16 @@ extern "C" {
 #define SKIPM_PREC_FP64  0   /* everything FP64 */
 #define SKIPM_PREC_MIXED 1   /* CG products read an FP32 copy of A (FP64 accumulation) inside
                                 an iterative refinement on FP64 residuals; residuals, v,
-                                step length and preconditioner FP64 */
+                                step length and preconditioner FP64.  Escalates to FP64
+                                products (tier SKIPM_TIER_FP64) when the refinement needs
+                                too many steps. */
+#define SKIPM_PREC_BF16  2   /* as SKIPM_PREC_MIXED, starting one tier lower: CG products read
+                                a BF16 copy of A, then escalate BF16 -> FP32 -> FP64 */
+
+/* precision tier of the CG products of one IPM iteration */
+#define SKIPM_TIER_FP64 0
+#define SKIPM_TIER_FP32 1
+#define SKIPM_TIER_BF16 2
 
 typedef struct skipm_lp_s* skipm_lp_t;
 
@@ -99,10 +110,11 @@ typedef struct {
   double guard;      /* step <= (1-guard) x distance to the boundary of x, s > 0  [1e-3] */
   int32_t w;         /* sketch width, m <= w  [0 = 4m]                                 */
   int32_t s;         /* non-zeros per row of W, s divides w  [1]                       */
-  int32_t max_cg;    /* CG iteration cap per solve  [500]                              */
+  int32_t max_cg;    /* CG iteration cap per normal-equation solve, counted over all the
+                        inner CG runs of the refinement in SKIPM_PREC_MIXED / _BF16  [500] */
   int32_t max_outer; /* IPM iteration cap  [300]                                       */
   int32_t resketch;  /* 1: fresh W every IPM iteration (salt = iteration), 0: one W  [1] */
-  int32_t precision; /* SKIPM_PREC_FP64 or SKIPM_PREC_MIXED  [FP64]                    */
+  int32_t precision; /* SKIPM_PREC_FP64, SKIPM_PREC_MIXED or SKIPM_PREC_BF16  [FP64]   */
   uint64_t seed;     /* sketch seed  [0]                                               */
   int32_t inner;     /* solver of Alg. 2 step (c): SKIPM_INNER_CG (Alg. 1), _SD (steepest
                         descent, App. B Alg. 4) or _RICHARDSON (App. A Alg. 3)  [CG]   */
@@ -123,6 +135,11 @@ typedef struct {
   double rp_norm;    /* ||A x - b|| */
   double rd_norm;    /* ||A^T y + s - c|| */
   double mu;         /* x^T s / n */
+  int32_t demote_iter;  /* first IPM iteration whose CG products moved up a precision tier
+                           (SKIPM_PREC_MIXED / _BF16), -1 if none did */
+  int32_t tier_final;   /* SKIPM_TIER_* of the CG products at the end of the run */
+  int32_t resketches;   /* fresh sketches drawn after a non-positive Gram pivot, summed */
+  int32_t shifts;       /* diagonally shifted factorisations after those, summed */
 } skipm_result;
 
 /* Diagnostics of one IPM iteration (host struct). */
@@ -142,6 +159,10 @@ typedef struct {
   int32_t v_iters;   /* refinement steps of the FP64 solve for t inside v */
   int32_t converged; /* 1: the stopping test held at the start, nothing was done */
   int32_t status;    /* SKIPM_OK or an error code */
+  int32_t tier;      /* SKIPM_TIER_* of the CG products when this iteration's solve ended */
+  int32_t refine_steps; /* outer refinement steps of the normal-equation solve (1 in FP64) */
+  int32_t resketches;   /* fresh sketches drawn after a non-positive Gram pivot */
+  int32_t shifts;       /* diagonally shifted factorisations after those */
 } skipm_step_info;
 
 /* Result of pcg_solve (host struct). */
@@ -160,7 +181,10 @@ int skipm_params_default(skipm_params* out);
  * (the experiments' all-ones start with y = 0).  Synchronises `stream`.
  * Dense FP64 LPs with m <= 64 whose A takes at most 1 MiB run each CG solve
  * in one workgroup (one launch); the environment variable
- * SKIPM_CG_SMALL_BYTES, read here, sets that limit in bytes (0: never). */
+ * SKIPM_CG_SMALL_BYTES, read here, sets that limit in bytes (0: never).
+ * LPs with n <= 1024 run the step tail of Alg. 2 (steps d-g) in one
+ * workgroup; SKIPM_STEP_ONE=0, read here, keeps the multi-launch tail, which
+ * computes the same sums in the same order. */
 int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* prm,
               hipStream_t stream);
 
@@ -183,6 +207,15 @@ int lp_get_iterate(skipm_lp_t lp, double* x, double* y, double* s, hipStream_t s
 /* Copy the last computed direction (dx, ds, v: n; dy: m) out (device pointers;
  * any may be NULL).  Valid after ipm_step. */
 int lp_get_direction(skipm_lp_t lp, double* dx, double* dy, double* ds, double* v,
+                     hipStream_t stream);
+
+/* Copy the vectors of the last ipm_step out (device pointers; any may be
+ * NULL): the prologue's residuals r_p = A x - b (m) and r_d = A^T y + s - c (n)
+ * (eqs. "primalres", "dualres") and right-hand side p (m, eq. "pdef"), and the
+ * epilogue's g = A D^2 A^T dy - p (m), the residual that the correction vector
+ * v of eq. "compv" cancels (eq. "addl").  pcg_solve leaves its right-hand side
+ * in g. */
+int lp_get_residuals(skipm_lp_t lp, double* rp, double* rd, double* p, double* g,
                      hipStream_t stream);
 
 /* The sparse embedding W used at IPM iteration (salt) k: for every row j < n

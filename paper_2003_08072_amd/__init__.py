@@ -35,6 +35,10 @@ SKIPM_SKETCH_COUNT = 0
 SKIPM_SKETCH_GAUSSIAN = 1
 SKIPM_PREC_FP64 = 0
 SKIPM_PREC_MIXED = 1
+SKIPM_PREC_BF16 = 2
+SKIPM_TIER_FP64 = 0
+SKIPM_TIER_FP32 = 1
+SKIPM_TIER_BF16 = 2
 
 
 class Problem(C.Structure):
@@ -56,7 +60,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cg_total", C.c_int32),
                 ("cg_max", C.c_int32), ("obj_p", C.c_double), ("obj_d", C.c_double),
                 ("rel_gap", C.c_double), ("rp_norm", C.c_double), ("rd_norm", C.c_double),
-                ("mu", C.c_double)]
+                ("mu", C.c_double), ("demote_iter", C.c_int32), ("tier_final", C.c_int32),
+                ("resketches", C.c_int32), ("shifts", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -64,7 +69,9 @@ class StepInfo(C.Structure):
                 ("rel_gap", C.c_double), ("eta", C.c_double), ("alpha_max", C.c_double),
                 ("alpha", C.c_double), ("f_norm", C.c_double), ("f0_norm", C.c_double),
                 ("v_norm", C.c_double), ("v_resid", C.c_double), ("cg_iters", C.c_int32),
-                ("v_iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32)]
+                ("v_iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("tier", C.c_int32), ("refine_steps", C.c_int32), ("resketches", C.c_int32),
+                ("shifts", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -97,6 +104,7 @@ SIGNATURES = {
     "lp_set_iterate": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP]),
     "lp_get_iterate": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "lp_get_direction": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "lp_get_residuals": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "sketch_hash": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _VP, _VP,
                               _VP]),
     "sketch_apply": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP]),
@@ -260,6 +268,10 @@ class SolveResult:
     rp_norm: float
     rd_norm: float
     mu: float
+    demote_iter: int = -1
+    tier_final: int = 0
+    resketches: int = 0
+    shifts: int = 0
 
     @property
     def ok(self):
@@ -334,6 +346,17 @@ class LP:
                                           _stream(self.stream)), "lp_get_direction")
         return dx, dy, ds, v
 
+    def get_residuals(self):
+        """(r_p, r_d, p, g) of the last step (lp_get_residuals)."""
+        import torch
+        rp = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        rd = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        p = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        _check(self._lib.lp_get_residuals(self.handle, _ptr(rp), _ptr(rd), _ptr(p), _ptr(g),
+                                          _stream(self.stream)), "lp_get_residuals")
+        return rp, rd, p, g
+
     def sketch(self, d, k):
         """B = A diag(d) W_k as an (m, w) float64 tensor."""
         import torch
@@ -385,8 +408,7 @@ class LP:
         code = self._lib.lp_solve(self.handle, C.byref(res), _stream(self.stream))
         if raise_on_error:
             _check(code, "lp_solve")
-        return SolveResult(code, res.iters, res.cg_total, res.cg_max, res.obj_p, res.obj_d,
-                           res.rel_gap, res.rp_norm, res.rd_norm, res.mu)
+        return _result(res, code)
 
     def kernel_timing(self, every=8):
         """Sample the CG's normal-equation product with HIP events (0: off)."""
@@ -413,7 +435,7 @@ class LP:
 def _result(res: Result, status=None) -> SolveResult:
     return SolveResult(res.status if status is None else status, res.iters, res.cg_total,
                        res.cg_max, res.obj_p, res.obj_d, res.rel_gap, res.rp_norm, res.rd_norm,
-                       res.mu)
+                       res.mu, res.demote_iter, res.tier_final, res.resketches, res.shifts)
 
 
 def solve_batch(lps, workers=0):

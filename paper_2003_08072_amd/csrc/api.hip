@@ -27,6 +27,7 @@
 #include <rocblas/rocblas.h>
 
 #include "common.h"
+#include "vrefine.h"
 
 namespace skipm {
 static thread_local std::string g_err;
@@ -63,8 +64,17 @@ struct skipm_lp_s {
   double *B1 = nullptr, *B2 = nullptr, *Gv = nullptr, *Xv = nullptr, *M1 = nullptr,
          *M2 = nullptr, *rv = nullptr, *uv1 = nullptr, *uv2 = nullptr;
   double *rt = nullptr, *dyc = nullptr;  // mixed precision: FP64 residual and correction
+  // correction vector: the best t so far and its residual (tw, rv), and the
+  // candidate of the current refinement step (tw2, rv2)
+  double *tw2 = nullptr, *rv2 = nullptr;
   int last_outer = 0;
-  int demoted = 0;  // mixed precision switched to FP64 CG for the rest of this run
+  // precision tier of the CG products (SKIPM_TIER_*): start_tier from the
+  // parameters, tier the current one (it only moves up within a run)
+  int start_tier = SKIPM_TIER_FP64, tier = SKIPM_TIER_FP64;
+  int demote_iter = -1;  // IPM iteration of the first move up, -1 if none
+  // rank-loss handling of the current solve and of the run (Lemma 3)
+  int step_resketches = 0, step_shifts = 0;
+  int run_resketches = 0, run_shifts = 0;
   int vrounds_built = 0;
   // CSR storage (format SKIPM_CSR)
   SparseA sp;
@@ -97,6 +107,7 @@ struct skipm_lp_s {
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
   int64_t small_cg_bytes = 0;  // dense CG in one workgroup when A's CG copy is at most this
+  int step_one = 1;  // one-workgroup step tail where the n-vector passes take one workgroup
   std::vector<void*> allocs;
   // sampled HIP-event timing of the CG's normal-equation product (lp_kernel_timing):
   // event pairs around every kt_every-th product, harvested at the CG's host checks
@@ -182,10 +193,6 @@ int run_colpass(ColPass& cp, hipStream_t st) {
   return SKIPM_OK;
 }
 
-// A pass over A (values of type ta) streams it with non-temporal loads once A
-// takes most of the 256 MiB Infinity Cache (240 MiB: measured, 200.8 MB read
-// 16 % faster cached, 263 MB 1.6 % faster streamed); a smaller one stays cached.
-constexpr int64_t kStreamBytes = (int64_t)240 << 20;
 int stream_A(const skipm_lp_s* lp, int ta) {
   return lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4) > kStreamBytes ? 1 : 0;
 }
@@ -388,7 +395,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;
-  if (lp->mixed) {  // FP32 copy of A, FP64 accumulation
+  if (lp->tier == SKIPM_TIER_FP32) {  // FP32 copy of A, FP64 accumulation
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
     cp.nt = stream_A(lp, SKIPM_F32);
@@ -461,11 +468,12 @@ int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, cons
 int pcg_small(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
               int* its, int* fact_fail, hipStream_t st) {
   if (lp->fmt != SKIPM_DENSE || lp->small_cg_bytes <= 0) return 0;
-  const int ta = lp->mixed ? SKIPM_F32 : lp->a_dtype;
+  const bool f32 = lp->tier == SKIPM_TIER_FP32;
+  const int ta = f32 ? SKIPM_F32 : lp->a_dtype;
   const int64_t bytes = lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4);
   if (bytes > lp->small_cg_bytes) return 0;
   SmallCg a;
-  a.A = lp->mixed ? (const void*)lp->A32 : lp->A;
+  a.A = f32 ? (const void*)lp->A32 : lp->A;
   a.lda = lp->lda;
   a.m = lp->m;
   a.n = lp->n;
@@ -545,46 +553,57 @@ int normal_residual_fp64(skipm_lp_s* lp, const double* rhs, const double* x, hip
   return SKIPM_OK;
 }
 
-constexpr int kMixedMaxOuter = 4;
+// Outer refinement steps after which the current tier's copy of A counts as
+// too coarse for this iterate (kappa(A D) too large): the rest of this solve,
+// and of the run, takes the products one tier up.
+constexpr int kRefineMaxOuter = 4;
+constexpr int kRefineCap = 8;
+
+// One precision tier up (BF16 -> FP32 -> FP64); records the first move.
+void escalate_tier(skipm_lp_s* lp) {
+  if (lp->tier == SKIPM_TIER_FP64) return;
+  lp->tier = lp->tier == SKIPM_TIER_BF16 ? SKIPM_TIER_FP32 : SKIPM_TIER_FP64;
+  if (lp->demote_iter < 0) lp->demote_iter = (int)lp->k;
+}
 
 // Mixed precision: iterative refinement with FP64 residuals around a CG whose
-// products use the FP32 copy of A.  Stops on the same test as the FP64 CG,
-// sqrt(r^T Q^{-1} r) <= tol sqrt(p^T Q^{-1} p), with r the FP64 residual.
-int pcg_mixed(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it, int* its,
-              int* fact_fail, hipStream_t st) {
+// products read the current tier's low-precision copy of A (FP64
+// accumulation).  Stops on the same test as the FP64 CG,
+// sqrt(r^T Q^{-1} r) <= tol sqrt(p^T Q^{-1} p), with r the FP64 residual, or
+// once the inner runs together have taken max_it CG iterations.
+int pcg_refined(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
+                int* its, int* fact_fail, hipStream_t st) {
   launch_fill_f64(xsol, 0.0, lp->m, st);
   launch_copy_f64(lp->rt, rhs, lp->m, st);
   double rho0 = -1, rho = 0;
   int total = 0;
   *fact_fail = 0;
-  const int max_outer = 6;
   int outer = 0;
-  for (; outer < max_outer; ++outer) {
+  for (; outer < kRefineCap; ++outer) {
+    const int budget = max_it - total;
+    if (budget <= 0) break;  // the solve's CG cap is spent
     // The inner CG is consistent (FP64 accumulation), so it can go straight to
-    // the target; further outer steps only correct the FP32 rounding of A.
+    // the target; further outer steps only correct the rounding of A's copy.
     const double rel_target = rho0 > 0 && rho > 0 ? tol * rho0 / rho : tol;
     const double inner_tol = std::min(0.5, rel_target);
     int inner = 0;
     const int first = std::max(2, outer == 0 ? lp->prev_cg - 1 : lp->prev_cg / 3);
-    SK_TRY(pcg_run(lp, lp->rt, lp->dyc, tol > 0 ? inner_tol : 0.0, max_it, first, &inner,
+    SK_TRY(pcg_run(lp, lp->rt, lp->dyc, tol > 0 ? inner_tol : 0.0, budget, first, &inner,
                    fact_fail, st));
     if (*fact_fail) return SKIPM_OK;
-    // If refinement needs many outer steps, the FP32 copy of A is too coarse
-    // for this iterate (kappa(A D) too large): finish this solve, and the rest
-    // of the run, with FP64 products.
-    if (outer + 1 >= kMixedMaxOuter) {
-      lp->demoted = 1;
-      lp->mixed = false;
-    }
+    if (outer + 1 >= kRefineMaxOuter) escalate_tier(lp);
     if (rho0 < 0) rho0 = sqrt(std::max(0.0, lp->hsc[S_CG_RZ0]));
     total += inner;
     launch_axpy(xsol, lp->dyc, 1.0, lp->m, st);
     SK_TRY(normal_residual_fp64(lp, rhs, xsol, st));
     SK_TRY(sync_read(lp, st));
     rho = sqrt(std::max(0.0, lp->hsc[S_RHO2]));
-    if (!(rho0 > 0) || rho <= tol * rho0 || tol <= 0) break;
+    if (!(rho0 > 0) || rho <= tol * rho0 || tol <= 0) {
+      ++outer;
+      break;
+    }
   }
-  lp->last_outer = outer + 1;
+  lp->last_outer = std::max(outer, 1);
   // report the FP64 residual in the CG slots
   lp->hsc[S_CG_RZ0] = rho0 * rho0;
   lp->hsc[S_CG_RZ] = rho * rho;
@@ -592,24 +611,54 @@ int pcg_mixed(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int m
   return SKIPM_OK;
 }
 
-// sketch + factor + CG with rank-failure retries (shifted Gram).
-int solve_normal(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
-                 int* its, hipStream_t st) {
+int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, double* B,
+                hipStream_t st);
+
+// Alg. 1 for one right-hand side: the sketch B = A D W with this salt, Q^{-1}
+// from its Gram matrix, then CG.  A non-positive pivot of the Gram matrix is
+// Lemma 3's failure event (rank(A D W) < m): the sketch is drawn again with a
+// fresh salt, up to kFreshSketches times.  If every sketch fails, A D itself
+// is numerically rank deficient and the last sketch's Gram matrix is factored
+// with a growing relative diagonal shift (kShifts times) before SKIPM_ERANK.
+constexpr int kFreshSketches = 3, kShifts = 3;
+
+int sketch_solve(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt,
+                 const double* rhs, double* xsol, double tol, int max_it, int* its,
+                 hipStream_t st) {
+  lp->step_resketches = 0;
+  lp->step_shifts = 0;
+  lp->last_outer = 1;
   double shift = 0.0;
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  int rc = SKIPM_ERANK;
+  for (int attempt = 0; attempt <= kFreshSketches + kShifts; ++attempt) {
+    if (attempt <= kFreshSketches) {
+      // fresh salts sit far above any IPM iteration index
+      const int64_t sa = salt + ((int64_t)attempt << 40);
+      SK_TRY(sketch_into(lp, dscale, is_d2, sa, lp->B, st));
+      if (attempt > 0) ++lp->step_resketches;
+    } else {
+      shift = shift == 0.0 ? 1e-12 : shift * 1e3;
+      ++lp->step_shifts;
+    }
     SK_TRY(factor(lp, shift, st));
     int fail = 0;
-    if (lp->mixed) {
-      SK_TRY(pcg_mixed(lp, rhs, xsol, tol, max_it, its, &fail, st));
+    if (lp->tier != SKIPM_TIER_FP64) {
+      SK_TRY(pcg_refined(lp, rhs, xsol, tol, max_it, its, &fail, st));
     } else {
       const int first = std::max(2, lp->prev_cg - 1);
       SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first, its, &fail, st));
     }
-    if (!fail) return SKIPM_OK;
-    shift = shift == 0.0 ? 1e-12 : shift * 1e3;
+    if (!fail) {
+      rc = SKIPM_OK;
+      break;
+    }
   }
-  set_error("sketch A D W is numerically rank deficient (non-positive Gram pivot)");
-  return SKIPM_ERANK;
+  lp->run_resketches += lp->step_resketches;
+  lp->run_shifts += lp->step_shifts;
+  if (rc != SKIPM_OK)
+    set_error("the sketch's Gram matrix kept a non-positive pivot through fresh sketches and "
+              "diagonal shifts (rank(A D W) < m)");
+  return rc;
 }
 
 int gaussian_ready(skipm_lp_s* lp) {
@@ -790,8 +839,8 @@ int sketch_t_apply(skipm_lp_s* lp, const double* Bk, const double* u, double* ou
   return run_colpass(cp, st);
 }
 
-// rv = g - B t ; S_V_RR = ||rv||^2
-int true_residual(skipm_lp_s* lp, hipStream_t st) {
+// out = g - B t ; S_V_RR = ||out||^2
+int true_residual(skipm_lp_s* lp, const double* t, double* out, hipStream_t st) {
   ColPass cp{};
   cp.mode = COL_AXPY;
   cp.A = lp->B;
@@ -800,14 +849,13 @@ int true_residual(skipm_lp_s* lp, hipStream_t st) {
   cp.lda = lp->lda;
   cp.m = lp->m;
   cp.n = lp->w;
-  cp.d2 = lp->tw;
+  cp.d2 = t;
   cp.part = lp->part;
   cp.ldp = lp->mp;
   cp.nblk = lp->nblk_B;
   SK_TRY(run_colpass(cp, st));
-  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, -1.0, lp->g, 1.0, lp->rv, nullptr,
-                st);
-  launch_norm2(lp->rv, lp->m, lp->sc, S_V_RR, st);
+  launch_finish(lp->part, lp->mp, 0, cp.nblk, lp->m, -1.0, lp->g, 1.0, out, nullptr, st);
+  launch_norm2(out, lp->m, lp->sc, S_V_RR, st);
   return SKIPM_OK;
 }
 
@@ -818,8 +866,9 @@ int spd_inverse_checked(skipm_lp_s* lp, double* Gm, double* Xm, hipStream_t st) 
   return SKIPM_OK;
 }
 
-// Build round K (1 or 2) of the whitening.
-int build_vround(skipm_lp_s* lp, int K, hipStream_t st) {
+// Build round K (1 or 2) of the whitening.  *ok = 0 when neither the round's
+// Gram matrix nor its shifted form has a Cholesky factor (the round is unusable).
+int build_vround(skipm_lp_s* lp, int K, int* ok, hipStream_t st) {
   SK_TRY(alloc_vbuffers(lp));
   const int64_t mp = lp->mp, mm = mp * mp;
   if (K == 1) {
@@ -840,8 +889,14 @@ int build_vround(skipm_lp_s* lp, int K, hipStream_t st) {
     launch_shift_trace(lp->Gv, mp, lp->m, 11.0 * (double)(lp->w * lp->m + lp->m * (lp->m + 1)) *
                                               1.1102230246251565e-16, st);
     SK_TRY(spd_inverse_checked(lp, lp->Gv, lp->Xv, st));
+    SK_TRY(sync_read(lp, st));
+    if (host_ints(lp)[I_FACT_FAIL]) {
+      *ok = 0;
+      return SKIPM_OK;
+    }
   }
   lp->vrounds_built = K;
+  *ok = 1;
   return SKIPM_OK;
 }
 
@@ -856,40 +911,47 @@ int pinv_apply(skipm_lp_s* lp, int K, hipStream_t st) {
   return sketch_t_apply(lp, K == 1 ? lp->B1 : lp->B2, lp->uv2, lp->tq, st);
 }
 
+// t = (A D W)^+ g by refinement (policy in vrefine.h).  Each step forms the
+// candidate t' = t + P (g - B t) and its true residual beside the kept t, and
+// keeps it only if its residual is finite and smaller, so the t that eq. compv
+// turns into v is always the best one found.  A non-finite g (nothing to
+// refine against) is reported as SKIPM_ENAN.
 int v_solve(skipm_lp_s* lp, int* its, double* rel_out, hipStream_t st) {
-  const double target = 1e-14;
-  const int max_steps = 12;
   lp->vrounds_built = 0;
-  launch_v_init(lp->tw, lp->w, lp->rv, lp->g, lp->m, lp->sc, S_V_GG, st);
+  launch_v_init(lp->tw, lp->w, lp->rv, lp->g, lp->m, lp->sc, S_V_GG, st);  // t = 0, r = g
   *its = 0;
   *rel_out = 0.0;
-  int K = 0;
-  double rel_prev = 1.0;
+  VRefine pol;
   // ||g||^2 is read with the first step's residual (one host read fewer); a
-  // zero (or non-finite) g gives t = 0 without refinement, as if tested first
-  for (int step = 0; step < max_steps; ++step) {
-    SK_TRY(pinv_apply(lp, K, st));
-    launch_axpy(lp->tw, lp->tq, 1.0, lp->w, st);
-    SK_TRY(true_residual(lp, st));
+  // zero g gives t = 0 without refinement, as if tested first
+  for (;;) {
+    SK_TRY(pinv_apply(lp, pol.round, st));
+    launch_add_f64(lp->tw2, lp->tw, lp->tq, lp->w, st);
+    SK_TRY(true_residual(lp, lp->tw2, lp->rv2, st));
     SK_CHECK_HIP(hipGetLastError());
     SK_TRY(sync_read(lp, st));
     const double gg = lp->hsc[S_V_GG];
-    if (!(gg > 0.0)) {
-      launch_fill_f64(lp->tw, 0.0, lp->w, st);
-      SK_CHECK_HIP(hipGetLastError());
-      return SKIPM_OK;
+    if (!std::isfinite(gg)) {
+      set_error("non-finite residual g of the normal equations");
+      return SKIPM_ENAN;
     }
-    const double rel = sqrt(std::max(0.0, lp->hsc[S_V_RR]) / gg);
-    *its = step + 1;
-    *rel_out = rel;
-    if (!(rel > target)) break;
-    if (K < 2 && rel > 1e-2 * rel_prev) {
-      K += 1;
-      SK_TRY(build_vround(lp, K, st));
-    } else if (rel > 0.5 * rel_prev) {
-      break;  // stagnated at the attainable accuracy
+    if (!(gg > 0.0)) return SKIPM_OK;  // g = 0: t stays 0
+    const double rr = lp->hsc[S_V_RR];
+    const double rel = std::isfinite(rr) && rr >= 0.0 ? sqrt(rr / gg) : NAN;
+    bool keep = false;
+    const VAct act = v_refine_next(pol, rel, &keep);
+    if (keep) {
+      std::swap(lp->tw, lp->tw2);
+      std::swap(lp->rv, lp->rv2);
     }
-    rel_prev = std::min(rel_prev, rel);
+    *its = pol.steps;
+    *rel_out = pol.best;
+    if (act == V_STOP) break;
+    if (act == V_BUILD) {
+      int ok = 0;
+      SK_TRY(build_vround(lp, pol.round, &ok, st));
+      if (!ok) break;  // no better pseudo-inverse: keep the best t
+    }
   }
   return SKIPM_OK;
 }
@@ -905,7 +967,7 @@ int finish_step(skipm_lp_s* lp, hipStream_t st) {
       return set_error("rocblas_dgemv (Gaussian sketch) failed"), SKIPM_EDEVICE;
     wt = lp->gy;
   }
-  if (lp->nblk_vec == 1) {
+  if (lp->nblk_vec == 1 && lp->step_one) {
     launch_step_one(lp->n, lp->m, lp->s, lp->x, lp->y, lp->sv, lp->d2, lp->ds, lp->dy, lp->bucket,
                     lp->sign, lp->tw, wt, lp->v, lp->dx, lp->sc, st);
     SK_CHECK_HIP(hipGetLastError());
@@ -962,9 +1024,8 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
   int its = 0;
   int rc = SKIPM_OK;
   if (defer) {
-    rc = sketch_into(lp, lp->d2, 1, salt, lp->B, st);
-    if (rc == SKIPM_OK)
-      rc = solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st);
+    rc = sketch_solve(lp, lp->d2, 1, salt, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its,
+                      st);
   }
   if (!defer || rc != SKIPM_OK) SK_TRY(sync_read(lp, st));
   // the prologue's x^T s is the same quantity as the update's; S_XS holds the
@@ -978,6 +1039,7 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
     info->rd_norm = ss.rd;
     info->rel_gap = ss.rel_gap;
     info->eta = lp->hsc[S_ETA];
+    info->tier = lp->tier;
   }
   if (ss.nan) {
     set_error("non-finite iterate");
@@ -996,10 +1058,17 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
     if (info) info->converged = 1;
     return SKIPM_OK;
   }
-  if (!defer) {
-    SK_TRY(sketch_into(lp, lp->d2, 1, salt, lp->B, st));
-    SK_TRY(solve_normal(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its, st));
-  } else if (rc != SKIPM_OK) {
+  if (!defer)
+    rc = sketch_solve(lp, lp->d2, 1, salt, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &its,
+                      st);
+  if (info) {
+    info->tier = lp->tier;
+    info->refine_steps = lp->last_outer;
+    info->resketches = lp->step_resketches;
+    info->shifts = lp->step_shifts;
+  }
+  if (rc != SKIPM_OK) {
+    if (info) info->status = rc;
     return rc;
   }
   ks_harvest(lp);  // the CG's host checks have waited past the sketch
@@ -1009,7 +1078,11 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
   SK_TRY(epilogue(lp, st));
   int vits = 0;
   double vrel = 0;
-  SK_TRY(v_solve(lp, &vits, &vrel, st));
+  rc = v_solve(lp, &vits, &vrel, st);
+  if (rc != SKIPM_OK) {
+    if (info) info->status = rc;
+    return rc;
+  }
   SK_TRY(finish_step(lp, st));
   lp->k += 1;
   if (info) {
@@ -1100,9 +1173,10 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
     nblk_csc = csc_dot_nblk(n);
   }
   for (int i = 0; i < 8; ++i) add(8 * n);    // c x s d2 r_d dx ds v
-  for (int i = 0; i < 18; ++i) add(8 * mp);  // m-vectors
+  for (int i = 0; i < 19; ++i) add(8 * mp);  // m-vectors
   add(8 * ((csr ? csr_fold_nblk(m) : finish_nblk(m)) +
            2 * (int64_t)colpass_nblk_dot(mp, m, SKIPM_F64)));  // CG partials
+  add(8 * w);
   add(8 * w);
   add(8 * w);
   add(8 * lda * w);  // B
@@ -1220,10 +1294,10 @@ int lp_reset(skipm_lp_t lp, hipStream_t st) {
   lp->last_rel_gap = HUGE_VAL;
   lp->origin_pending = 1;
   lp->small_steps = 0;
-  if (lp->demoted) {
-    lp->demoted = 0;
-    lp->mixed = true;
-  }
+  lp->tier = lp->start_tier;
+  lp->demote_iter = -1;
+  lp->run_resketches = 0;
+  lp->run_shifts = 0;
   SK_TRY(mu_from_iterate(lp, st));
   SK_CHECK_HIP(hipStreamSynchronize(st));
   return SKIPM_OK;
@@ -1268,6 +1342,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   // a CSR problem's values are read as stored (FP32 or FP64) with FP64
   // accumulation in every pass, so it has no separate mixed mode
   lp->mixed = prm->precision == SKIPM_PREC_MIXED && !csr;
+  lp->start_tier = lp->mixed ? SKIPM_TIER_FP32 : SKIPM_TIER_FP64;
+  lp->tier = lp->start_tier;
   lp->lda = round_up(m, 4);
   lp->mp = round_up(m, 64);
   const int64_t mp = lp->mp, lda = lp->lda, w = lp->w;
@@ -1383,6 +1459,9 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     // size limit of A's CG copy (0 turns it off)
     lp->small_cg_bytes = 1 << 20;
     if (const char* e = getenv("SKIPM_CG_SMALL_BYTES")) lp->small_cg_bytes = atoll(e);
+    // SKIPM_STEP_ONE=0 keeps the multi-launch step tail for every n (the
+    // one-workgroup tail computes the same sums in the same order)
+    if (const char* e = getenv("SKIPM_STEP_ONE")) lp->step_one = atoi(e) != 0;
   }
   lp->cg_nd = colpass_nblk_dot(mp, m, SKIPM_F64);
   ALLOC(lp->cgred, lp->cg_nf + 2 * (int64_t)lp->cg_nd);
@@ -1390,11 +1469,13 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cw, mp);
   ALLOC(lp->cx, mp);
   ALLOC(lp->rv, mp);
+  ALLOC(lp->rv2, mp);
   ALLOC(lp->rt, mp);
   ALLOC(lp->dyc, mp);
   ALLOC(lp->uv1, mp);
   ALLOC(lp->uv2, mp);
   ALLOC(lp->tw, w);
+  ALLOC(lp->tw2, w);
   ALLOC(lp->tq, w);
   ALLOC(lp->B, lda * w);
   {
@@ -1443,8 +1524,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   launch_fill_f64(lp->sc, 0.0, S_NSLOTS, st);
   launch_fill_i32(lp->is, 0, I_NINTS, st);
   double* zero_vecs[] = {lp->b,  lp->y,  lp->rp, lp->p,  lp->dy, lp->g,  lp->cr,  lp->cz,
-                         lp->cd, lp->cd2, lp->cq, lp->cw, lp->cx, lp->rv, lp->uv1, lp->uv2,
-                         lp->rt, lp->dyc};
+                         lp->cd, lp->cd2, lp->cq, lp->cw, lp->cx, lp->rv, lp->rv2, lp->uv1,
+                         lp->uv2, lp->rt, lp->dyc};
   for (double* z : zero_vecs) launch_fill_f64(z, 0.0, mp, st);
   launch_fill_f64(lp->B, 0.0, lda * w, st);
   launch_copy_f64(lp->b, prob->b, m, st);
@@ -1516,6 +1597,19 @@ int lp_get_direction(skipm_lp_t lp, double* dx, double* dy, double* ds, double* 
   return SKIPM_OK;
 }
 
+int lp_get_residuals(skipm_lp_t lp, double* rp, double* rd, double* p, double* g,
+                     hipStream_t st) {
+  if (!lp) return set_error("null handle"), SKIPM_EINVAL;
+  SK_CHECK_HIP(hipSetDevice(lp->device));
+  if (rp) launch_copy_f64(rp, lp->rp, lp->m, st);
+  if (rd) launch_copy_f64(rd, lp->rd, lp->n, st);
+  if (p) launch_copy_f64(p, lp->p, lp->m, st);
+  if (g) launch_copy_f64(g, lp->g, lp->m, st);
+  SK_CHECK_HIP(hipGetLastError());
+  SK_CHECK_HIP(hipStreamSynchronize(st));
+  return SKIPM_OK;
+}
+
 int sketch_hash(uint64_t seed, int64_t k, int32_t s, int64_t n, int32_t w, int32_t* bucket,
                 int8_t* sign, hipStream_t st) {
   if (!bucket || !sign) return set_error("null output"), SKIPM_EINVAL;
@@ -1544,9 +1638,8 @@ int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, doubl
   SK_CHECK_HIP(hipSetDevice(lp->device));
   launch_copy_f64(lp->d2, d2, lp->n, st);
   launch_copy_f64(lp->g, p, lp->m, st);  // g doubles as the right-hand side buffer here
-  SK_TRY(sketch_into(lp, lp->d2, 1, k, lp->B, st));
   int its = 0;
-  SK_TRY(solve_normal(lp, lp->g, lp->cx, tol, max_it, &its, st));
+  SK_TRY(sketch_solve(lp, lp->d2, 1, k, lp->g, lp->cx, tol, max_it, &its, st));
   launch_copy_f64(dy, lp->cx, lp->m, st);
   SK_CHECK_HIP(hipGetLastError());
   SK_CHECK_HIP(hipStreamSynchronize(st));
@@ -1600,7 +1693,7 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;
-  if (lp->mixed) {
+  if (lp->tier == SKIPM_TIER_FP32) {
     cp.A = lp->A32;
     cp.ta = SKIPM_F32;
     cp.nt = stream_A(lp, SKIPM_F32);
@@ -1680,6 +1773,10 @@ int lp_solve(skipm_lp_t lp, skipm_result* res, hipStream_t st) {
   res->rp_norm = ss.rp;
   res->rd_norm = ss.rd;
   res->mu = ss.mu;
+  res->demote_iter = lp->demote_iter;
+  res->tier_final = lp->tier;
+  res->resketches = lp->run_resketches;
+  res->shifts = lp->run_shifts;
   if (status != SKIPM_OK && status != SKIPM_ENOTCONV) return status;
   return status == SKIPM_ENOTCONV ? (set_error("max_outer reached"), SKIPM_ENOTCONV) : SKIPM_OK;
 }

@@ -119,28 +119,36 @@ struct skipm_server_s {
   bool head_fits() const {
     return !queue.empty() && queue.front()->info.footprint <= budget - in_use;
   }
-  void run(Req* r, hipStream_t st);
+  struct Outcome {
+    skipm_result res{};
+    int32_t rc = SKIPM_OK;
+    int64_t device_bytes = 0;
+  };
+  void run(Req* r, hipStream_t st, Outcome* out);
   void worker_main();
 };
 
-void skipm_server_s::run(Req* r, hipStream_t st) {
+// Runs one request.  The outcome goes to *out (a copy private to this
+// worker); the caller publishes it into r->info under the lock, so srv_poll
+// never sees a half-written result.
+void skipm_server_s::run(Req* r, hipStream_t st, Outcome* out) {
   int rc = SKIPM_OK;
   if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess) rc = SKIPM_EDEVICE;
   skipm_lp_t lp = nullptr;
   if (rc == SKIPM_OK) rc = lp_create(&lp, &r->prob, &r->prm, st);
   if (rc == SKIPM_OK) {
-    rc = lp_solve(lp, &r->info.res, st);
+    rc = lp_solve(lp, &out->res, st);
     if (rc == SKIPM_ENOTCONV || rc == SKIPM_ESTALL || rc == SKIPM_ERANK || rc == SKIPM_ENAN)
-      rc = SKIPM_OK;  // an outcome of the LP, in info.res.status
+      rc = SKIPM_OK;  // an outcome of the LP, in res.status
     if (rc == SKIPM_OK && r->x_out) rc = lp_get_iterate(lp, r->x_out, nullptr, nullptr, st);
     int64_t held = 0;
     lp_device_bytes(lp, &held);
-    r->info.device_bytes = held;
+    out->device_bytes = held;
   } else {
-    r->info.res.status = rc;
+    out->res.status = rc;
   }
   if (lp) lp_destroy(lp);
-  r->info.rc = rc;
+  out->rc = rc;
 }
 
 void skipm_server_s::worker_main() {
@@ -159,13 +167,17 @@ void skipm_server_s::worker_main() {
     r->info.state = SKIPM_REQ_RUNNING;
     r->info.t_start = now();
     lk.unlock();
+    Outcome oc;
     if (have_stream) {
-      run(r, st);
+      run(r, st, &oc);
     } else {
-      r->info.rc = SKIPM_EDEVICE;
-      r->info.res.status = SKIPM_EDEVICE;
+      oc.rc = SKIPM_EDEVICE;
+      oc.res.status = SKIPM_EDEVICE;
     }
     lk.lock();
+    r->info.res = oc.res;
+    r->info.rc = oc.rc;
+    r->info.device_bytes = oc.device_bytes;
     in_use -= r->info.footprint;
     --running;
     ++completed;

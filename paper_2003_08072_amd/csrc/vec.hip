@@ -563,7 +563,18 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
     y[i] += a * x[i];
 }
 
+__global__ void k_add(double* __restrict__ out, const double* __restrict__ a,
+                      const double* __restrict__ b, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = a[i] + b[i];
+}
+
 }  // namespace
+
+void launch_add_f64(double* out, const double* a, const double* b, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, st, out, a, b, n);
+}
 
 void launch_norm2(const double* u, int64_t m, double* sc, int slot, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, u, m, sc, slot);

@@ -37,8 +37,8 @@ def test_struct_layouts_match_header():
     # sizes follow the C layout of the header structs on x86-64
     assert ctypes.sizeof(sk.Params) == 6 * 8 + 6 * 4 + 8 + 8
     assert ctypes.sizeof(sk.Problem) == 3 * 8 + 2 * 4 + 8 + 8 + 4 * 8
-    assert ctypes.sizeof(sk.Result) == 4 * 4 + 6 * 8
-    assert ctypes.sizeof(sk.StepInfo) == 11 * 8 + 4 * 4
+    assert ctypes.sizeof(sk.Result) == 4 * 4 + 6 * 8 + 4 * 4
+    assert ctypes.sizeof(sk.StepInfo) == 11 * 8 + 8 * 4
 
 
 def test_params_default_values():
@@ -81,8 +81,10 @@ def _c_layouts():
     fields = {
         "skipm_problem": ["m", "nnz", "format", "a_vals", "lda", "a_colidx", "c"],
         "skipm_params": ["sigma", "guard", "w", "s", "precision", "seed", "inner", "sketch"],
-        "skipm_result": ["status", "cg_max", "obj_p", "mu"],
-        "skipm_step_info": ["mu", "v_resid", "cg_iters", "status"],
+        "skipm_result": ["status", "cg_max", "obj_p", "mu", "demote_iter", "tier_final",
+                         "resketches", "shifts"],
+        "skipm_step_info": ["mu", "v_resid", "cg_iters", "status", "tier", "refine_steps",
+                            "resketches", "shifts"],
         "skipm_pcg_info": ["iters", "f0_norm", "f_norm"],
         "skipm_request_info": ["res", "state", "rc", "footprint", "device_bytes", "t_submit",
                                "t_done"],
@@ -169,3 +171,80 @@ def test_batch_and_server_validate_arguments_without_a_device():
     assert lib.srv_create(ctypes.byref(h), 1 << 30, 0) == sk.SKIPM_EINVAL
     assert lib.srv_create(ctypes.byref(h), 0, 4) == sk.SKIPM_EINVAL
     assert lib.srv_destroy(None) == sk.SKIPM_OK
+
+
+def test_result_fields_reach_python():
+    """The precision-tier and rank-loss fields of skipm_result travel through
+    the binding's SolveResult (a host-only round trip of the struct)."""
+    r = sk.Result(status=0, iters=7, demote_iter=3, tier_final=sk.SKIPM_TIER_FP64,
+                  resketches=2, shifts=1)
+    out = sk._result(r)
+    assert (out.demote_iter, out.tier_final, out.resketches, out.shifts) == (3, 0, 2, 1)
+    assert sk.SKIPM_TIER_FP32 == 1 and sk.SKIPM_TIER_BF16 == 2
+
+
+def test_correction_vector_refinement_policy():
+    """The host policy of the refinement for t = (A D W)^+ g (vrefine.h),
+    compiled on its own with g++: a finite, smaller residual replaces the kept
+    t; NaN, inf or a larger residual never does; a poor contraction builds the
+    next pseudo-inverse round while one is left; stagnation or the target ends
+    the refinement."""
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("g++") is None:
+        pytest.skip("g++ missing")
+    hdr = Path(__file__).resolve().parents[1] / "paper_2003_08072_amd" / "csrc"
+    prog = r"""
+#include <cstdio>
+#include <cmath>
+#include "vrefine.h"
+using namespace skipm;
+static void run(const char* name, const double* rel, int n) {
+  VRefine s;
+  printf("%s", name);
+  for (int i = 0; i < n; ++i) {
+    bool keep = false;
+    VAct a = v_refine_next(s, rel[i], &keep);
+    printf(" %d%c%d", (int)a, keep ? 'k' : '-', s.round);
+    if (a == V_STOP) break;
+  }
+  printf(" best=%.3g\n", s.best);
+}
+int main() {
+  const double conv[] = {1e-3, 1e-9, 1e-15};           // good contraction: no rounds built
+  const double slow[] = {0.5, 0.2, 0.1, 1e-16};        // poor contraction: rounds 1 and 2
+  const double nan_[] = {1e-3, NAN, 1e-16};            // NaN never kept; builds a round
+  const double worse[] = {1e-6, 1e-3, 1e-5, 1e-7};     // larger residual rejected
+  const double stag[] = {1e-9, 0.9e-9};                // weak contraction: builds a round
+  const double inf_[] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  run("conv", conv, 3);
+  run("slow", slow, 4);
+  run("nan", nan_, 3);
+  run("worse", worse, 4);
+  run("stag", stag, 2);
+  run("inf", inf_, 4);
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        src = Path(d) / "p.cpp"
+        src.write_text(prog)
+        exe = Path(d) / "p"
+        subprocess.run(["g++", "-std=c++17", f"-I{hdr}", str(src), "-o", str(exe)], check=True)
+        out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    lines = {ln.split()[0]: ln.split()[1:] for ln in out.splitlines()}
+    # 1e-3 from 1: ratio 1e-3 <= 1e-2, next step; 1e-9 ratio 1e-6; 1e-15 meets the target
+    assert lines["conv"] == ["1k0", "1k0", "0k0", "best=1e-15"]
+    # 0.5: build round 1; 0.2 (ratio 0.4): build round 2; 0.1 (ratio 0.5, no
+    # round left): next; 1e-16: target met
+    assert lines["slow"] == ["2k1", "2k2", "1k2", "0k2", "best=1e-16"]
+    # NaN: not kept, counts as no contraction: build round 1; then 1e-16
+    assert lines["nan"] == ["1k0", "2-1", "0k1", "best=1e-16"]
+    # 1e-3 after 1e-6: rejected, build round 1; 1e-5: rejected, round 2;
+    # 1e-7: kept (ratio 0.1, no round left, below 0.5): next
+    assert lines["worse"] == ["1k0", "2-1", "2-2", "1k2", "best=1e-07"]
+    # 0.9e-9 after 1e-9: ratio 0.9 > 1e-2 builds round 1 while rounds are left
+    assert lines["stag"] == ["1k0", "2k1", "best=9e-10"]
+    # never finite: nothing kept; rounds 1, 2 built, then stop with t = 0
+    assert lines["inf"] == ["2-1", "2-2", "0-2", "best=1"]

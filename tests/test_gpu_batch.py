@@ -129,3 +129,58 @@ def test_server_rejects_what_never_fits(torch, sk):
         with pytest.raises(sk.SkipmError) as e:
             srv.submit(lp.A, lp.b, lp.c, a_dtype="f32")
         assert e.value.code == sk.SKIPM_ENOMEM
+
+
+def serving_sample(per_kind=3, dense_cap=2.0e7, csr_cap=4.0e5):
+    """The first requests of the serving trace itself (m log-uniform in
+    [50, 2000], n/m log-uniform in [50, 500]) of each kind whose size keeps
+    a solve within seconds: dense m n <= dense_cap entries, CSR
+    0.01 m n + n <= csr_cap non-zeros (the all-ones row included)."""
+    from lpgen import serving_trace
+    out, got = [], {"dense": 0, "csr": 0}
+    for req in serving_trace():
+        kind = req["kind"]
+        size = req["m"] * req["n"] if kind == "dense" else 0.01 * req["m"] * req["n"] + req["n"]
+        if got[kind] < per_kind and size <= (dense_cap if kind == "dense" else csr_cap):
+            out.append(req)
+            got[kind] += 1
+        if min(got.values()) >= per_kind:
+            break
+    return out
+
+
+def test_server_on_serving_trace_requests(torch, sk):
+    """Requests of the serving workload's own trace (both kinds) through the
+    server with 3 slots and a budget for about two at once: each meets its
+    planted optimum and the KKT bounds, and its result and final x are
+    bitwise those of the same LP solved alone."""
+    from lpgen import serving_lp
+    reqs = serving_sample()
+    lps = [serving_lp(r) for r in reqs]
+    say("server on serving-trace requests: " +
+        ", ".join(f"{r['kind']} {r['m']}x{r['n']}" for r in reqs))
+    assert {r["kind"] for r in reqs} == {"dense", "csr"}
+    kw = [dict(w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap, s=2) for lp in lps]
+    fps = []
+    for lp, k in zip(lps, kw):
+        prob, keep = sk.problem(lp.A, lp.b, lp.c, lp.a_dtype)
+        fps.append(sk.footprint(prob, **k))
+        del keep
+    budget = int(sorted(fps)[-1] + sorted(fps)[-2])
+    alone = []
+    for lp, k in zip(lps, kw):
+        with sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, **k) as h:
+            alone.append((h.solve(), h.get_iterate()[0].cpu().numpy()))
+    with sk.Server(budget, slots=3) as srv:
+        tickets = [srv.submit(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, want_x=True, **k)
+                   for lp, k in zip(lps, kw)]
+        got = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(lps) and st["peak_in_use"] <= budget
+    for lp, (r1, x1), (rq, x2) in zip(lps, alone, got):
+        assert rq.state == sk.SKIPM_REQ_DONE and rq.rc == 0
+        check_planted(lp, rq.result)
+        assert rq.result.rp_norm <= 1e-8 * np.linalg.norm(lp.b)
+        assert rq.result.rd_norm <= 1e-8 * np.linalg.norm(lp.c)
+        same(r1, rq.result)
+        assert np.array_equal(x2.cpu().numpy(), x1)

@@ -316,8 +316,11 @@ def test_ipm_step_parity(torch, sk, iters, s_nnz):
         h.set_iterate(x, y, s, reset_origin=True)
         info = h.step()
         dx, dy, ds, v = (t.cpu().numpy() for t in h.get_direction())
+        rp_gpu, rd_gpu, p_gpu, g_gpu = (t.cpu().numpy() for t in h.get_residuals())
         xn, yn, sn = (t.cpu().numpy() for t in h.get_iterate())
     assert info.converged == 0 and info.status == 0
+    assert info.tier == sk.SKIPM_TIER_FP64 and info.refine_steps == 1
+    assert info.resketches == 0 and info.shifts == 0
     A, b, c = lp.A, lp.b, lp.c
     rp, rd = O.residuals(A, b, c, x, y, s)
     mu = float(x @ s) / lp.n
@@ -329,6 +332,14 @@ def test_ipm_step_parity(torch, sk, iters, s_nnz):
     assert info.rd_norm == pytest.approx(np.linalg.norm(rd), rel=1e-10, abs=tol_rd)
     p = O.normal_rhs(A, b, c, x, y, s, 0.5, mu)
     d2 = x / s
+    # a1 element by element: r_p, r_d and p of eq. pdef against the oracle's
+    # definitions, each within the rounding of the sums that form it
+    aA = abs(A)
+    assert np.all(np.abs(rp_gpu - rp) <= 8 * lp.n * EPS * (aA @ abs(x) + abs(b)))
+    bnd_rd = 8 * lp.m * EPS * (aA.T @ abs(y) + abs(s) + abs(c))
+    assert np.all(np.abs(rd_gpu - rd) <= bnd_rd)
+    bnd_p = 8 * lp.n * EPS * (abs(b) + aA @ (0.5 * mu / s + d2 * (abs(rd) + bnd_rd)))
+    assert np.all(np.abs(p_gpu - p) <= bnd_p + 8 * lp.n * EPS * (aA @ abs(x)))
     g = A @ (d2 * (A.T @ dy)) - p
     # g cancels terms of size ~||p||: compare at the rounding scale of those terms
     scale_g = np.linalg.norm(abs(A) @ (d2 * abs(A.T @ dy))) + np.linalg.norm(p)
@@ -348,6 +359,31 @@ def test_ipm_step_parity(torch, sk, iters, s_nnz):
     W = sketch_matrix(17, 0, s_nnz, lp.n, lp.w)
     ref = O.sketch_direction(A, b, c, x, y, s, 0.5, W, tol_cg=1e-5, max_cg=500)
     assert info.cg_iters == ref.cg_iters
+    # eq. compv element by element, at the g of this step (the GPU's own
+    # epilogue output): the oracle's v = (XS)^{1/2} W (A D W)^+ g with
+    # (A D W)^+ from the SVD.  The GPU refines t on B t = g from t = 0 with
+    # corrections in range(B^T), so it must reach the minimum-norm solution
+    # (A D W)^+ g itself, not just some t with B t = g (Lemma 4 bounds ||v||
+    # for that choice).  Forward error of t: kappa(B) ||t|| times the rounding
+    # of B (sums of at most kmax terms) plus the refinement's own residual
+    # ||B t - g|| / ||g|| (info.v_resid); each entry of W t adds s of them.
+    Bh = A * np.sqrt(d2) @ W.toarray()
+    sv_b = np.linalg.svd(Bh, compute_uv=False)
+    kappa_b = sv_b[0] / sv_b[-1]
+    assert kappa_b <= 1e6, kappa_b
+    kmax = int(np.diff(W.tocsc().indptr).max())
+    vref = O.correction_vector(x, s, W, ref.pcg.U, ref.pcg.sv, ref.pcg.Vh, g_gpu)
+    t_ref = ref.pcg.Vh.T @ ((ref.pcg.U.T @ g_gpu) / ref.pcg.sv)
+    assert 0 <= info.v_resid <= 1e-13
+    err_t = (16 * (kmax + 2) * EPS + 2 * info.v_resid) * kappa_b * np.linalg.norm(t_ref)
+    rt_xs = np.sqrt(x * s)
+    assert np.all(np.abs(v - vref) <= s_nnz * err_t * rt_xs), \
+        float(np.max(np.abs(v - vref) / (rt_xs * s_nnz * err_t)))
+    assert s_nnz * err_t * float(np.max(rt_xs)) <= 1e-6 * float(np.max(np.abs(vref)))
+    # the GPU's g is A D^2 A^T dy - p of its own dy and p, up to the rounding
+    # of the cancelling terms
+    g_own = A @ (d2 * (A.T @ dy)) - p_gpu
+    assert np.linalg.norm(g_gpu - g_own) <= 64 * EPS * scale_g
     # Both are CG iterates stopped at tol_cg; they must agree far below their
     # common distance to the exact Newton direction (the GPU inverts the Gram
     # matrix, the oracle takes an SVD, so the rounding paths differ).
@@ -361,6 +397,100 @@ def test_ipm_step_parity(torch, sk, iters, s_nnz):
     # step (g)
     assert np.allclose(xn, x + info.alpha * dx, rtol=1e-15, atol=1e-300)
     assert np.allclose(yn, y + info.alpha * dy, rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("iters", [2, 6])
+def test_ipm_step_tight_cg_gives_the_exact_direction(torch, sk, iters):
+    """With tol_cg = 1e-13 the step's dy is the exact solution of eq. normal
+    (the oracle's Cholesky solve from the same iterate) to relative 1e-8, on
+    iterates with kappa(A D^2 A^T) <= 1e7; ds of eq. delshat follows from it."""
+    lp = dense_planted(45, 900, rng=np.random.default_rng(33))
+    x, y, s = mid_iterate(lp, iters)
+    N = O.normal_matrix(lp.A, x / s)
+    assert np.linalg.cond(N) <= 1e7
+    say(f"ipm_step with tol_cg 1e-13 from exact-IPM iterate {iters}")
+    with sk.LP(lp.A, lp.b, lp.c, seed=17, s=2, tol_cg=1e-13, max_cg=400) as h:
+        h.set_iterate(x, y, s, reset_origin=True)
+        info = h.step()
+        dx, dy, ds, v = (t.cpu().numpy() for t in h.get_direction())
+    assert info.status == 0 and info.cg_iters < 400
+    exact = O.exact_direction(lp.A, lp.b, lp.c, x, y, s, 0.5)
+    assert np.linalg.norm(dy - exact.dy) <= 1e-8 * np.linalg.norm(exact.dy)
+    assert np.linalg.norm(ds - exact.ds) <= 1e-8 * np.linalg.norm(exact.ds)
+
+
+@contextlib.contextmanager
+def step_tail(path):
+    """LPs created inside run the step tail (Alg. 2 steps d-g) in one
+    workgroup ('one', the default for n <= 1024) or as separate launches
+    ('multi')."""
+    old = os.environ.get("SKIPM_STEP_ONE")
+    if path == "multi":
+        os.environ["SKIPM_STEP_ONE"] = "0"
+    else:
+        os.environ.pop("SKIPM_STEP_ONE", None)
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("SKIPM_STEP_ONE", None)
+        else:
+            os.environ["SKIPM_STEP_ONE"] = old
+
+
+def test_step_tail_one_workgroup_matches_the_launches(torch, sk):
+    """The one-workgroup step tail takes the same per-entry arithmetic and the
+    same sums in the same order as the separate direction, step-length and
+    update launches: one step from a shared iterate, and a whole solve, are
+    bitwise the same on both paths."""
+    lp = dense_planted(45, 900, rng=np.random.default_rng(33))
+    x, y, s = mid_iterate(lp, 4)
+    say("step tail: one workgroup vs separate launches")
+    out = {}
+    for path in ("one", "multi"):
+        with step_tail(path), sk.LP(lp.A, lp.b, lp.c, seed=17, s=2) as h:
+            h.set_iterate(x, y, s, reset_origin=True)
+            info = h.step()
+            direc = [t.cpu().numpy() for t in h.get_direction()]
+            it = [t.cpu().numpy() for t in h.get_iterate()]
+            h.reset()
+            res = h.solve()
+            xf = h.get_iterate()[0].cpu().numpy()
+        out[path] = (info, direc, it, res, xf)
+    (i1, d1, it1, r1, x1), (i2, d2, it2, r2, x2) = out["one"], out["multi"]
+    for f in ("alpha", "alpha_max", "v_norm", "mu", "cg_iters"):
+        assert getattr(i1, f) == getattr(i2, f), f
+    for a, b in zip(d1 + it1, d2 + it2):
+        assert np.array_equal(a, b)
+    for f in ("status", "iters", "cg_total", "obj_p", "obj_d", "rel_gap", "mu"):
+        assert getattr(r1, f) == getattr(r2, f), f
+    assert np.array_equal(x1, x2)
+    check_solution(lp, r1, 1e-6)
+
+
+def _zero_row_lp():
+    """A planted LP whose A has a zero row: B = A D W then has a zero row for
+    every W, so its Gram matrix has a zero pivot that neither a fresh sketch
+    nor a relative diagonal shift lifts (Lemma 3's failure event, forced)."""
+    lp = dense_planted(24, 600, rng=np.random.default_rng(77))
+    A = lp.A.copy()
+    A[5] = 0.0
+    return A, A @ lp.x_star, A.T @ lp.y_star + lp.s_star
+
+
+def test_rank_loss_resketches_then_shifts_then_erank(torch, sk):
+    """rank(A D W) < m forced from the host: the step draws 3 fresh sketches
+    (new salts), then factors the last one with 3 growing diagonal shifts, and
+    ends with SKIPM_ERANK; lp_solve reports both counts."""
+    A, b, c = _zero_row_lp()
+    say("rank loss: zero row (24 x 600)")
+    with sk.LP(A, b, c, s=2, seed=3) as h:
+        with pytest.raises(sk.SkipmError) as e:
+            h.step()
+        assert e.value.code == sk.SKIPM_ERANK
+        res = h.solve()
+    assert res.status == sk.SKIPM_ERANK
+    assert res.resketches >= 3 and res.shifts >= 3
 
 
 # ---------------------------------------------------------------------------
@@ -439,30 +569,25 @@ def test_solve_f32_values(torch, sk):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_small_and_multi_workgroup_cg_agree(torch, sk, prec):
+def test_small_and_multi_workgroup_cg_solves(torch, sk, prec):
     """The one-workgroup CG and the fused multi-workgroup CG are the same
-    iteration (their fixed-iteration iterates agree to 1e-9 in the test above);
-    full solves both meet the bar.  Their IPM trajectories are not compared
-    step by step: a CG that stops at a tolerance can stop one iteration apart
-    on rounding, and at s = 1 that changes later steps (iteration counts are
-    parity unpinned), so the counts only have to be close."""
+    iteration (their fixed-iteration iterates match Alg. 1 to 1e-9 in the test
+    above).  Whole solves on either path meet the planted optimum and the exact
+    oracle's objective; their iteration counts are not compared (a CG stopped
+    at a tolerance can stop one iteration apart on rounding, and at s = 1 that
+    moves later steps: counts are parity unpinned)."""
     lp = config_lp(0)
     say(f"small vs multi-workgroup CG, config 0, {prec}")
     pr = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
-    out = {}
+    ref = O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap))
+    assert ref.status == "optimal"
     for path in ("small", "multi"):
         with cg_path(path), sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap,
                                   precision=pr) as h:
-            out[path] = h.solve()
-    a, b = out["small"], out["multi"]
-    check_solution(lp, a, lp.eps_gap)
-    check_solution(lp, b, lp.eps_gap)
-    # at s = 1 a rounding-level change moves the count by up to ~20 % (49 to
-    # 59 IPM iterations seen on config 0); far larger differences would point
-    # to a broken path
-    assert abs(a.iters - b.iters) <= max(5, b.iters // 4), (a.iters, b.iters)
-    assert abs(a.cg_total - b.cg_total) <= 0.25 * b.cg_total, (a.cg_total, b.cg_total)
-    assert abs(a.obj_p - b.obj_p) <= 2 * lp.eps_gap * abs(b.obj_p)
+            res = h.solve()
+        check_solution(lp, res, lp.eps_gap)
+        assert abs(res.obj_p - ref.obj_p) <= 2e-8 * abs(ref.obj_p)
+        assert abs(res.obj_d - ref.obj_d) <= 2e-8 * abs(ref.obj_d)
 
 
 def test_solve_mixed_precision_small(torch, sk):
@@ -618,12 +743,24 @@ def test_mixed_pcg_at_full_size_matches_cholesky(torch, sk, cfg1):
     assert np.linalg.norm(dy - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
-def test_solve_config1_full_size(torch, sk):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_config1_full_size(torch, sk, prec):
+    """The bench's headline workload at full size, in both precision modes the
+    bench times (s = 1): planted optimum, KKT residuals, and the precision
+    tier the run ended at."""
     lp = config_lp(1)
-    say("solve config 1 (500 x 100000 FP64, w=2000, s=1)")
-    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap) as h:
+    say(f"solve config 1 (500 x 100000 FP64, w=2000, s=1), {prec}")
+    pr = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, eps_gap=lp.eps_gap, precision=pr) as h:
         res = h.solve()
     check_solution(lp, res, lp.eps_gap)
+    assert res.cg_max <= 500
+    if prec == "fp64":
+        assert res.tier_final == sk.SKIPM_TIER_FP64 and res.demote_iter == -1
+    else:
+        assert res.tier_final in (sk.SKIPM_TIER_FP32, sk.SKIPM_TIER_FP64)
+        assert (res.demote_iter == -1) == (res.tier_final == sk.SKIPM_TIER_FP32)
+        assert res.demote_iter < res.iters
 
 
 # ---------------------------------------------------------------------------
