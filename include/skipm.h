@@ -252,6 +252,27 @@ int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps,
 int normal_matvec_timed(skipm_lp_t lp, const double* u, double* out, int32_t reps,
                         float* ms_per_pass, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of normal_matvec, out = A D^2 A^T u, on the caller's own A and D^2, with no
+ * handle and no allocation of any kind.  The same kernels as normal_matvec
+ * (one fused pass over A, then a fixed-order sum of per-workgroup partials),
+ * so the result is bitwise that of normal_matvec on a handle holding the same
+ * A and D^2.  The partials and a zero-padded copy of u live in a static device
+ * buffer of the library (8 MiB + 16 KiB on each device it runs on, held until
+ * the process ends, its address looked up on the first call on a device).
+ *   A: dense column-major, a_dtype SKIPM_F64 or SKIPM_F32, 16-byte aligned,
+ *      leading dimension lda with m <= lda <= 2048 and lda a multiple of 4;
+ *      rows m..lda-1 are read and must hold finite values (lp_create's own
+ *      layout holds zeros there).
+ *   d2: n FP64 (NULL: D = I); u: m FP64; out: m FP64.  1 <= m <= 2048, n >= 1.
+ * SKIPM_EINVAL outside these limits (checked before any device work).  Every
+ * call on a device shares that device's buffer: calls that overlap on one
+ * device (different streams or threads without ordering) race; calls ordered
+ * on one stream do not.  Nothing is synchronised. */
+int normal_matvec_noalloc(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                          const double* d2, const double* u, double* out, hipStream_t stream);
+
 /* Sampled timing of the CG's normal-equation product A D^2 A^T d inside
  * ipm_step / lp_solve / pcg_solve (the solver's dominant kernel: the fused
  * column pass for dense A, the column + row passes for CSR).  every > 0: a HIP

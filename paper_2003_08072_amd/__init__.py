@@ -112,6 +112,8 @@ SIGNATURES = {
                             C.POINTER(PcgInfo), _VP]),
     "normal_matvec": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP]),
     "normal_matvec_timed": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.POINTER(C.c_float), _VP]),
+    "normal_matvec_noalloc": (C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _VP, _VP,
+                                        _VP, _VP]),
     "ipm_step": (C.c_int, [_VP, C.POINTER(StepInfo), _VP]),
     "lp_solve": (C.c_int, [_VP, C.POINTER(Result), _VP]),
     "lp_footprint": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_int64)]),

@@ -248,3 +248,19 @@ int main() {
     assert lines["stag"] == ["1k0", "2k1", "best=9e-10"]
     # never finite: nothing kept; rounds 1, 2 built, then stop with t = 0
     assert lines["inf"] == ["2-1", "2-2", "0-2", "best=1"]
+
+
+def test_noalloc_product_validates_before_any_device_call():
+    """normal_matvec_noalloc rejects shapes its static scratch buffer cannot
+    hold, and bad layouts, with SKIPM_EINVAL before touching a device."""
+    lib = sk.load()
+    a = 16  # a 16-byte aligned stand-in address: never dereferenced here
+    bad = [(2049, 10, 2052, sk.SKIPM_F64), (8, 10, 6, sk.SKIPM_F64), (8, 10, 4096, sk.SKIPM_F64),
+           (0, 10, 4, sk.SKIPM_F64), (8, 0, 8, sk.SKIPM_F64), (8, 10, 8, 7)]
+    for m, n, lda, dt in bad:
+        assert lib.normal_matvec_noalloc(a, dt, m, n, lda, None, a, a, None) == \
+            sk.SKIPM_EINVAL, (m, n, lda, dt)
+    assert lib.normal_matvec_noalloc(8, sk.SKIPM_F64, 8, 10, 8, None, a, a, None) == \
+        sk.SKIPM_EINVAL   # A not 16-byte aligned
+    assert lib.normal_matvec_noalloc(None, sk.SKIPM_F64, 8, 10, 8, None, a, a, None) == \
+        sk.SKIPM_EINVAL
