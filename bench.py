@@ -59,7 +59,10 @@ def parse():
                     help="config 4 --find-rate: bisection steps")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0,
                     help="config 4: device memory the server may admit against")
-    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--precision", default="all", choices=["fp64", "mixed", "bf16", "both", "all"],
+                    help="precision modes of the CG products: fp64; mixed (FP32 copy of A, "
+                         "escalating to FP64); bf16 (BF16 copy, escalating BF16 -> FP32 -> "
+                         "FP64); both = fp64 and mixed; all = the three")
     ap.add_argument("--s", type=int, default=1,
                     help="non-zeros per row of the sketch for the headline (1: CountSketch)")
     ap.add_argument("--s-extra", default="2",
@@ -75,6 +78,8 @@ def parse():
                     help="count: block CountSketch (Sec. 2); gaussian: dense W_G (Sec. 5)")
     ap.add_argument("--resketch", type=int, default=1, choices=[0, 1],
                     help="1: fresh W every IPM iteration; 0: one W for the whole solve")
+    ap.add_argument("--max-cg", type=int, default=1000,
+                    help="CG iteration cap per normal-equation solve (CG inner solver)")
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=25.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
@@ -100,7 +105,8 @@ def run_probe(args):
     import paper_2003_08072_amd as sk
     from lpgen import config_lp
     lp = config_lp(args.config)
-    prec = sk.SKIPM_PREC_MIXED if args.precision == "mixed" else sk.SKIPM_PREC_FP64
+    prec = {"mixed": sk.SKIPM_PREC_MIXED, "bf16": sk.SKIPM_PREC_BF16}.get(args.precision,
+                                                                        sk.SKIPM_PREC_FP64)
     with sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=args.s,
                eps_gap=lp.eps_gap, precision=prec) as h:
         h.step()
@@ -112,15 +118,22 @@ def run_probe(args):
                       "launches": args.matvec_reps}), flush=True)
 
 
-def matvec_bytes(lp, precision):
+# bytes per value of A that the CG products read at each precision tier
+TIER_BYTES = {0: 8, 1: 4, 2: 2}
+TIER_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
+PREC_START_TIER = {"fp64": 0, "mixed": 1, "bf16": 2}
+
+
+def matvec_bytes(lp, precision, tier=None):
     """Algorithmic HBM bytes of one normal product A D^2 A^T u.
 
-    Dense: A once (m n values in the precision the CG reads), D^2 once (n FP64
-    values), u in and the product out (m FP64 each).  CSR: the column pass reads the CSC copy (row indices,
-    values, column pointers) and D^2 and writes one coefficient per column; the
-    row pass reads the CSR copy (column indices, values, row pointers) and the
-    coefficients once."""
-    pa = 4 if (precision == "mixed" or lp.a_dtype == "f32") else 8
+    Dense: A once (m n values in the precision the CG reads: the tier's copy),
+    D^2 once (n FP64 values), u in and the product out (m FP64 each).  CSR:
+    the column pass reads the CSC copy (row indices, values, column pointers)
+    and D^2 and writes one coefficient per column; the row pass reads the CSR
+    copy (column indices, values, row pointers) and the coefficients once."""
+    tier = PREC_START_TIER[precision] if tier is None else tier
+    pa = min(TIER_BYTES[tier], 4 if lp.a_dtype == "f32" else 8)
     if lp.fmt == "dense":
         return lp.m * lp.n * pa + lp.n * 8 + 2 * lp.m * 8
     nnz = int(lp.A.nnz)
@@ -138,12 +151,13 @@ def percentile(xs, q):
 
 def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
     sketch = sketch or args.sketch or "count"
-    prec = sk.SKIPM_PREC_MIXED if precision == "mixed" else sk.SKIPM_PREC_FP64
+    prec = {"fp64": sk.SKIPM_PREC_FP64, "mixed": sk.SKIPM_PREC_MIXED,
+            "bf16": sk.SKIPM_PREC_BF16}[precision]
     inner = {"cg": sk.SKIPM_INNER_CG, "sd": sk.SKIPM_INNER_SD,
              "richardson": sk.SKIPM_INNER_RICHARDSON}[args.inner]
     h = sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed, s=s_nnz,
               eps_gap=lp.eps_gap, precision=prec, max_outer=1000, inner=inner,
-              resketch=args.resketch, max_cg=5000 if args.inner != "cg" else 500,
+              resketch=args.resketch, max_cg=5000 if args.inner != "cg" else args.max_cg,
               sketch=sk.SKIPM_SKETCH_GAUSSIAN if sketch == "gaussian" else sk.SKIPM_SKETCH_COUNT)
     stream = torch.cuda.current_stream()
     res = None
@@ -171,9 +185,28 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         cg.append(res.cg_total)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kt_ms, kt_n = h.kernel_time()
+    start_tier = PREC_START_TIER[precision] if lp.fmt == "dense" else 0
+    # the sampled products of the start tier (one byte count per mean); a run
+    # that moved up a tier has samples at the other tiers too, reported apart
+    kt_ms, kt_n = h.kernel_time_tier(start_tier)
+    per_tier = {}
+    for t in (0, 1, 2):
+        ms_t, n_t = h.kernel_time_tier(t)
+        if n_t:
+            b_t = matvec_bytes(lp, precision, t)
+            per_tier[TIER_NAMES[t]] = dict(ms=ms_t, samples=n_t, bytes=b_t,
+                                           gbs=b_t / (ms_t * 1e-3) / 1e9)
     ks_ms, ks_n = h.sketch_time()
     h.kernel_timing(0)
+    # one more solve, stepped, for the precision tier of every IPM iteration
+    trace = []
+    if precision != "fp64":
+        h.reset()
+        for _ in range(1000):
+            info = h.step()
+            if info.converged:
+                break
+            trace.append((int(info.tier), int(info.refine_steps), int(info.cg_iters)))
     opt = getattr(lp, "opt", None)
     ok = (res.status == 0 and res.rel_gap <= lp.eps_gap
           and (opt is None or abs(res.obj_p - opt) <= 2 * lp.eps_gap * max(1.0, abs(opt))))
@@ -205,6 +238,10 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         rel_gap=res.rel_gap,
         obj_rel_err=None if opt is None else abs(res.obj_p - opt) / max(1.0, abs(opt)),
         rp_rel=res.rp_norm / float(sum(v * v for v in lp.b) ** 0.5),
+        demote_iter=res.demote_iter, tier_final=TIER_NAMES[res.tier_final],
+        tier_trace="".join(str(t) for t, _, _ in trace) if trace else None,
+        refine_steps=[r for _, r, _ in trace] if trace else None,
+        matvec_per_tier=per_tier,
         matvec_ms=kt_ms, matvec_samples=kt_n, matvec_bytes=mv_bytes,
         sketch_ms=ks_ms, sketch_samples=ks_n,
         matvec_gbs=mv_bytes / (kt_ms * 1e-3) / 1e9 if kt_n else None,
@@ -575,7 +612,8 @@ def main():
         print(json.dumps(run_serving(sk, torch, args)), flush=True)
         return
     lp = config_lp(args.config)
-    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    precs = {"both": ["fp64", "mixed"], "all": ["fp64", "mixed", "bf16"]}.get(
+        args.precision, [args.precision])
     if lp.fmt != "dense":
         precs = ["fp64"]  # the sparse path keeps its values in their own precision
     s_list = [args.s] + [int(v) for v in args.s_extra.split(",") if v and int(v) != args.s]
@@ -586,14 +624,17 @@ def main():
             results[f"{pr}_s{s_nnz}"] = run_mode(sk, torch, lp, pr, s_nnz, args)
     # headline: the literal sketch (s = args.s), the faster of the FP64 and the
     # mixed-precision mode among those that meet the accuracy target
-    cands = [results[k] for k in (f"fp64_s{args.s}", f"mixed_s{args.s}") if k in results]
+    cands = [results[k] for k in (f"fp64_s{args.s}", f"mixed_s{args.s}", f"bf16_s{args.s}")
+             if k in results]
     ok = [r for r in cands if r["ok"]] or cands
     head = max(ok, key=lambda r: r["solves_per_s"])
     speedup = {}
     for s_nnz in s_list:
-        a, b = results.get(f"mixed_s{s_nnz}"), results.get(f"fp64_s{s_nnz}")
-        if a and b and a["ok"] and b["ok"]:
-            speedup[f"s{s_nnz}"] = a["solves_per_s"] / b["solves_per_s"]
+        b = results.get(f"fp64_s{s_nnz}")
+        for low in ("mixed", "bf16"):
+            a = results.get(f"{low}_s{s_nnz}")
+            if a and b and a["ok"] and b["ok"]:
+                speedup[f"{low}_s{s_nnz}"] = a["solves_per_s"] / b["solves_per_s"]
     print("[bench] cpu baseline", file=sys.stderr, flush=True)
     cpu = cpu_baseline(lp, args.cpu_budget) if args.cpu_budget > 0 else None
     cpu1 = None
@@ -625,7 +666,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head["precision"] == "fp64" else "f64 (CG products f32)",
+        "dtype": {"fp64": "f64", "mixed": "f64 (CG products f32)",
+                  "bf16": "f64 (CG products bf16, escalating to f32, f64)"}[head["precision"]],
         "data": "synthetic planted LP (seeded), resident in HBM",
         "config": {"workload": f"config {args.config}: {lp.fmt} {lp.m} x {lp.n} "
                                f"{'FP64' if lp.a_dtype == 'f64' else 'FP32'} planted LP, "
@@ -637,7 +679,7 @@ def main():
         "p99_ms": head["p99_ms"],
         "matvec_gbs": mv["matvec_gbs"],
         "modes": results,
-        "mixed_over_fp64": speedup,
+        "low_precision_over_fp64": speedup,
         "roofline": {"bound": "hbm", "achieved": mv["matvec_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": mv["matvec_gbs"] / HBM_PEAK_GBS,
                      "traffic": MEASURED_TRAFFIC.get((args.config, head["precision"])),

@@ -24,9 +24,10 @@
  *    stream before returning.
  *  - A handle is not thread-safe; distinct handles are independent.
  *  - All floating-point state of the IPM (x, y, s, residuals, p, v, the step)
- *    is FP64.  SKIPM_PREC_MIXED only lets the CG matrix-vector products read an
- *    FP32 copy of A; the normal-equation residual that decides convergence is
- *    recomputed from the FP64 A.
+ *    is FP64.  SKIPM_PREC_MIXED / SKIPM_PREC_BF16 only let the CG
+ *    matrix-vector products read an FP32 / BF16 copy of A (FP64 accumulation);
+ *    the normal-equation residual that decides convergence is recomputed from
+ *    the FP64 A.
  */
 #ifndef SKIPM_H
 #define SKIPM_H
@@ -111,7 +112,7 @@ typedef struct {
   int32_t w;         /* sketch width, m <= w  [0 = 4m]                                 */
   int32_t s;         /* non-zeros per row of W, s divides w  [1]                       */
   int32_t max_cg;    /* CG iteration cap per normal-equation solve, counted over all the
-                        inner CG runs of the refinement in SKIPM_PREC_MIXED / _BF16  [500] */
+                        inner CG runs of the refinement in SKIPM_PREC_MIXED / _BF16  [1000] */
   int32_t max_outer; /* IPM iteration cap  [300]                                       */
   int32_t resketch;  /* 1: fresh W every IPM iteration (salt = iteration), 0: one W  [1] */
   int32_t precision; /* SKIPM_PREC_FP64, SKIPM_PREC_MIXED or SKIPM_PREC_BF16  [FP64]   */
@@ -240,9 +241,10 @@ int pcg_solve(skipm_lp_t lp, const double* d2, const double* p, int64_t k, doubl
 
 /* out = A D^2 A^T u with the handle's current D^2 (as left by the last prologue
  * of ipm_step / lp_solve or by pcg_solve): the operator of eq. "normal" applied
- * by the same fused one-pass kernel CG uses (FP32 copy of A in
- * SKIPM_PREC_MIXED).  The pass is launched `reps` >= 1 times (to time it);
- * u: m, out: m (device). */
+ * by the same fused one-pass kernel CG uses, reading the copy of A of the
+ * handle's current precision tier (FP32 or BF16 values, FP64 accumulation, in
+ * SKIPM_PREC_MIXED / _BF16 until the run escalates).  The pass is launched
+ * `reps` >= 1 times (to time it); u: m, out: m (device). */
 int normal_matvec(skipm_lp_t lp, const double* u, double* out, int32_t reps,
                   hipStream_t stream);
 
@@ -284,6 +286,10 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every);
 
 /* Mean duration (ms, host) of the sampled products and their number. */
 int lp_kernel_time(skipm_lp_t lp, double* avg_ms, int64_t* samples);
+
+/* As lp_kernel_time, over the sampled products that read the copy of A of one
+ * precision tier (SKIPM_TIER_*), so that each mean has one byte count. */
+int lp_kernel_time_tier(skipm_lp_t lp, int32_t tier, double* avg_ms, int64_t* samples);
 
 /* While lp_kernel_timing is on (every > 0), a second HIP event pair brackets
  * the sketch product B = A D W of each IPM iteration (Alg. 2 step (a)): for

@@ -121,6 +121,8 @@ SIGNATURES = {
     "lp_kernel_timing": (C.c_int, [_VP, C.c_int32]),
     "lp_kernel_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lp_sketch_time": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "lp_kernel_time_tier": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]),
     "lp_solve_batch": (C.c_int, [C.POINTER(_VP), C.c_int32, C.POINTER(Result), C.c_int32]),
     "srv_create": (C.c_int, [C.POINTER(_VP), C.c_int64, C.c_int32]),
     "srv_submit": (C.c_int, [_VP, C.POINTER(Problem), C.POINTER(Params), _VP, _VP,
@@ -420,6 +422,13 @@ class LP:
         """(mean ms of the sampled products, number of samples)."""
         ms, n = C.c_double(), C.c_int64()
         _check(self._lib.lp_kernel_time(self.handle, C.byref(ms), C.byref(n)), "lp_kernel_time")
+        return float(ms.value), int(n.value)
+
+    def kernel_time_tier(self, tier):
+        """(mean ms, samples) of the sampled products at one precision tier."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.lp_kernel_time_tier(self.handle, int(tier), C.byref(ms), C.byref(n)),
+               "lp_kernel_time_tier")
         return float(ms.value), int(n.value)
 
     def sketch_time(self):

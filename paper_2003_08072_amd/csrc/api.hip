@@ -48,6 +48,8 @@ struct skipm_lp_s {
   // device buffers
   void* A = nullptr;
   float* A32 = nullptr;
+  uint16_t* A16 = nullptr;  // bfloat16 copy of A (precision SKIPM_PREC_BF16)
+  int64_t lda16 = 0;        // its leading dimension: m rounded up to 8 (16-byte columns)
   double *b = nullptr, *c = nullptr, *x = nullptr, *y = nullptr, *sv = nullptr;
   double *d2 = nullptr, *rd = nullptr, *dx = nullptr, *ds = nullptr, *v = nullptr;
   double *rp = nullptr, *p = nullptr, *dy = nullptr, *g = nullptr;
@@ -88,7 +90,7 @@ struct skipm_lp_s {
   double* sc = nullptr;
   int32_t* is = nullptr;
   double* hsc = nullptr;  // pinned: S_NSLOTS doubles then I_NINTS ints
-  int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_B = 1, nblk_vec = 1;
+  int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_A16 = 1, nblk_B = 1, nblk_vec = 1;
   int64_t k = 0;
   int64_t hashed_k = -1;
   int prev_cg = 8;
@@ -114,8 +116,11 @@ struct skipm_lp_s {
   int kt_every = 0;
   std::vector<hipEvent_t> kt_ev;  // 2 * kKtPairs events
   std::vector<int> kt_iter;       // CG iteration of each pending pair
+  std::vector<int> kt_tier;       // precision tier of the product it brackets
   double kt_sum_ms = 0;
   int64_t kt_count = 0;
+  double kt_tier_ms[3] = {0, 0, 0};  // the same, per SKIPM_TIER_*
+  int64_t kt_tier_n[3] = {0, 0, 0};
   // event pair around the sketch product of every IPM iteration while timing is on
   hipEvent_t ks_ev[2] = {nullptr, nullptr};
   bool ks_pending = false;
@@ -150,7 +155,8 @@ int validate_params(const skipm_params& p, int64_t m, int64_t n) {
   if (p.s < 1 || p.s > 16) return set_error("s must lie in [1, 16]"), SKIPM_EINVAL;
   if (w % p.s != 0) return set_error("s must divide w"), SKIPM_EINVAL;
   if (p.max_cg < 1 || p.max_outer < 0) return set_error("bad iteration caps"), SKIPM_EINVAL;
-  if (p.precision != SKIPM_PREC_FP64 && p.precision != SKIPM_PREC_MIXED)
+  if (p.precision != SKIPM_PREC_FP64 && p.precision != SKIPM_PREC_MIXED &&
+      p.precision != SKIPM_PREC_BF16)
     return set_error("unknown precision"), SKIPM_EINVAL;
   if (p.inner != SKIPM_INNER_CG && p.inner != SKIPM_INNER_SD && p.inner != SKIPM_INNER_RICHARDSON)
     return set_error("unknown inner solver"), SKIPM_EINVAL;
@@ -194,7 +200,27 @@ int run_colpass(ColPass& cp, hipStream_t st) {
 }
 
 int stream_A(const skipm_lp_s* lp, int ta) {
-  return lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4) > kStreamBytes ? 1 : 0;
+  const int64_t bytes = ta == SKIPM_F64 ? lp->lda * lp->n * 8
+                        : ta == SKIPM_F32 ? lp->lda * lp->n * 4
+                                          : lp->lda16 * lp->n * 2;
+  return bytes > kStreamBytes ? 1 : 0;
+}
+
+// The CG products read the copy of A of the current precision tier: FP32 or
+// BF16 values, widened and accumulated in FP64.
+void use_tier_copy(skipm_lp_s* lp, ColPass& cp) {
+  if (lp->tier == SKIPM_TIER_FP32) {
+    cp.A = lp->A32;
+    cp.ta = SKIPM_F32;
+    cp.nt = stream_A(lp, SKIPM_F32);
+    cp.nblk = lp->nblk_A32;
+  } else if (lp->tier == SKIPM_TIER_BF16) {
+    cp.A = lp->A16;
+    cp.ta = kTypeBF16;
+    cp.lda = lp->lda16;
+    cp.nt = stream_A(lp, kTypeBF16);
+    cp.nblk = lp->nblk_A16;
+  }
 }
 
 ColPass colpass_A(skipm_lp_s* lp, int mode) {
@@ -322,6 +348,7 @@ int kt_take(skipm_lp_s* lp, int iter) {
   const int q = (int)lp->kt_iter.size();
   if (q >= kKtPairs) return -1;
   lp->kt_iter.push_back(iter);
+  lp->kt_tier.push_back(lp->fmt == SKIPM_CSR ? SKIPM_TIER_FP64 : lp->tier);
   return q;
 }
 
@@ -330,6 +357,7 @@ int kt_begin(skipm_lp_s* lp, int iter, hipStream_t st) {
   const int q = kt_take(lp, iter);
   if (q >= 0 && hipEventRecord(lp->kt_ev[2 * q], st) != hipSuccess) {
     lp->kt_iter.pop_back();
+    lp->kt_tier.pop_back();
     return -1;
   }
   return q;
@@ -349,9 +377,12 @@ void kt_harvest(skipm_lp_s* lp, int executed) {
     if (hipEventElapsedTime(&ms, lp->kt_ev[2 * q], lp->kt_ev[2 * q + 1]) == hipSuccess) {
       lp->kt_sum_ms += ms;
       ++lp->kt_count;
+      lp->kt_tier_ms[lp->kt_tier[q]] += ms;
+      ++lp->kt_tier_n[lp->kt_tier[q]];
     }
   }
   lp->kt_iter.clear();
+  lp->kt_tier.clear();
 }
 
 int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, const double* pdq,
@@ -395,12 +426,7 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;
-  if (lp->tier == SKIPM_TIER_FP32) {  // FP32 copy of A, FP64 accumulation
-    cp.A = lp->A32;
-    cp.ta = SKIPM_F32;
-    cp.nt = stream_A(lp, SKIPM_F32);
-    cp.nblk = lp->nblk_A32;
-  }
+  use_tier_copy(lp, cp);
   cp.done = done;
   const int q = kt_take(lp, iter);
   if (q >= 0) {  // dense product: the runtime stamps the events with the kernel itself
@@ -467,7 +493,7 @@ int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, cons
 // Returns 1 if it ran, 0 if this LP takes the multi-workgroup path.
 int pcg_small(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
               int* its, int* fact_fail, hipStream_t st) {
-  if (lp->fmt != SKIPM_DENSE || lp->small_cg_bytes <= 0) return 0;
+  if (lp->fmt != SKIPM_DENSE || lp->small_cg_bytes <= 0 || lp->tier == SKIPM_TIER_BF16) return 0;
   const bool f32 = lp->tier == SKIPM_TIER_FP32;
   const int ta = f32 ? SKIPM_F32 : lp->a_dtype;
   const int64_t bytes = lp->lda * lp->n * (ta == SKIPM_F64 ? 8 : 4);
@@ -1122,7 +1148,7 @@ int skipm_params_default(skipm_params* out) {
   out->guard = 1e-3;
   out->w = 0;
   out->s = 1;
-  out->max_cg = 500;
+  out->max_cg = 1000;
   out->max_outer = 300;
   out->resketch = 1;
   out->precision = SKIPM_PREC_FP64;
@@ -1150,7 +1176,8 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   int nblk_csc = 0;
   if (!csr) {
     add(esz * lda * n);
-    if (prm->precision == SKIPM_PREC_MIXED && f64) add(4 * lda * n);
+    if (prm->precision != SKIPM_PREC_FP64 && f64) add(4 * lda * n);
+    if (prm->precision == SKIPM_PREC_BF16) add(2 * round_up(m, 8) * n);
   } else {
     const int64_t nnz = prob->nnz;
     const int64_t nseg = m + nnz / kSeg + 1;
@@ -1200,11 +1227,13 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   const int nblk_A = colpass_nblk(lda, n, ta, SKIPM_F64, COL_NORMAL);
   const int nblk_Ap = colpass_nblk(lda, n, ta, SKIPM_F64, COL_PROLOGUE);
   const int nblk_A32 = colpass_nblk(lda, n, SKIPM_F32, SKIPM_F64, COL_NORMAL);
+  const int nblk_A16 = colpass_nblk(round_up(m, 8), n, kTypeBF16, SKIPM_F64, COL_NORMAL);
   const int nblk_B = colpass_nblk(lda, w, SKIPM_F64, SKIPM_F64, COL_NORMAL);
   const int nblk_vec = vec_nblk(n);
   int64_t pe = std::max<int64_t>(2 * (int64_t)nblk_Ap * mp, (int64_t)nblk_A * mp);
   pe = std::max<int64_t>(pe, (int64_t)nblk_B * mp);
   pe = std::max<int64_t>(pe, (int64_t)nblk_A32 * mp);
+  pe = std::max<int64_t>(pe, (int64_t)nblk_A16 * mp);
   pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
   add(8 * pe);
   add(8 * 8 * (int64_t)std::max(std::max(std::max(nblk_Ap, nblk_vec), nblk_csc), 64));
@@ -1239,8 +1268,13 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every) {
   }
   lp->kt_every = every;
   lp->kt_iter.clear();
+  lp->kt_tier.clear();
   lp->kt_sum_ms = 0;
   lp->kt_count = 0;
+  for (int t = 0; t < 3; ++t) {
+    lp->kt_tier_ms[t] = 0;
+    lp->kt_tier_n[t] = 0;
+  }
   lp->ks_pending = false;
   lp->ks_sum_ms = 0;
   lp->ks_count = 0;
@@ -1259,6 +1293,14 @@ int lp_kernel_time(skipm_lp_t lp, double* avg_ms, int64_t* samples) {
   if (!lp || !avg_ms || !samples) return set_error("null argument"), SKIPM_EINVAL;
   *samples = lp->kt_count;
   *avg_ms = lp->kt_count ? lp->kt_sum_ms / (double)lp->kt_count : 0.0;
+  return SKIPM_OK;
+}
+
+int lp_kernel_time_tier(skipm_lp_t lp, int32_t tier, double* avg_ms, int64_t* samples) {
+  if (!lp || !avg_ms || !samples) return set_error("null argument"), SKIPM_EINVAL;
+  if (tier < SKIPM_TIER_FP64 || tier > SKIPM_TIER_BF16) return set_error("unknown tier"), SKIPM_EINVAL;
+  *samples = lp->kt_tier_n[tier];
+  *avg_ms = *samples ? lp->kt_tier_ms[tier] / (double)*samples : 0.0;
   return SKIPM_OK;
 }
 
@@ -1341,8 +1383,10 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   lp->s = prm->s;
   // a CSR problem's values are read as stored (FP32 or FP64) with FP64
   // accumulation in every pass, so it has no separate mixed mode
-  lp->mixed = prm->precision == SKIPM_PREC_MIXED && !csr;
-  lp->start_tier = lp->mixed ? SKIPM_TIER_FP32 : SKIPM_TIER_FP64;
+  lp->mixed = prm->precision != SKIPM_PREC_FP64 && !csr;
+  const bool bf16 = prm->precision == SKIPM_PREC_BF16 && !csr;
+  lp->start_tier = bf16 ? SKIPM_TIER_BF16 : (lp->mixed ? SKIPM_TIER_FP32 : SKIPM_TIER_FP64);
+  lp->lda16 = round_up(m, 8);
   lp->tier = lp->start_tier;
   lp->lda = round_up(m, 4);
   lp->mp = round_up(m, 64);
@@ -1434,7 +1478,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     ALLOC(lp->segsum, 2 * (int64_t)hnseg);
     lp->nblk_csc = csc_dot_nblk(n);
   }
-  if (lp->mixed) ALLOC(lp->A32, lda * n);
+  if (lp->mixed && lp->a_dtype == SKIPM_F64) ALLOC(lp->A32, lda * n);
+  if (bf16) ALLOC(lp->A16, lp->lda16 * n);
   ALLOC(lp->b, mp);
   ALLOC(lp->c, n);
   ALLOC(lp->x, n);
@@ -1499,12 +1544,14 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   lp->nblk_A = colpass_nblk(lda, n, lp->a_dtype, SKIPM_F64, COL_NORMAL);
   lp->nblk_Ap = colpass_nblk(lda, n, lp->a_dtype, SKIPM_F64, COL_PROLOGUE);
   lp->nblk_A32 = colpass_nblk(lda, n, SKIPM_F32, SKIPM_F64, COL_NORMAL);
+  lp->nblk_A16 = colpass_nblk(lp->lda16, n, kTypeBF16, SKIPM_F64, COL_NORMAL);
   lp->nblk_B = colpass_nblk(lda, w, SKIPM_F64, SKIPM_F64, COL_NORMAL);
   lp->nblk_vec = vec_nblk(n);
   {
     int64_t pe = std::max<int64_t>(2 * (int64_t)lp->nblk_Ap * mp, (int64_t)lp->nblk_A * mp);
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_B * mp);
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A32 * mp);
+    pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A16 * mp);
     pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
     ALLOC(lp->part, pe);
   }
@@ -1540,6 +1587,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     launch_pad_copy_f32((float*)lp->A, lda, (const float*)prob->a_vals, lda_in, m, n, st);
     if (lp->mixed) lp->A32 = (float*)lp->A;
   }
+  if (bf16)
+    launch_pad_copy_to_bf16(lp->A16, lp->lda16, prob->a_vals, lp->a_dtype, lda_in, m, n, st);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
     lp_destroy(lp);
     return set_error("device error while copying the problem"), SKIPM_EDEVICE;
@@ -1693,12 +1742,7 @@ static int normal_matvec_impl(skipm_lp_t lp, const double* u, double* out, int32
   ColPass cp = colpass_A(lp, COL_NORMAL);
   cp.u = lp->cd;
   cp.d2 = lp->d2;
-  if (lp->tier == SKIPM_TIER_FP32) {
-    cp.A = lp->A32;
-    cp.ta = SKIPM_F32;
-    cp.nt = stream_A(lp, SKIPM_F32);
-    cp.nblk = lp->nblk_A32;
-  }
+  use_tier_copy(lp, cp);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
     SK_CHECK_HIP(hipEventCreateWithFlags(&e0, kTimingEvent));

@@ -45,6 +45,23 @@ struct Vec<float> {
   static constexpr int V = 4;
   typedef fvec4 type;
 };
+// bfloat16 values as raw 16-bit patterns (the upper half of an FP32 word)
+struct bf16_t {
+  unsigned short bits;
+};
+typedef unsigned short hvec8 __attribute__((ext_vector_type(8)));
+template <>
+struct Vec<bf16_t> {
+  static constexpr int V = 8;
+  typedef hvec8 type;
+};
+
+// one element of a loaded vector, widened exactly to FP64
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return (double)v; }
+__device__ __forceinline__ double widen(unsigned short b) {
+  return (double)__uint_as_float((unsigned)b << 16);
+}
 
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
@@ -118,17 +135,21 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   // nothing, so their latency overlaps the set-up below.  Two columns per trip
   // later, the next two prefetched while these are used (up to four columns
   // per lane group in flight).
-  VT c0v[R], c1v[R], n0v[R], n1v[R];
+  // PD columns per trip (2 * PD per lane group in flight).  Four per trip for
+  // BF16 columns (one 16-byte load per lane each) measured no faster than two.
+  constexpr int PD = 2;
+  VT cv[PD][R], nv[PD][R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    c0v[r] = (VT)0;
-    c1v[r] = (VT)0;
-    n0v[r] = (VT)0;
-    n1v[r] = (VT)0;
-  }
+  for (int q = 0; q < PD; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cv[q][r] = (VT)0;
+      nv[q][r] = (VT)0;
+    }
   int64_t col = c0 + slot;
-  if (col < c1) load_col(c0v, col);
-  if (col + NSLOT < c1) load_col(c1v, col + NSLOT);
+#pragma unroll
+  for (int q = 0; q < PD; ++q)
+    if (col + q * NSLOT < c1) load_col(cv[q], col + q * NSLOT);
 
   const bool cg = a.cg.on != 0;
   const bool cg_dir = cg && MODE == COL_NORMAL && a.cg.k > 0;
@@ -298,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
         for (int r = 0; r < R; ++r) {
           if (!valid[r]) continue;
 #pragma unroll
-          for (int e = 0; e < V; ++e) dot += (TC)cur[r][e] * uu[r][e];
+          for (int e = 0; e < V; ++e) dot += (TC)widen(cur[r][e]) * uu[r][e];
         }
         dot = group_sum<G>(dot);
       }
@@ -307,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)widen(cur[r][e]);
       } else if (MODE == COL_DOT) {
         if (cg) {
           if (lg == 0) {  // w_j = (Q^{-1} q)_j: update x, r, z at j
@@ -330,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)cur[r][e];
+          for (int e = 0; e < V; ++e) acc1[r][e] += coef * (TC)widen(cur[r][e]);
       } else if (MODE == COL_EPILOGUE) {
         const double t = (double)dot;
         const double dsj = -a.rd[col] - t;
@@ -339,7 +360,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int e = 0; e < V; ++e) acc1[r][e] += (TC)(coef * (double)cur[r][e]);
+          for (int e = 0; e < V; ++e) acc1[r][e] += (TC)(coef * widen(cur[r][e]));
       } else {  // COL_PROLOGUE
         const double t = (double)dot;
         const double xj = a.x[col], sj = a.s[col], cj = a.c[col];
@@ -358,22 +379,24 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
         for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            acc1[r][e] += (TC)(xj * (double)cur[r][e]);
-            acc2[r][e] += (TC)(ej * (double)cur[r][e]);
+            acc1[r][e] += (TC)(xj * widen(cur[r][e]));
+            acc2[r][e] += (TC)(ej * widen(cur[r][e]));
           }
       }
   };
   while (col < c1) {
-    if (col + 2 * NSLOT < c1) load_col(n0v, col + 2 * NSLOT);
-    if (col + 3 * NSLOT < c1) load_col(n1v, col + 3 * NSLOT);
-    process(c0v, col);
-    if (col + NSLOT < c1) process(c1v, col + NSLOT);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      c0v[r] = n0v[r];
-      c1v[r] = n1v[r];
-    }
-    col += 2 * NSLOT;
+    for (int q = 0; q < PD; ++q)
+      if (col + (PD + q) * NSLOT < c1) load_col(nv[q], col + (PD + q) * NSLOT);
+    process(cv[0], col);
+#pragma unroll
+    for (int q = 1; q < PD; ++q)
+      if (col + q * NSLOT < c1) process(cv[q], col + q * NSLOT);
+#pragma unroll
+    for (int q = 0; q < PD; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) cv[q][r] = nv[q][r];
+    col += PD * NSLOT;
   }
 
   if (MODE == COL_PROLOGUE) {
@@ -545,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_sketch(const TA* __restrict__ A, int64_t
         for (int r = 0; r < R; ++r)
           if (valid[r])
 #pragma unroll
-            for (int e = 0; e < V; ++e) acc[r][e] += coef * (double)cur[r][e];
+            for (int e = 0; e < V; ++e) acc[r][e] += coef * widen(cur[r][e]);
 #pragma unroll
         for (int r = 0; r < R; ++r) cur[r] = nxt[r];
       }
@@ -670,14 +693,16 @@ Shape pick_shape(int64_t lda, int V) {
 // Block size from an estimate of the VGPRs a lane needs (u and accumulators in
 // the compute type, four 16-byte column buffers, ~32 for addressing, ~32 more
 // for the prologue's per-column terms, 8 more when FP32 columns are widened to
-// FP64): 1024 threads need <= 128 VGPRs, 512 threads <= 256.  The estimate
+// FP64, 24 per row vector when BF16 columns are: eight FP64 values from one
+// 16-byte load): 1024 threads need <= 128 VGPRs, 512 threads <= 256.  The estimate
 // puts every instantiation that the compiler would have to spill to scratch
 // at the smaller block.  DOT passes write no partial sums, so they use small
 // blocks and many of them.
 constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
   const int nacc = mode == COL_PROLOGUE ? 2 : (mode == COL_DOT ? 0 : 1);
   const int est = (1 + nacc) * R * V * tc_bytes / 4 + 16 * R + 32 +
-                  (mode == COL_PROLOGUE ? 32 : 0) + (V == 4 && tc_bytes == 8 ? 8 : 0);
+                  (mode == COL_PROLOGUE ? 32 : 0) + (V == 4 && tc_bytes == 8 ? 8 : 0) +
+                  (V == 8 ? 24 * R : 0);
   if (mode == COL_DOT) return 256;
   return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
@@ -755,8 +780,10 @@ void sketch_dispatch(const TA* A, int64_t lda, int s, const double* d2, int is_d
 
 }  // namespace
 
+int vec_width(int ta) { return ta == SKIPM_F64 ? 2 : (ta == SKIPM_F32 ? 4 : 8); }
+
 int colpass_nblk_dot(int64_t lda, int64_t n, int ta) {
-  const int V = ta == SKIPM_F64 ? 2 : 4;
+  const int V = vec_width(ta);
   const Shape sh = pick_shape(lda, V);
   if (sh.G == 0) return 1;
   const int64_t slots = (256 / 64) * (64 / sh.G);
@@ -767,7 +794,7 @@ int colpass_nblk_dot(int64_t lda, int64_t n, int ta) {
 }
 
 int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode) {
-  const int V = ta == SKIPM_F64 ? 2 : 4;
+  const int V = vec_width(ta);
   const Shape sh = pick_shape(lda, V);
   if (sh.G == 0) return 1;
   const int nt = threads_for(mode, sh.R, V, tc == SKIPM_F64 ? 8 : 4);
@@ -827,6 +854,9 @@ int launch_colpass(ColPass& c, hipStream_t st) {
       case COL_EPILOGUE: rc = dispatch<float, double, COL_EPILOGUE>(a, nblk, c.nt, st); break;
       case COL_DOT: rc = dispatch<float, double, COL_DOT>(a, nblk, c.nt, st); break;
     }
+  } else if (c.ta == kTypeBF16 && c.tc == SKIPM_F64 && c.mode == COL_NORMAL) {
+    // the BF16 copy of A serves the CG products only
+    rc = dispatch<bf16_t, double, COL_NORMAL>(a, nblk, c.nt, st, c.ev0, c.ev1);
   }
   return rc;
 }

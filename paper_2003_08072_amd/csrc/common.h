@@ -31,6 +31,9 @@ void set_error(const std::string& msg);
   } while (0)
 
 constexpr int kWave = 64;
+// element type of a low-precision copy of A (alongside SKIPM_F64 / SKIPM_F32):
+// bfloat16, rounded to nearest even
+constexpr int kTypeBF16 = 2;
 // Largest m (rows of A) the library takes: the column passes keep a column of
 // up to this many rows in one lane group's registers, the sparse passes keep
 // an m-vector in LDS.
@@ -91,6 +94,9 @@ void launch_pad_copy_f32(float* dst, int64_t ldd, const float* src, int64_t lds,
                          int64_t m, int64_t n, hipStream_t st);
 void launch_pad_copy_f64_to_f32(float* dst, int64_t ldd, const double* src, int64_t lds,
                                 int64_t m, int64_t n, hipStream_t st);
+// bfloat16 copy (round to nearest even, from FP64 or FP32 source values)
+void launch_pad_copy_to_bf16(uint16_t* dst, int64_t ldd, const void* src, int src_dtype,
+                             int64_t lds, int64_t m, int64_t n, hipStream_t st);
 
 // hash + counting sort of (row, block) items by bucket
 void launch_hash(uint64_t seed, int64_t k, int s, int64_t n, int w, int32_t* bucket,

@@ -88,6 +88,27 @@ __global__ void k_pad_copy(TD* dst, int64_t ldd, const TS* src, int64_t lds, int
     dst[e] = i < m ? (TD)src[i + j * lds] : (TD)0;
   }
 }
+// x rounded to bfloat16 (8 significant bits, ties to even), as a 16-bit
+// pattern: x is first cut to FP32 by round-to-odd (truncate, then set the
+// last bit if anything was cut), which carries enough bits that the final
+// round-to-nearest-even to 8 bits equals a direct rounding of x.
+__device__ __forceinline__ uint16_t to_bf16(double x) {
+  const float t = __double2float_rz(x);
+  unsigned b = __float_as_uint(t);
+  if ((double)t != x) b |= 1u;
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+template <typename TS>
+__global__ void k_pad_copy_bf16(uint16_t* dst, int64_t ldd, const TS* src, int64_t lds, int64_t m,
+                                int64_t n) {
+  const int64_t total = ldd * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e % ldd, j = e / ldd;
+    dst[e] = i < m ? to_bf16((double)src[i + j * lds]) : (uint16_t)0;
+  }
+}
 __global__ void k_sqrt(const double* in, double* out, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -622,6 +643,15 @@ void launch_pad_copy_f64_to_f32(float* dst, int64_t ldd, const double* src, int6
                                 int64_t m, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_pad_copy<float, double>), dim3(grid_for(ldd * n)), dim3(256), 0, st, dst,
                      ldd, src, lds, m, n);
+}
+void launch_pad_copy_to_bf16(uint16_t* dst, int64_t ldd, const void* src, int src_dtype,
+                             int64_t lds, int64_t m, int64_t n, hipStream_t st) {
+  if (src_dtype == SKIPM_F64)
+    hipLaunchKernelGGL((k_pad_copy_bf16<double>), dim3(grid_for(ldd * n)), dim3(256), 0, st, dst,
+                       ldd, (const double*)src, lds, m, n);
+  else
+    hipLaunchKernelGGL((k_pad_copy_bf16<float>), dim3(grid_for(ldd * n)), dim3(256), 0, st, dst,
+                       ldd, (const float*)src, lds, m, n);
 }
 void launch_sqrt_vec(int64_t n, const double* in, double* out, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_sqrt, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
