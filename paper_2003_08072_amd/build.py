@@ -57,7 +57,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> Path:
         objs = list(ex.map(lambda s: _compile(s, hipcc), srcs))
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *map(str, objs),
-           "-lrocblas", "-o", str(tmp)]
+           "-o", str(tmp)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

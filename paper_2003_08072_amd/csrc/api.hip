@@ -24,8 +24,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "common.h"
 #include "vrefine.h"
 
@@ -101,11 +99,13 @@ struct skipm_lp_s {
   // fused CG (dense A): second direction buffer and the partial sums
   double* cd2 = nullptr;
   double* Ct = nullptr;  // mp x mp scratch of the triangular inverse
-  // Gaussian sketch: Wd = D W_G (n x w), W t for the correction vector, rocBLAS
+  // Gaussian sketch: Wd = D W_G (n x w, leading dimension ldw = n rounded up
+  // to even, so its columns are 16-byte aligned), (D W_G) t for the correction
+  // vector
   double* Wd = nullptr;
+  int64_t ldw = 0;
   double* gy = nullptr;
   double* Bsplit = nullptr;  // K-split partial sketches of the Gaussian GEMM
-  rocblas_handle blas = nullptr;
   double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
   int cg_nf = 0, cg_nd = 0;
   int64_t small_cg_bytes = 0;  // dense CG in one workgroup when A's CG copy is at most this
@@ -688,51 +688,32 @@ int sketch_solve(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt,
 }
 
 int gaussian_ready(skipm_lp_s* lp) {
-  if (!lp->Wd) SK_TRY(dalloc(lp, &lp->Wd, lp->n * (int64_t)lp->w));
+  lp->ldw = round_up(lp->n, 2);
+  if (!lp->Wd) SK_TRY(dalloc(lp, &lp->Wd, lp->ldw * (int64_t)lp->w));
   if (!lp->gy) SK_TRY(dalloc(lp, &lp->gy, lp->n));
-  if (!lp->blas && rocblas_create_handle(&lp->blas) != rocblas_status_success) {
-    lp->blas = nullptr;
-    return set_error("rocblas_create_handle failed"), SKIPM_EDEVICE;
-  }
   return SKIPM_OK;
 }
 
 int sketch_into(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt, double* B,
                 hipStream_t st) {
   if (lp->prm.sketch == SKIPM_SKETCH_GAUSSIAN) {
-    // B = A (D W_G): fill D W_G, then one FP64 GEMM over the padded rows
+    // B = A (D W_G): fill D W_G, then the FP64 matrix-core GEMM over the padded
+    // rows, split along n into slices that are summed in order
     SK_TRY(gaussian_ready(lp));
-    launch_gauss_fill(lp->prm.seed, salt, lp->n, lp->w, dscale, is_d2, lp->Wd, lp->n, st);
+    launch_gauss_fill(lp->prm.seed, salt, lp->n, lp->w, dscale, is_d2, lp->Wd, lp->ldw, st);
     SK_CHECK_HIP(hipGetLastError());
-    const double one = 1.0, zero = 0.0;
-    const int lda = (int)lp->lda, w = lp->w, n = (int)lp->n;
     const double* A = (const double*)lp->A;
-    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success)
-      return set_error("rocblas_set_stream failed"), SKIPM_EDEVICE;
-    const int ns = gauss_ksplit(lp->lda, w, lp->n);
+    const int ns = gauss_gemm_slices(lp->n, gauss_ksplit(lp->lda, lp->w, lp->n));
     const bool timed = lp->kt_every > 0 && lp->ks_ev[0] && !lp->ks_pending &&
                        hipEventRecord(lp->ks_ev[0], st) == hipSuccess;
-    rocblas_status rs;
     if (ns <= 1) {
-      rs = rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, lda, w, n,
-                         &one, A, lda, lp->Wd, n, &zero, B, lda);
+      launch_gauss_gemm(A, lp->lda, lp->Wd, lp->ldw, lp->w, lp->n, 1, B, st);
     } else {
-      // K split in ns slices (one batched GEMM, enough tiles for the GPU), the
-      // remainder of n added into slice 0, then the slices summed in order
-      const int64_t lw = lp->lda * (int64_t)w;
-      if (!lp->Bsplit) SK_TRY(dalloc(lp, &lp->Bsplit, ns * lw));
-      const int kc = n / ns, rem = n - ns * kc;
-      rs = rocblas_dgemm_strided_batched(lp->blas, rocblas_operation_none, rocblas_operation_none,
-                                         lda, w, kc, &one, A, lda, (int64_t)kc * lda, lp->Wd, n,
-                                         kc, &zero, lp->Bsplit, lda, lw, ns);
-      if (rs == rocblas_status_success && rem > 0)
-        rs = rocblas_dgemm(lp->blas, rocblas_operation_none, rocblas_operation_none, lda, w, rem,
-                           &one, A + (int64_t)ns * kc * lda, lda, lp->Wd + (int64_t)ns * kc, n,
-                           &one, lp->Bsplit, lda);
-      if (rs == rocblas_status_success) launch_sum_slices(lp->Bsplit, ns, lw, B, st);
+      const int64_t lw = lp->lda * (int64_t)lp->w;
+      if (!lp->Bsplit) SK_TRY(dalloc(lp, &lp->Bsplit, (int64_t)gauss_ksplit(lp->lda, lp->w, lp->n) * lw));
+      launch_gauss_gemm(A, lp->lda, lp->Wd, lp->ldw, lp->w, lp->n, ns, lp->Bsplit, st);
+      launch_sum_slices(lp->Bsplit, ns, lw, B, st);
     }
-    if (rs != rocblas_status_success)
-      return set_error("rocblas GEMM (Gaussian sketch) failed"), SKIPM_EDEVICE;
     SK_CHECK_HIP(hipGetLastError());
     if (timed) lp->ks_pending = hipEventRecord(lp->ks_ev[1], st) == hipSuccess;
     return SKIPM_OK;
@@ -986,11 +967,8 @@ int finish_step(skipm_lp_s* lp, hipStream_t st) {
   const double* wt = nullptr;
   if (lp->prm.sketch == SKIPM_SKETCH_GAUSSIAN) {
     // (D W_G) t; the direction kernel forms v_j = sqrt(x_j s_j) (W_G t)_j = s_j (D W_G t)_j
-    const double one = 1.0, zero = 0.0;
-    if (rocblas_set_stream(lp->blas, st) != rocblas_status_success ||
-        rocblas_dgemv(lp->blas, rocblas_operation_none, (int)lp->n, lp->w, &one, lp->Wd,
-                      (int)lp->n, lp->tw, 1, &zero, lp->gy, 1) != rocblas_status_success)
-      return set_error("rocblas_dgemv (Gaussian sketch) failed"), SKIPM_EDEVICE;
+    launch_gauss_gemv(lp->Wd, lp->ldw, lp->n, lp->w, lp->tw, lp->gy, st);
+    SK_CHECK_HIP(hipGetLastError());
     wt = lp->gy;
   }
   if (lp->nblk_vec == 1 && lp->step_one) {
@@ -1240,7 +1218,7 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   add(8 * S_NSLOTS);
   add(4 * I_NINTS);
   if (prm->sketch == SKIPM_SKETCH_GAUSSIAN) {  // D W_G, (D W_G) t, K-split slices
-    add(8 * n * w);
+    add(8 * round_up(n, 2) * w);
     add(8 * n);
     const int ns = gauss_ksplit(lda, w, n);
     if (ns > 1) add(8 * ns * lda * w);
@@ -1319,7 +1297,6 @@ int lp_destroy(skipm_lp_t lp) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : lp->ks_ev)
     if (e) (void)hipEventDestroy(e);
-  if (lp->blas) (void)rocblas_destroy_handle(lp->blas);
   if (lp->hsc) (void)hipHostFree(lp->hsc);
   delete lp;
   return SKIPM_OK;

@@ -208,6 +208,15 @@ void launch_gauss_fill(uint64_t seed, int64_t k, int64_t n, int64_t w, const dou
 void launch_sum_slices(const double* part, int ns, int64_t lw, double* out, hipStream_t st);
 // K-split of the Gaussian sketch GEMM: number of slices for m x w x n
 int gauss_ksplit(int64_t lda, int64_t w, int64_t n);
+// B_s = A[:, slice s] Wd[slice s, :] on the FP64 matrix cores for the slices
+// of n that gauss_gemm_slices(n, ns) counts (out: that many lda x w blocks;
+// with one slice, out is B itself); Wd has leading dimension ldw (even)
+void launch_gauss_gemm(const double* A, int64_t lda, const double* Wd, int64_t ldw, int64_t w,
+                       int64_t n, int ns, double* out, hipStream_t st);
+int gauss_gemm_slices(int64_t n, int ns);
+// gy = Wd t (n rows, w columns)
+void launch_gauss_gemv(const double* Wd, int64_t ldw, int64_t n, int64_t w, const double* t,
+                       double* gy, hipStream_t st);
 void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t n, int s,
                          const double* dscale, int is_d2, const int32_t* ptr,
                          const int32_t* perm, const int8_t* sign, int w, double* B,
