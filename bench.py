@@ -249,6 +249,40 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         matvec_cold_ms=cold_ms, matvec_cold_gbs=mv_bytes / (cold_ms * 1e-3) / 1e9)
 
 
+def hbm_product(sk, torch, precision, m=500, reps=50):
+    """The CG product at one precision tier over a copy of A larger than the
+    256 MiB Infinity Cache, so that every launch streams it from HBM (the
+    passes switch to non-temporal loads above 240 MiB): FP32 500 x 150000
+    (300 MB) or BF16 500 x 300000 (302 MB), FP32-valued planted LP drawn on the
+    device.  D^2 of a positive iterate; `reps` launches back to back between
+    two HIP events."""
+    from lpgen.device import dense_planted_device
+    n = 150_000 if precision == "mixed" else 300_000
+    lp = dense_planted_device(m, n, seed=(9 << 32) + n, w=4 * m)
+    prec = sk.SKIPM_PREC_MIXED if precision == "mixed" else sk.SKIPM_PREC_BF16
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    d2 = torch.rand(n, generator=gen, device="cuda", dtype=torch.float64) * 10 + 0.1
+    with sk.LP(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, s=2, seed=1, precision=prec,
+               max_cg=1) as h:
+        h.pcg(d2, torch.ones(m, dtype=torch.float64, device="cuda"), 0, tol=0.0, max_it=1)
+        u = torch.randn(m, dtype=torch.float64, device="cuda")
+        h.normal_matvec(u, reps=3)
+        ms = h.normal_matvec_timed(u, reps=reps)
+    del lp
+    tier = PREC_START_TIER[precision]
+    pa = TIER_BYTES[tier]
+    lda = (m + 7) // 8 * 8 if tier == 2 else (m + 3) // 4 * 4
+    a_bytes = pa * lda * n
+    nbytes = pa * m * n + 8 * n + 16 * m
+    return dict(shape=f"{m} x {n}", copy=TIER_NAMES[tier], copy_bytes=a_bytes,
+                bytes_per_launch=nbytes, avg_ms=ms, achieved=nbytes / (ms * 1e-3) / 1e9,
+                frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                timing=f"{reps} launches back to back between two HIP events",
+                why="copy larger than the 256 MiB Infinity Cache: every launch reads it "
+                    "from HBM")
+
+
 def host_threads():
     """Threads the oracle runs on: its BLAS/LAPACK pool (numpy's own loops are
     single-threaded), bounded by the cores this process may use."""
@@ -380,33 +414,48 @@ def run_batch(sk, torch, args):
         "cg_total_mean": sum(r.cg_total for r in res) / len(res),
         "batch_walls_s": walls,
         "cg_product_gbs": cg_bytes * args.steps / wall / 1e9,
-        "roofline": {"bound": "hbm", "achieved": mv_bytes / (mv_ms * 1e-3) / 1e9,
+        # the batch as a whole: the CG products' algorithmic bytes over all LPs
+        # and all timed passes, over the wall time of those passes
+        "roofline": {"bound": "hbm", "achieved": cg_bytes * args.steps / wall / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_colpass (fused normal matvec) on the largest LP "
-                               f"{lps[big].m} x {lps[big].n} FP32",
-                     "avg_ms": mv_ms, "bytes_per_launch": mv_bytes},
+                     "frac": cg_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_colpass (fused normal matvec) over every LP of the batch",
+                     "timing": "CG-product bytes of all solves of the timed batch passes over "
+                               "their wall time",
+                     "single_lp": {"kernel": f"k_colpass on the largest LP {lps[big].m} x "
+                                             f"{lps[big].n} FP32, back to back",
+                                   "avg_ms": mv_ms, "bytes_per_launch": mv_bytes,
+                                   "achieved": mv_bytes / (mv_ms * 1e-3) / 1e9,
+                                   "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}},
         "cpu_baseline": cpu,
     }
 
 
 def cpu_baseline_batch(budget):
-    """The oracle (exact-Cholesky IPM) on the host cores over the numpy LPs of
-    the batched workload, in index order, until `budget` seconds are spent."""
-    from lpgen import batch_lp
+    """The oracle (exact-Cholesky IPM) on the host cores over the very LPs the
+    GPU batch solves (drawn again on the device, copied to the host), in index
+    order, until `budget` seconds are spent."""
+    import numpy as np
+    import torch
+
+    from lpgen.device import batch_lp_device
     from oracle import ipm as O
     cores = host_threads()
     t_used, done, i = 0.0, 0, 0
     while t_used < budget and i < 64:
-        lp = batch_lp(i)
+        lp = batch_lp_device(i)
+        A = lp.A.to(torch.float64).cpu().numpy()
+        b, c = lp.b.cpu().numpy(), lp.c.cpu().numpy()
+        del lp
         t0 = time.perf_counter()
-        O.ipm(lp.A, lp.b, lp.c, O.IPMParams(solver="exact", eps_gap=lp.eps_gap))
+        O.ipm(np.ascontiguousarray(A), b, c, O.IPMParams(solver="exact", eps_gap=1e-6))
         t_used += time.perf_counter() - t0
         done += 1
         i += 1
     return dict(value=done / t_used, unit="solves/s", cores=cores, kind="oracle",
-                sample=f"LPs 0..{done - 1} of the batched workload (numpy draws of the same "
-                       f"distribution), full exact-Cholesky solves, {t_used:.1f} s")
+                sample=f"LPs 0..{done - 1} of the batched workload (the same device-drawn "
+                       f"instances the GPU solves), full exact-Cholesky solves, "
+                       f"{t_used:.1f} s")
 
 
 def serve_trace(sk, torch, args, trace, lps, scale=1.0):
@@ -646,6 +695,14 @@ def main():
                 cpu1 = cpu_baseline(lp, args.cpu_budget / 2)
         except ImportError:
             cpu1 = None
+    # the low-precision products measured where the cache cannot hold their copy
+    hbm_valid = {}
+    if lp.fmt == "dense":
+        for pr in precs:
+            if pr != "fp64":
+                print(f"[bench] {pr} product over a copy larger than the cache", file=sys.stderr,
+                      flush=True)
+                hbm_valid[pr] = hbm_product(sk, torch, pr)
     mv = dict(head)
     timing = ("HIP events stamped with the kernel's start and end (hipExtLaunchKernelGGL) on "
               "every 8th CG product of the timed solves")
@@ -693,7 +750,10 @@ def main():
                      # the product's working set against the 256 MiB Infinity Cache
                      # (memory-side cache in front of HBM): at or under it, part of
                      # the bytes can be served from the cache
-                     "cache_resident": mv["matvec_bytes"] <= INFINITY_CACHE_BYTES},
+                     "cache_resident": mv["matvec_bytes"] <= INFINITY_CACHE_BYTES,
+                     # the same kernel at the same tier on a copy the cache cannot hold
+                     "hbm_valid": hbm_valid.get(head["precision"])},
+        "hbm_valid_products": hbm_valid,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
     }

@@ -318,16 +318,23 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* by
 int lp_device_bytes(skipm_lp_t lp, int64_t* bytes);
 
 /* Solve `count` independent LPs (handles from lp_create, each from its
- * current iterate, as lp_solve).  `workers` host threads (<= 0: min(count, 8))
- * each own one non-blocking stream of default priority and take the next
- * unsolved handle in index order, so up to `workers` LPs run their IPM
- * iterations at once and their kernels overlap on the device.  Each LP's
- * arithmetic is that of lp_solve alone, so res[i] (and its final iterate) is
- * bitwise the same as a lone solve.  The call first waits for all work queued
- * on the device and returns when every LP has finished.  res: host array of
- * `count`.  Returns SKIPM_OK when every solve ran, an LP's outcome (OK,
- * ENOTCONV, ESTALL, ERANK, ENAN) being res[i].status; an argument, memory or
- * device error stops the batch and is returned. */
+ * current iterate, as lp_solve).  Dense LPs with FP64 CG products go through
+ * the grouped engine: `workers` host threads (<= 0: min(count, 8)), each with
+ * its own non-blocking stream of default priority, take the LPs through the
+ * per-LP steps of their IPM iterations (stopping test, sketch, factorisation;
+ * epilogue, correction vector, step), while one executor runs the CG of every
+ * LP that is ready in grouped launches: one launch per CG pass and lane-group
+ * shape, whose work list is the (LP, workgroup) pairs of its LPs, each LP at
+ * its own CG iteration; an LP joins when its factorisation is done and leaves
+ * at the first host check after its CG has converged (Alg. 1 / Alg. 2 per LP,
+ * unchanged).  The other LPs (CSR, FP32/BF16 CG copies) run lp_solve on
+ * `workers` further threads.  Every LP keeps the arithmetic of a lone solve,
+ * so res[i] (and its final iterate) is bitwise that of lp_solve alone.  The
+ * call first waits for all work queued on the device and returns when every
+ * LP has finished.  res: host array of `count`.  Returns SKIPM_OK when every
+ * solve ran, an LP's outcome (OK, ENOTCONV, ESTALL, ERANK, ENAN) being
+ * res[i].status; an argument, memory or device error stops the batch and is
+ * returned. */
 int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t workers);
 
 /* Request server: a FIFO of LP solves admitted by device-memory footprint.

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.h"
+#include "handle.h"
 #include "vrefine.h"
 
 namespace skipm {
@@ -33,100 +34,6 @@ void set_error(const std::string& msg) { g_err = msg; }
 }  // namespace skipm
 
 using namespace skipm;
-
-struct skipm_lp_s {
-  int device = 0;
-  int64_t bytes = 0;  // device bytes held (every allocation of the handle)
-  int64_t m = 0, n = 0, nnz = 0;
-  int fmt = SKIPM_DENSE, a_dtype = SKIPM_F64;
-  int64_t lda = 0, mp = 0;
-  skipm_params prm{};
-  int w = 0, s = 1;
-  bool mixed = false;
-  // device buffers
-  void* A = nullptr;
-  float* A32 = nullptr;
-  uint16_t* A16 = nullptr;  // bfloat16 copy of A (precision SKIPM_PREC_BF16)
-  int64_t lda16 = 0;        // its leading dimension: m rounded up to 8 (16-byte columns)
-  double *b = nullptr, *c = nullptr, *x = nullptr, *y = nullptr, *sv = nullptr;
-  double *d2 = nullptr, *rd = nullptr, *dx = nullptr, *ds = nullptr, *v = nullptr;
-  double *rp = nullptr, *p = nullptr, *dy = nullptr, *g = nullptr;
-  double *cr = nullptr, *cz = nullptr, *cd = nullptr, *cq = nullptr, *cw = nullptr,
-         *cx = nullptr;
-  double *tw = nullptr, *tq = nullptr;
-  double* B = nullptr;
-  double* Gpart = nullptr;
-  int ksplit = 1;
-  double* G = nullptr;
-  double* Xb = nullptr;
-  // correction-vector solve: whitened sketches B1 = L0^{-1} B, B2 = L1^{-1} B1, their
-  // Gram inverses, and the accumulated inverse factors M1 = X0, M2 = X1 X0
-  double *B1 = nullptr, *B2 = nullptr, *Gv = nullptr, *Xv = nullptr, *M1 = nullptr,
-         *M2 = nullptr, *rv = nullptr, *uv1 = nullptr, *uv2 = nullptr;
-  double *rt = nullptr, *dyc = nullptr;  // mixed precision: FP64 residual and correction
-  // correction vector: the best t so far and its residual (tw, rv), and the
-  // candidate of the current refinement step (tw2, rv2)
-  double *tw2 = nullptr, *rv2 = nullptr;
-  int last_outer = 0;
-  // precision tier of the CG products (SKIPM_TIER_*): start_tier from the
-  // parameters, tier the current one (it only moves up within a run)
-  int start_tier = SKIPM_TIER_FP64, tier = SKIPM_TIER_FP64;
-  int demote_iter = -1;  // IPM iteration of the first move up, -1 if none
-  // rank-loss handling of the current solve and of the run (Lemma 3)
-  int step_resketches = 0, step_shifts = 0;
-  int run_resketches = 0, run_shifts = 0;
-  int vrounds_built = 0;
-  // CSR storage (format SKIPM_CSR)
-  SparseA sp;
-  double *cf1 = nullptr, *cf2 = nullptr, *segsum = nullptr;
-  int nblk_csc = 1;
-  int32_t *bucket = nullptr, *perm = nullptr, *perm_raw = nullptr, *bptr = nullptr,
-          *bcnt = nullptr, *bcur = nullptr;
-  int8_t* sign = nullptr;
-  double* part = nullptr;  // column-pass partial sums
-  double* red = nullptr;
-  double* sc = nullptr;
-  int32_t* is = nullptr;
-  double* hsc = nullptr;  // pinned: S_NSLOTS doubles then I_NINTS ints
-  int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_A16 = 1, nblk_B = 1, nblk_vec = 1;
-  int64_t k = 0;
-  int64_t hashed_k = -1;
-  int prev_cg = 8;
-  double last_rel_gap = HUGE_VAL;  // relative gap at the last stopping test
-  int origin_pending = 1;
-  int small_steps = 0;
-  double bnorm = 0, cnorm = 0;
-  // fused CG (dense A): second direction buffer and the partial sums
-  double* cd2 = nullptr;
-  double* Ct = nullptr;  // mp x mp scratch of the triangular inverse
-  // Gaussian sketch: Wd = D W_G (n x w, leading dimension ldw = n rounded up
-  // to even, so its columns are 16-byte aligned), (D W_G) t for the correction
-  // vector
-  double* Wd = nullptr;
-  int64_t ldw = 0;
-  double* gy = nullptr;
-  double* Bsplit = nullptr;  // K-split partial sketches of the Gaussian GEMM
-  double* cgred = nullptr;  // [cg_nf] d^T q partials, then [cg_nd][2] r^T z, r^T r partials
-  int cg_nf = 0, cg_nd = 0;
-  int64_t small_cg_bytes = 0;  // dense CG in one workgroup when A's CG copy is at most this
-  int step_one = 1;  // one-workgroup step tail where the n-vector passes take one workgroup
-  std::vector<void*> allocs;
-  // sampled HIP-event timing of the CG's normal-equation product (lp_kernel_timing):
-  // event pairs around every kt_every-th product, harvested at the CG's host checks
-  int kt_every = 0;
-  std::vector<hipEvent_t> kt_ev;  // 2 * kKtPairs events
-  std::vector<int> kt_iter;       // CG iteration of each pending pair
-  std::vector<int> kt_tier;       // precision tier of the product it brackets
-  double kt_sum_ms = 0;
-  int64_t kt_count = 0;
-  double kt_tier_ms[3] = {0, 0, 0};  // the same, per SKIPM_TIER_*
-  int64_t kt_tier_n[3] = {0, 0, 0};
-  // event pair around the sketch product of every IPM iteration while timing is on
-  hipEvent_t ks_ev[2] = {nullptr, nullptr};
-  bool ks_pending = false;
-  double ks_sum_ms = 0;
-  int64_t ks_count = 0;
-};
 
 namespace {
 
@@ -385,8 +292,68 @@ void kt_harvest(skipm_lp_s* lp, int executed) {
   lp->kt_tier.clear();
 }
 
-int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, const double* pdq,
-                  double* prz, const int32_t* done, hipStream_t st);
+// The passes of a fused dense CG iteration of parity p (d_k lives in cd for
+// even k, cd2 for odd k): the product pass that opens it, the finish that
+// forms q and the d^T q partials, and the Q^{-1} pass that closes it.  cg.k is
+// the caller's (the iteration).  The lone CG and the grouped batch CG launch
+// exactly these arguments.
+ColPass cg_normal_args(skipm_lp_s* lp, int p) {
+  ColPass cp = colpass_A(lp, COL_NORMAL);
+  cp.u = lp->cd;  // d_0 (written by the CG init) for iteration 0
+  cp.d2 = lp->d2;
+  use_tier_copy(lp, cp);
+  cp.done = lp->is + I_CG_DONE;
+  cp.cg.on = 1;
+  cp.cg.inner = lp->prm.inner;
+  cp.cg.z = lp->cz;
+  cp.cg.d_old = p ? lp->cd : lp->cd2;
+  cp.cg.d_new = p ? lp->cd2 : lp->cd;
+  cp.cg.prz = lp->cgred + lp->cg_nf;
+  cp.cg.np = lp->cg_nd;
+  cp.cg.sc = lp->sc;
+  cp.cg.is = lp->is;
+  return cp;
+}
+
+FinishDotArgs cg_finish_args(skipm_lp_s* lp, int p, int nblk_product) {
+  FinishDotArgs f;
+  f.part = lp->part;
+  f.ldp = lp->mp;
+  f.nblk = nblk_product;
+  f.m = lp->m;
+  f.dvec = p ? lp->cd2 : lp->cd;
+  f.out = lp->cq;
+  f.dq_out = lp->cgred;
+  f.done = lp->is + I_CG_DONE;
+  return f;
+}
+
+ColPass cg_close_args(skipm_lp_s* lp, double* xsol, int p) {
+  ColPass pq{};
+  pq.mode = COL_DOT;
+  pq.A = lp->G;
+  pq.ta = SKIPM_F64;
+  pq.tc = SKIPM_F64;
+  pq.lda = lp->mp;
+  pq.m = lp->mp;
+  pq.n = lp->m;
+  pq.u = lp->cq;
+  pq.done = lp->is + I_CG_DONE;
+  pq.nblk = lp->cg_nd;
+  pq.cg.on = 1;
+  pq.cg.inner = lp->prm.inner;
+  pq.cg.sc = lp->sc;
+  pq.cg.is = lp->is;
+  pq.cg.q = lp->cq;
+  pq.cg.d = p ? lp->cd2 : lp->cd;
+  pq.cg.x = xsol;
+  pq.cg.r = lp->cr;
+  pq.cg.zz = lp->cz;
+  pq.cg.pdq = lp->cgred;
+  pq.cg.nf = lp->cg_nf;
+  pq.cg.prz_out = lp->cgred + lp->cg_nf;
+  return pq;
+}
 
 // One CG iteration on A D^2 A^T (the chunk loop checks the done flag).
 int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
@@ -419,71 +386,24 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
     launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, done, st);
     launch_csr_fold(A, lp->segsum, 0, 1.0, nullptr, 0.0, lp->cq, done, st, dk, pdq);
     kt_end(lp, q, st);
-    SK_TRY(cg_close_pass(lp, xsol, iter, dk, pdq, prz, done, st));
-    SK_CHECK_HIP(hipGetLastError());
-    return SKIPM_OK;
+  } else {
+    // Three launches per iteration: the product pass opens the iteration (stop
+    // test, beta, d_k), the finish adds d^T q partials, the Q^{-1} pass closes
+    // it (alpha, x, r, z and r^T z partials).  d alternates between two buffers.
+    ColPass cp = cg_normal_args(lp, iter & 1);
+    cp.cg.k = iter;
+    const int q = kt_take(lp, iter);
+    if (q >= 0) {  // dense product: the runtime stamps the events with the kernel itself
+      cp.ev0 = lp->kt_ev[2 * q];
+      cp.ev1 = lp->kt_ev[2 * q + 1];
+    }
+    SK_TRY(run_colpass(cp, st));
+    if (launch_finish_dot(lp->part, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
+        lp->cg_nf)
+      return set_error("fused CG: finish shape mismatch"), SKIPM_EINVAL;
   }
-  ColPass cp = colpass_A(lp, COL_NORMAL);
-  cp.u = lp->cd;
-  cp.d2 = lp->d2;
-  use_tier_copy(lp, cp);
-  cp.done = done;
-  const int q = kt_take(lp, iter);
-  if (q >= 0) {  // dense product: the runtime stamps the events with the kernel itself
-    cp.ev0 = lp->kt_ev[2 * q];
-    cp.ev1 = lp->kt_ev[2 * q + 1];
-  }
-  // Three launches per iteration: the product pass opens the iteration (stop
-  // test, beta, d_k), the finish adds d^T q partials, the Q^{-1} pass closes it
-  // (alpha, x, r, z and r^T z partials).  d alternates between two buffers.
-  cp.u = lp->cd;  // d_0 (written by the CG init) for iteration 0
-  cp.cg.on = 1;
-  cp.cg.inner = lp->prm.inner;
-  cp.cg.k = iter;
-  cp.cg.z = lp->cz;
-  cp.cg.d_old = dprev;
-  cp.cg.d_new = dk;
-  cp.cg.prz = prz;
-  cp.cg.np = lp->cg_nd;
-  cp.cg.sc = lp->sc;
-  cp.cg.is = lp->is;
-  SK_TRY(run_colpass(cp, st));
-  if (launch_finish_dot(lp->part, lp->mp, cp.nblk, lp->m, dk, lp->cq, pdq, done, st) !=
-      lp->cg_nf)
-    return set_error("fused CG: finish shape mismatch"), SKIPM_EINVAL;
-  SK_TRY(cg_close_pass(lp, xsol, iter, dk, pdq, prz, done, st));
-  SK_CHECK_HIP(hipGetLastError());
-  return SKIPM_OK;
-}
-
-// The Q^{-1} pass that closes CG iteration `iter`: alpha, w = Q^{-1} q, the x,
-// r, z updates and the r^T z, r^T r partials.
-int cg_close_pass(skipm_lp_s* lp, double* xsol, int iter, const double* dk, const double* pdq,
-                  double* prz, const int32_t* done, hipStream_t st) {
-  ColPass pq{};
-  pq.mode = COL_DOT;
-  pq.A = lp->G;
-  pq.ta = SKIPM_F64;
-  pq.tc = SKIPM_F64;
-  pq.lda = lp->mp;
-  pq.m = lp->mp;
-  pq.n = lp->m;
-  pq.u = lp->cq;
-  pq.done = done;
-  pq.nblk = lp->cg_nd;
-  pq.cg.on = 1;
-  pq.cg.inner = lp->prm.inner;
+  ColPass pq = cg_close_args(lp, xsol, iter & 1);
   pq.cg.k = iter;
-  pq.cg.sc = lp->sc;
-  pq.cg.is = lp->is;
-  pq.cg.q = lp->cq;
-  pq.cg.d = dk;
-  pq.cg.x = xsol;
-  pq.cg.r = lp->cr;
-  pq.cg.zz = lp->cz;
-  pq.cg.pdq = pdq;
-  pq.cg.nf = lp->cg_nf;
-  pq.cg.prz_out = prz;
   SK_TRY(run_colpass(pq, st));
   SK_CHECK_HIP(hipGetLastError());
   return SKIPM_OK;
@@ -650,13 +570,15 @@ constexpr int kFreshSketches = 3, kShifts = 3;
 
 int sketch_solve(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt,
                  const double* rhs, double* xsol, double tol, int max_it, int* its,
-                 hipStream_t st) {
-  lp->step_resketches = 0;
-  lp->step_shifts = 0;
+                 hipStream_t st, int first_attempt = 0) {
+  if (first_attempt == 0) {
+    lp->step_resketches = 0;
+    lp->step_shifts = 0;
+  }
   lp->last_outer = 1;
   double shift = 0.0;
   int rc = SKIPM_ERANK;
-  for (int attempt = 0; attempt <= kFreshSketches + kShifts; ++attempt) {
+  for (int attempt = first_attempt; attempt <= kFreshSketches + kShifts; ++attempt) {
     if (attempt <= kFreshSketches) {
       // fresh salts sit far above any IPM iteration index
       const int64_t sa = salt + ((int64_t)attempt << 40);
@@ -1099,6 +1021,24 @@ int step_internal(skipm_lp_s* lp, skipm_step_info* info, double bnorm, double cn
   return SKIPM_OK;
 }
 
+// res from the slots of the last stopping test (the rest of res, the CG
+// counts, is accumulated by the caller)
+void fill_result(skipm_lp_s* lp, skipm_result* res, int status, int it) {
+  const StopState ss = stop_test(lp, lp->bnorm, lp->cnorm);
+  res->status = status;
+  res->iters = it;
+  res->obj_p = ss.ctx;
+  res->obj_d = ss.bty;
+  res->rel_gap = ss.rel_gap;
+  res->rp_norm = ss.rp;
+  res->rd_norm = ss.rd;
+  res->mu = ss.mu;
+  res->demote_iter = lp->demote_iter;
+  res->tier_final = lp->tier;
+  res->resketches = lp->run_resketches;
+  res->shifts = lp->run_shifts;
+}
+
 double host_norm(const double* dptr, int64_t n, int* rc) {
   std::vector<double> h((size_t)n);
   if (hipMemcpy(h.data(), dptr, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
@@ -1112,6 +1052,131 @@ double host_norm(const double* dptr, int64_t n, int* rc) {
 }
 
 }  // namespace
+
+namespace skipm {
+
+bool batch_groupable(const skipm_lp_s* lp) {
+  return lp->fmt == SKIPM_DENSE && lp->start_tier == SKIPM_TIER_FP64;
+}
+
+void batch_phase_a(skipm_lp_s* lp, skipm_result* res, BatchLp* b, hipStream_t st) {
+  b->grouped = false;
+  b->its = 0;
+  b->fail = 0;
+  auto end = [&](int status) {
+    fill_result(lp, res, status, b->it);
+    b->active = false;
+  };
+  auto check = [&](int rc) {
+    if (rc == SKIPM_OK) return true;
+    b->rc = rc;
+    b->err = skipm_last_error();
+    res->status = rc;
+    b->active = false;
+    return false;
+  };
+  if (!check(hipSetDevice(lp->device) == hipSuccess ? SKIPM_OK : SKIPM_EDEVICE)) return;
+  if (!check(prologue(lp, st)) || !check(sync_read(lp, st))) return;
+  const StopState ss = stop_test(lp, lp->bnorm, lp->cnorm);
+  lp->last_rel_gap = ss.nan ? HUGE_VAL : ss.rel_gap;
+  if (b->it >= lp->prm.max_outer) {
+    end(ss.converged ? SKIPM_OK : (ss.nan ? SKIPM_ENAN : SKIPM_ENOTCONV));
+    return;
+  }
+  if (ss.nan) return end(SKIPM_ENAN);
+  if (lp->k > 0) {
+    lp->small_steps = lp->hsc[S_ALPHA] < 1e-12 ? lp->small_steps + 1 : 0;
+    if (lp->small_steps >= 3) return end(SKIPM_ESTALL);
+  }
+  if (ss.converged) return end(SKIPM_OK);
+  const int64_t salt = lp->prm.resketch ? lp->k : 0;
+  lp->step_resketches = 0;
+  lp->step_shifts = 0;
+  lp->last_outer = 1;
+  if (!check(sketch_into(lp, lp->d2, 1, salt, lp->B, st)) || !check(factor(lp, 0.0, st))) return;
+  // the one-workgroup CG where pcg_run would take it (small dense FP64 LPs),
+  // else the grouped CG
+  const int rc = pcg_small(lp, lp->p, lp->dy, lp->prm.tol_cg, lp->prm.max_cg, &b->its, &b->fail, st);
+  if (rc < 0) check(rc);
+  else b->grouped = rc == 0;
+}
+
+void batch_phase_b(skipm_lp_s* lp, skipm_result* res, BatchLp* b, hipStream_t st) {
+  auto fail_with = [&](int rc) {
+    if (rc == SKIPM_EINVAL || rc == SKIPM_EDEVICE || rc == SKIPM_ENOMEM) {
+      b->rc = rc;
+      b->err = skipm_last_error();
+    }
+    fill_result(lp, res, rc, b->it);
+    b->active = false;
+  };
+  if (hipSetDevice(lp->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return fail_with(SKIPM_EDEVICE);
+  }
+  int its = b->its;
+  if (b->fail) {
+    // Lemma 3's failure event: fresh sketches, then shifts, each with its own CG
+    const int64_t salt = lp->prm.resketch ? lp->k : 0;
+    const int rc = sketch_solve(lp, lp->d2, 1, salt, lp->p, lp->dy, lp->prm.tol_cg,
+                                lp->prm.max_cg, &its, st, 1);
+    if (rc != SKIPM_OK) return fail_with(rc);
+  } else {
+    lp->run_resketches += lp->step_resketches;
+    lp->run_shifts += lp->step_shifts;
+  }
+  lp->prev_cg = its;
+  res->cg_total += its;
+  res->cg_max = std::max(res->cg_max, its);
+  int rc = epilogue(lp, st);
+  if (rc != SKIPM_OK) return fail_with(rc);
+  int vits = 0;
+  double vrel = 0;
+  rc = v_solve(lp, &vits, &vrel, st);
+  if (rc != SKIPM_OK) return fail_with(rc);
+  rc = finish_step(lp, st);
+  if (rc != SKIPM_OK) return fail_with(rc);
+  lp->k += 1;
+  b->it += 1;
+}
+
+void batch_cg_passes(skipm_lp_s* lp, ColPass normal[2], FinishDotArgs fin[2], ColPass close[2],
+                     ColPass* qinit, CgInitArgs* init, CgCloseArgs* cls) {
+  for (int p = 0; p < 2; ++p) {
+    normal[p] = cg_normal_args(lp, p);
+    fin[p] = cg_finish_args(lp, p, normal[p].nblk);
+    close[p] = cg_close_args(lp, lp->dy, p);
+  }
+  ColPass q{};
+  q.mode = COL_DOT;
+  q.A = lp->G;
+  q.ta = SKIPM_F64;
+  q.tc = SKIPM_F64;
+  q.lda = lp->mp;
+  q.m = lp->mp;
+  q.n = lp->m;
+  q.u = lp->p;
+  q.t_out = lp->cw;
+  q.nblk = 0;
+  *qinit = q;
+  init->m = lp->m;
+  init->rhs = lp->p;
+  init->zin = lp->cw;
+  init->r = lp->cr;
+  init->z = lp->cz;
+  init->d = lp->cd;
+  init->x = lp->dy;
+  init->sc = lp->sc;
+  init->is = lp->is;
+  init->tol = lp->prm.tol_cg;
+  init->max_it = lp->prm.max_cg;
+  cls->prz = lp->cgred + lp->cg_nf;
+  cls->np = lp->cg_nd;
+  cls->sc = lp->sc;
+  cls->is = lp->is;
+}
+
+}  // namespace skipm
 
 extern "C" {
 
@@ -1785,19 +1850,7 @@ int lp_solve(skipm_lp_t lp, skipm_result* res, hipStream_t st) {
     res->cg_total += info.cg_iters;
     res->cg_max = std::max(res->cg_max, info.cg_iters);
   }
-  const StopState ss = stop_test(lp, bn, cn);
-  res->status = status;
-  res->iters = it;
-  res->obj_p = ss.ctx;
-  res->obj_d = ss.bty;
-  res->rel_gap = ss.rel_gap;
-  res->rp_norm = ss.rp;
-  res->rd_norm = ss.rd;
-  res->mu = ss.mu;
-  res->demote_iter = lp->demote_iter;
-  res->tier_final = lp->tier;
-  res->resketches = lp->run_resketches;
-  res->shifts = lp->run_shifts;
+  fill_result(lp, res, status, it);
   if (status != SKIPM_OK && status != SKIPM_ENOTCONV) return status;
   return status == SKIPM_ENOTCONV ? (set_error("max_outer reached"), SKIPM_ENOTCONV) : SKIPM_OK;
 }

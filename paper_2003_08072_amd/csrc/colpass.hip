@@ -23,6 +23,7 @@
 // fixed order and writes one partial vector; launch_finish sums the partials
 // of all workgroups in a fixed order, so results are bitwise reproducible.
 #include <hip/hip_ext.h>
+#include <string.h>
 
 #include "common.h"
 
@@ -92,8 +93,10 @@ struct Args {
   CgFuse cg;
 };
 
+// The pass of workgroup `bid` of one matrix (its column range, its partial):
+// the body of k_colpass, and of k_colpass_grouped for each matrix of a group.
 template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
-__global__ __launch_bounds__(NT) void k_colpass(Args a) {
+__device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
   constexpr int V = Vec<TA>::V;
   typedef typename Vec<TA>::type VT;
   constexpr int NGW = 64 / G;
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   const int grp = lane / G, lg = lane % G;
   const int slot = wid * NGW + grp;
   constexpr int NSLOT = NW * NGW;
-  const int64_t c0 = (int64_t)blockIdx.x * a.cpb;
+  const int64_t c0 = (int64_t)bid * a.cpb;
   const int64_t c1 = c0 + a.cpb < a.n ? c0 + a.cpb : a.n;
   const TA* __restrict__ A = (const TA*)a.A;
   const TC* __restrict__ u = (const TC*)a.u;
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
       const double crit = is[I_CG_RESID] ? rr : rz;
       const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
       cg_beta = a.cg.inner == SKIPM_INNER_CG ? rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)] : 0.0;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bid == 0 && threadIdx.x == 0) {
         sc[S_CG_RZ] = rz;
         sc[S_V_RR] = rr;
         sc[S_CG_RZH0 + (int)(k & 1)] = rz;
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
     } else if (MODE == COL_DOT) {
       const double dq = cgs[0];
       if (!(dq > 0)) {  // breakdown: the operator lost positive definiteness numerically
-        if (blockIdx.x == 0 && threadIdx.x == 0) is[I_CG_DONE] = 1;
+        if (bid == 0 && threadIdx.x == 0) is[I_CG_DONE] = 1;
         return;
       }
       cg_alpha = a.cg.inner == SKIPM_INNER_RICHARDSON ? 1.0 : sc[S_CG_RZH0 + (int)(k & 1)] / dq;
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
   }
   double cg_pz = 0, cg_pr = 0;
   if (cg_dir) {  // d_k = z_k + beta_k d_{k-1}; block 0 stores it
-    const bool store = blockIdx.x == 0 && wid == 0 && grp == 0;
+    const bool store = bid == 0 && wid == 0 && grp == 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t row0 = (int64_t)(r * G + lg) * V;
@@ -428,8 +431,8 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
           t0 += sred[w][0];
           t1 += sred[w][1];
         }
-        a.cg.prz_out[2 * blockIdx.x] = t0;
-        a.cg.prz_out[2 * blockIdx.x + 1] = t1;
+        a.cg.prz_out[2 * bid] = t0;
+        a.cg.prz_out[2 * bid + 1] = t1;
       }
     }
     return;
@@ -445,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
         if (NACC > 1) acc2[r][e] += __shfl_xor(acc2[r][e], off, 64);
       }
   }
-  TC* part = (TC*)a.part + (int64_t)blockIdx.x * NACC * a.ldp;
+  TC* part = (TC*)a.part + (int64_t)bid * NACC * a.ldp;
   if constexpr (kOneStep) {
     // each row of the partial is the sum over waves in wave order: the same
     // order, hence the same rounding, as the turn-by-turn fold below
@@ -495,10 +498,40 @@ __global__ __launch_bounds__(NT) void k_colpass(Args a) {
       t1 += sred[w][1];
       t2 += sred[w][2];
     }
-    a.red[blockIdx.x * 8 + 0] = t0;
-    a.red[blockIdx.x * 8 + 1] = t1;
-    a.red[blockIdx.x * 8 + 2] = t2;
+    a.red[bid * 8 + 0] = t0;
+    a.red[bid * 8 + 1] = t1;
+    a.red[bid * 8 + 2] = t2;
   }
+}
+
+template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
+__global__ __launch_bounds__(NT) void k_colpass(Args a) {
+  colpass_body<TA, TC, G, R, MODE, NT, STREAM>(a, blockIdx.x);
+}
+
+// The same pass over several matrices of one lane-group shape in one launch
+// (the CG of a batch of LPs): first[i] is the first workgroup of matrix i
+// (first[nmat] the total), each matrix keeps its own workgroup count, column
+// ranges and partials, so its arithmetic is that of its own launch.  Matrix
+// i is at CG iteration kstart[i] + j and takes the arguments of that
+// iteration's parity, args[2 i + (k & 1)]; a pass outside the CG (kstart
+// null) takes args[i].
+template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
+__global__ __launch_bounds__(NT) void k_colpass_grouped(const Args* __restrict__ args,
+                                                        const int32_t* __restrict__ first,
+                                                        int nmat,
+                                                        const int64_t* __restrict__ kstart,
+                                                        int j) {
+  int lo = 0, hi = nmat - 1;  // the matrix whose workgroup range holds blockIdx.x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t k = kstart ? kstart[lo] + j : 0;
+  Args a = args[kstart ? 2 * lo + (int)(k & 1) : lo];
+  a.cg.k = k;
+  colpass_body<TA, TC, G, R, MODE, NT, STREAM>(a, (int)blockIdx.x - first[lo]);
 }
 
 // B[:, b] = sum over the (sorted) items of bucket b of sign * d_j * A[:, j]
@@ -628,16 +661,17 @@ __global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int
 }
 
 // k_finish for the fused CG: out = sum of the partials, and per workgroup the
-// partial sum of dvec_i out_i over its 16 rows, in row order.
-__global__ __launch_bounds__(256) void k_finish_dot(const double* __restrict__ part, int64_t ldp,
-                                                    int nblk, int64_t m,
-                                                    const double* __restrict__ dvec,
-                                                    double* __restrict__ out,
-                                                    double* __restrict__ dq_out,
-                                                    const int32_t* __restrict__ done) {
+// partial sum of dvec_i out_i over its 16 rows, in row order.  Workgroup `bid`
+// of one matrix (the body of k_finish_dot and of k_finish_dot_grouped).
+__device__ __forceinline__ void finish_dot_body(const double* __restrict__ part, int64_t ldp,
+                                                int nblk, int64_t m,
+                                                const double* __restrict__ dvec,
+                                                double* __restrict__ out,
+                                                double* __restrict__ dq_out,
+                                                const int32_t* __restrict__ done, const int bid) {
   __shared__ double tile[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t i = (int64_t)blockIdx.x * 16 + tx;
+  const int64_t i = (int64_t)bid * 16 + tx;
   // as in k_finish: 16 partials per thread in flight before the done flag
   const int64_t ic = i < m ? i : m - 1;
   double v[16];
@@ -668,8 +702,35 @@ __global__ __launch_bounds__(256) void k_finish_dot(const double* __restrict__ p
   if (threadIdx.x == 0) {
     double s = 0;
     for (int c = 0; c < 16; ++c) s += tile[1][c];
-    dq_out[blockIdx.x] = s;
+    dq_out[bid] = s;
   }
+}
+
+__global__ __launch_bounds__(256) void k_finish_dot(const double* __restrict__ part, int64_t ldp,
+                                                    int nblk, int64_t m,
+                                                    const double* __restrict__ dvec,
+                                                    double* __restrict__ out,
+                                                    double* __restrict__ dq_out,
+                                                    const int32_t* __restrict__ done) {
+  finish_dot_body(part, ldp, nblk, m, dvec, out, dq_out, done, blockIdx.x);
+}
+
+// k_finish_dot over the LPs of a grouped CG; LP i at iteration kstart[i] + j
+// takes args[2 i + (k & 1)].
+__global__ __launch_bounds__(256) void k_finish_dot_grouped(const FinishDotArgs* __restrict__ args,
+                                                            const int32_t* __restrict__ first,
+                                                            int nmat,
+                                                            const int64_t* __restrict__ kstart,
+                                                            int j) {
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const FinishDotArgs& f = args[2 * lo + (int)((kstart[lo] + j) & 1)];
+  finish_dot_body(f.part, f.ldp, f.nblk, f.m, f.dvec, f.out, f.dq_out, f.done,
+                  (int)blockIdx.x - first[lo]);
 }
 
 // ---------------------------------------------------------------------------
@@ -800,7 +861,10 @@ int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode) {
   const int nt = threads_for(mode, sh.R, V, tc == SKIPM_F64 ? 8 : 4);
   const int64_t slots = (int64_t)(nt / 64) * (64 / sh.G);
   const int target = nt == 256 ? 512 : 256;
-  int64_t nb = (n + slots * 4 - 1) / (slots * 4);  // at least ~4 columns per slot
+  // at least 16 columns per lane group: fewer, longer workgroups for small
+  // matrices, whose passes are bound by each workgroup's fixed start and fold
+  // (in the batch engine's grouped launches most of all)
+  int64_t nb = (n + slots * 16 - 1) / (slots * 16);
   if (nb > target) nb = target;
   if (nb < 1) nb = 1;
   return (int)nb;
@@ -876,6 +940,104 @@ void launch_sketch_dense(const void* A, int ta, int64_t lda, int64_t m, int64_t 
 }
 
 int finish_nblk(int64_t m) { return (int)((m + 15) / 16); }
+
+// ---- grouped passes (many matrices of one shape per launch) ----------------
+
+namespace {
+
+Args to_args(const ColPass& c) {
+  Args a;
+  a.A = c.A;
+  a.lda = c.lda;
+  a.m = c.m;
+  a.n = c.n;
+  a.u = c.u;
+  a.x = c.x;
+  a.s = c.s;
+  a.c = c.c;
+  a.rd = c.rd;
+  a.d2 = c.d2;
+  a.rd_out = c.rd_out;
+  a.d2_out = c.d2_out;
+  a.d2f_out = c.d2f_out;
+  a.ds_out = c.ds_out;
+  a.t_out = c.t_out;
+  a.part = c.part;
+  a.ldp = c.ldp;
+  a.red = c.red;
+  a.sc = c.sc;
+  a.done = c.done;
+  a.cg = c.cg;
+  a.cpb = (c.n + c.nblk - 1) / c.nblk;
+  return a;
+}
+
+template <typename TA, int MODE>
+int dispatch_grouped(const ColKey& k, const Args* args, const int32_t* first, int nmat, int total,
+                     const int64_t* kstart, int kit, hipStream_t st) {
+#define SK_GCASE(GG, RR)                                                                    \
+  if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                                            \
+    if (k.G == GG && k.R == RR) {                                                           \
+      constexpr int NT = threads_for(MODE, RR, Vec<TA>::V, 8);                              \
+      if constexpr (stream_mode(MODE)) {                                                    \
+        if (k.nt) {                                                                         \
+          hipLaunchKernelGGL((k_colpass_grouped<TA, double, GG, RR, MODE, NT, true>),      \
+                             dim3(total), dim3(NT), 0, st, args, first, nmat, kstart, kit); \
+          return 0;                                                                         \
+        }                                                                                   \
+      }                                                                                     \
+      hipLaunchKernelGGL((k_colpass_grouped<TA, double, GG, RR, MODE, NT, false>), dim3(total), \
+                         dim3(NT), 0, st, args, first, nmat, kstart, kit);                  \
+      return 0;                                                                             \
+    }                                                                                       \
+  }
+  SK_GCASE(16, 1) SK_GCASE(16, 2)
+  SK_GCASE(64, 1) SK_GCASE(64, 2) SK_GCASE(64, 3) SK_GCASE(64, 4)
+  SK_GCASE(64, 6) SK_GCASE(64, 8) SK_GCASE(64, 12) SK_GCASE(64, 16)
+#undef SK_GCASE
+  return -1;
+}
+
+}  // namespace
+
+size_t colpass_args_bytes() { return sizeof(Args); }
+
+int colpass_prepare(ColPass& c, void* args_out, ColKey* key) {
+  if (c.tc != SKIPM_F64 || (c.ta != SKIPM_F64 && c.ta != SKIPM_F32)) return -1;
+  if (c.mode != COL_NORMAL && c.mode != COL_DOT) return -1;
+  if (c.nblk <= 0)
+    c.nblk = c.mode == COL_DOT ? colpass_nblk_dot(c.lda, c.n, c.ta)
+                               : colpass_nblk(c.lda, c.n, c.ta, c.tc, c.mode);
+  const Shape sh = pick_shape(c.lda, vec_width(c.ta));
+  if (sh.G == 0) return -1;
+  key->ta = c.ta;
+  key->mode = c.mode;
+  key->G = sh.G;
+  key->R = sh.R;
+  key->nt = c.mode == COL_NORMAL && c.nt != 0;
+  const Args a = to_args(c);
+  memcpy(args_out, &a, sizeof(Args));
+  return c.nblk;
+}
+
+int launch_colpass_grouped(const ColKey& key, const void* dargs, const int32_t* dfirst, int nmat,
+                           int total_blocks, const int64_t* kstart, int j, hipStream_t st) {
+  const Args* a = (const Args*)dargs;
+  if (key.ta == SKIPM_F64)
+    return key.mode == COL_NORMAL
+               ? dispatch_grouped<double, COL_NORMAL>(key, a, dfirst, nmat, total_blocks, kstart, j,
+                                                      st)
+               : dispatch_grouped<double, COL_DOT>(key, a, dfirst, nmat, total_blocks, kstart, j, st);
+  return key.mode == COL_NORMAL
+             ? dispatch_grouped<float, COL_NORMAL>(key, a, dfirst, nmat, total_blocks, kstart, j, st)
+             : dispatch_grouped<float, COL_DOT>(key, a, dfirst, nmat, total_blocks, kstart, j, st);
+}
+
+void launch_finish_dot_grouped(const FinishDotArgs* dargs, const int32_t* dfirst, int nmat,
+                               int total_blocks, const int64_t* kstart, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_dot_grouped, dim3(total_blocks), dim3(256), 0, st, dargs, dfirst,
+                     nmat, kstart, j);
+}
 
 int launch_finish_dot(const double* part, int64_t ldp, int nblk, int64_t m, const double* dvec,
                       double* out, double* dq_out, const int32_t* done, hipStream_t st) {

@@ -173,6 +173,61 @@ struct ColPass {
 enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
 int launch_colpass(ColPass& a, hipStream_t st);
 
+// Grouped passes: the CG passes of many LPs in one launch per lane-group shape.
+// colpass_prepare fills the kernel arguments of one pass (colpass_args_bytes()
+// bytes, to be copied to the device) and the shape key; returns its
+// workgroup count, or -1 for a pass the grouped kernels do not cover (only
+// COL_NORMAL and COL_DOT over FP64 / FP32 values).  Passes launched together
+// must share the key.
+struct ColKey {
+  int ta = 0, mode = 0, G = 0, R = 0;
+  bool nt = false;
+  bool operator==(const ColKey& o) const {
+    return ta == o.ta && mode == o.mode && G == o.G && R == o.R && nt == o.nt;
+  }
+};
+size_t colpass_args_bytes();
+int colpass_prepare(ColPass& c, void* args_out, ColKey* key);
+// dargs: the argument blocks (two per matrix, for even and odd CG iterations,
+// when kstart is given: matrix i is at iteration kstart[i] + j; else one);
+// dfirst: nmat + 1 workgroup offsets (device)
+int launch_colpass_grouped(const ColKey& key, const void* dargs, const int32_t* dfirst, int nmat,
+                           int total_blocks, const int64_t* kstart, int j, hipStream_t st);
+struct FinishDotArgs {
+  const double* part;
+  int64_t ldp;
+  int nblk;
+  int64_t m;
+  const double* dvec;
+  double* out;
+  double* dq_out;
+  const int32_t* done;
+};
+// dargs: two per LP (even, odd iteration); LP i at iteration kstart[i] + j
+void launch_finish_dot_grouped(const FinishDotArgs* dargs, const int32_t* dfirst, int nmat,
+                               int total_blocks, const int64_t* kstart, int j, hipStream_t st);
+// the CG bookkeeping kernels, one workgroup per LP
+struct CgInitArgs {
+  int64_t m;
+  const double* rhs;
+  const double* zin;
+  double *r, *z, *d, *x;
+  double* sc;
+  int32_t* is;
+  double tol;
+  int max_it;
+};
+void launch_cg_init_grouped(const CgInitArgs* dargs, int nmat, hipStream_t st);
+struct CgCloseArgs {
+  const double* prz;
+  int np;
+  double* sc;
+  int32_t* is;
+};
+void launch_cg_close_grouped(const CgCloseArgs* dargs, int nmat, int64_t k, hipStream_t st);
+// out[3 i .. 3 i + 2] = (done, iterations, factorisation failure) of LP i
+void launch_cg_flags(int32_t* const* is, int nmat, int32_t* out, hipStream_t st);
+
 // A whole CG solve in one workgroup (small dense LPs): A (lda x n, element
 // type given to the launcher), D^2 (n), Q^{-1} (mp x mp), right-hand side
 // (m); the solution goes to x, the final r, z, d to r, z, d (each may be

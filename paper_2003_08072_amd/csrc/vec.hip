@@ -174,6 +174,38 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(int64_t m, const double*
   }
 }
 
+// k_cg_init for many LPs, one workgroup each (the same sums in the same order)
+__global__ __launch_bounds__(kCgThreads) void k_cg_init_grouped(const CgInitArgs* __restrict__ args) {
+  const CgInitArgs& g = args[blockIdx.x];
+  __shared__ double buf[kCgThreads / 64];
+  double rz = 0, rr = 0;
+  for (int64_t i = threadIdx.x; i < g.m; i += kCgThreads) {
+    const double ri = g.rhs[i], zi = g.zin[i];
+    g.r[i] = ri;
+    g.z[i] = zi;
+    g.d[i] = zi;
+    g.x[i] = 0;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  rz = block_sum<kCgThreads>(rz, buf);
+  rr = block_sum<kCgThreads>(rr, buf);
+  if (threadIdx.x == 0) {
+    double* sc = g.sc;
+    int32_t* is = g.is;
+    sc[S_CG_RZ] = rz;
+    sc[S_CG_RZ0] = rz;
+    sc[S_CG_RZH0] = rz;
+    sc[S_CG_TOL2] = g.tol > 0 ? g.tol * g.tol * rz : -1.0;
+    sc[S_V_RR] = rr;
+    sc[S_V_GG] = rr;
+    is[I_CG_ITERS] = 0;
+    is[I_CG_MAX] = g.max_it;
+    is[I_CG_DONE] = (g.max_it <= 0 || !(rz > 0) || rz <= sc[S_CG_TOL2]) ? 1 : 0;
+    is[I_CG_RESID] = 0;
+  }
+}
+
 // Fused CG stopped by its iteration cap after iteration k - 1: the bookkeeping
 // the next iteration's first pass would have done (rz_k, rr_k, count, done).
 __global__ __launch_bounds__(64) void k_cg_close(const double* __restrict__ prz, int np,
@@ -197,6 +229,40 @@ __global__ __launch_bounds__(64) void k_cg_close(const double* __restrict__ prz,
     sc[S_CG_RZH0 + (int)(k & 1)] = s0;
     is[I_CG_ITERS] = (int32_t)k;
     is[I_CG_DONE] = 1;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_cg_close_grouped(const CgCloseArgs* __restrict__ args,
+                                                         int64_t k) {
+  const CgCloseArgs& g = args[blockIdx.x];
+  if (g.is[I_CG_DONE]) return;
+  const int lane = threadIdx.x;
+  double s0 = 0, s1 = 0;
+  for (int p = lane; p < g.np; p += 64) {
+    s0 += g.prz[2 * p];
+    s1 += g.prz[2 * p + 1];
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+  }
+  if (lane == 0) {
+    g.sc[S_CG_RZ] = s0;
+    g.sc[S_V_RR] = s1;
+    g.sc[S_CG_RZH0 + (int)(k & 1)] = s0;
+    g.is[I_CG_ITERS] = (int32_t)k;
+    g.is[I_CG_DONE] = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cg_flags(int32_t* const* __restrict__ is, int nmat,
+                                                  int32_t* __restrict__ out) {
+  for (int i = threadIdx.x; i < nmat; i += 256) {
+    const int32_t* p = is[i];
+    out[3 * i] = p[I_CG_DONE];
+    out[3 * i + 1] = p[I_CG_ITERS];
+    out[3 * i + 2] = p[I_FACT_FAIL];
   }
 }
 
@@ -667,6 +733,19 @@ void launch_cg_init(int64_t m, const double* p, const double* z, double* r, doub
 void launch_cg_close(const double* prz, int np, int64_t k, double* sc, int32_t* is,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_cg_close, dim3(1), dim3(64), 0, st, prz, np, k, sc, is);
+}
+
+void launch_cg_init_grouped(const CgInitArgs* dargs, int nmat, hipStream_t st) {
+  if (nmat > 0)
+    hipLaunchKernelGGL(k_cg_init_grouped, dim3(nmat), dim3(kCgThreads), 0, st, dargs);
+}
+
+void launch_cg_close_grouped(const CgCloseArgs* dargs, int nmat, int64_t k, hipStream_t st) {
+  if (nmat > 0) hipLaunchKernelGGL(k_cg_close_grouped, dim3(nmat), dim3(64), 0, st, dargs, k);
+}
+
+void launch_cg_flags(int32_t* const* is, int nmat, int32_t* out, hipStream_t st) {
+  if (nmat > 0) hipLaunchKernelGGL(k_cg_flags, dim3(1), dim3(256), 0, st, is, nmat, out);
 }
 
 void launch_prologue_finalize(int64_t m, const double* rp, const double* b, const double* y,

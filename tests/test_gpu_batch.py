@@ -184,3 +184,62 @@ def test_server_on_serving_trace_requests(torch, sk):
         assert rq.result.rd_norm <= 1e-8 * np.linalg.norm(lp.c)
         same(r1, rq.result)
         assert np.array_equal(x2.cpu().numpy(), x1)
+
+
+def test_batch_with_a_rank_lost_lp(torch, sk):
+    """A batch holding an LP whose sketch loses rank at every salt (a zero row
+    of A): it ends with SKIPM_ERANK after its fresh sketches and shifts, the
+    same result as alone, and the other LPs of the batch are unaffected."""
+    rng = np.random.default_rng(77)
+    bad = dense_planted(24, 600, rng=rng)
+    A = bad.A.copy()
+    A[5] = 0.0
+    lps = [dense_planted(40, 3000, rng=np.random.default_rng(3), eps_gap=1e-8, seed=4),
+           (A, A @ bad.x_star, A.T @ bad.y_star + bad.s_star),
+           dense_planted(90, 5000, rng=np.random.default_rng(4), a_dtype="f32", eps_gap=1e-8,
+                         seed=5)]
+    say("batch with a rank-lost LP (zero row) between two planted LPs")
+
+    def make(x):
+        if isinstance(x, tuple):
+            return sk.LP(*x, s=2, seed=3)
+        return sk.LP(x.A, x.b, x.c, a_dtype=x.a_dtype, s=2, seed=x.seed, eps_gap=x.eps_gap)
+
+    hs = [make(x) for x in lps]
+    lone = []
+    for h in hs:
+        lone.append(h.solve())
+        h.reset()
+    torch.cuda.synchronize()
+    batch = sk.solve_batch(hs, workers=3)
+    assert batch[1].status == sk.SKIPM_ERANK
+    assert batch[1].resketches >= 3 and batch[1].shifts >= 3
+    for r1, r2 in zip(lone, batch):
+        same(r1, r2)
+    check_planted(lps[0], batch[0])
+    check_planted(lps[2], batch[2])
+    for h in hs:
+        h.close()
+
+
+def test_batch_with_capped_cg(torch, sk):
+    """LPs with different CG caps in one batch (caps of 4 and 7 iterations stop
+    most of their CG solves early; max_outer 8 ends the runs): every result is
+    bitwise that of the same LP alone."""
+    lps = [dense_planted(70, 4000, rng=np.random.default_rng(40 + i), a_dtype=dt, seed=i)
+           for i, dt in enumerate(("f32", "f64", "f32"))]
+    caps = (4, 1000, 7)
+    say("batch with CG caps 4, 1000, 7 and max_outer 8")
+    hs = [sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, s=1, seed=lp.seed, max_cg=cap,
+                max_outer=8) for lp, cap in zip(lps, caps)]
+    lone = []
+    for h in hs:
+        lone.append(h.solve())
+        h.reset()
+    torch.cuda.synchronize()
+    batch = sk.solve_batch(hs, workers=2)
+    for r1, r2 in zip(lone, batch):
+        same(r1, r2)
+    assert batch[0].cg_max <= 4 and batch[2].cg_max <= 7
+    for h in hs:
+        h.close()
