@@ -338,13 +338,16 @@ int lp_device_bytes(skipm_lp_t lp, int64_t* bytes);
 int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t workers);
 
 /* Request server: a FIFO of LP solves admitted by device-memory footprint.
- * srv_create starts `slots` worker threads (each with its own non-blocking
- * stream).  A worker takes the request at the head of the queue once its
- * footprint (lp_footprint) fits in hbm_budget minus the footprints of the
- * requests running; it then creates the LP from the request's buffers, solves
- * it (lp_solve), optionally copies the final x out, and frees the LP.  Requests
- * that arrive while others run are admitted as slots and memory free up, so
- * their IPM iterations overlap on the device with those already running. */
+ * srv_create starts `slots` slot threads (each with its own non-blocking
+ * stream) and a grouped engine like lp_solve_batch's.  A slot takes the request
+ * at the head of the queue once at most `slots` requests are in flight and its
+ * footprint (lp_footprint) fits in hbm_budget minus the footprints of those in
+ * flight, and creates the LP from the request's buffers.  A dense LP with FP64
+ * CG products joins the engine: its CG iterations run in the same grouped
+ * launches as those of every other request in flight, whatever their sizes,
+ * and the slot moves on to the next admission; any other LP is solved on the
+ * slot (lp_solve).  At the end the final x is copied out if asked and the LP
+ * freed.  Every request's arithmetic is that of lp_solve alone. */
 typedef struct skipm_server_s* skipm_server_t;
 
 #define SKIPM_REQ_QUEUED  0

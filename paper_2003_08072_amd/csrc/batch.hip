@@ -10,6 +10,8 @@
 #include <string.h>
 
 #include <atomic>
+#include <functional>
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -85,61 +87,111 @@ std::vector<Group> group_by(const std::vector<ColKey>& keys, const std::vector<i
 
 constexpr int kChunk = 6;  // CG iterations between host checks of the grouped CG
 
+// One LP in the engine: its handle and result, its loop state, its prepared
+// CG arguments, and what to do when its run has ended (called on a worker
+// thread, with that worker's stream, after the engine has let go of it).
+struct Entry {
+  skipm_lp_s* lp = nullptr;
+  skipm_result* res = nullptr;
+  BatchLp b;
+  CgPrep prep;
+  std::function<void(Entry*, hipStream_t)> done;
+};
+
 class Engine {
  public:
-  Engine(skipm_lp_t* lps, skipm_result* res, std::vector<int> idx, int nthreads, int dev)
-      : lps_(lps), res_(res), idx_(std::move(idx)), nthreads_(nthreads), dev_(dev) {}
-
+  Engine(int nthreads, int dev) : nthreads_(std::max(1, nthreads)), dev_(dev) {}
   ~Engine() {
+    stop();
     if (dbuf_) (void)hipFree(dbuf_);
     if (hbuf_) (void)hipHostFree(hbuf_);
     if (hflags_) (void)hipHostFree(hflags_);
   }
 
-  int run(std::string* err) {
+  // Streams, worker threads and the executor thread.
+  int start(std::string* err) {
     if (hipSetDevice(dev_) != hipSuccess) return *err = "hipSetDevice failed", SKIPM_EDEVICE;
-    const int n = (int)idx_.size();
-    st_.assign(n, BatchLp{});
-    prep_.assign(n, CgPrep{});
-    for (int i : idx_) memset(&res_[i], 0, sizeof(res_[i]));
     ab_ = colpass_args_bytes();
-    int rc = SKIPM_OK;
-    if (hipStreamCreateWithFlags(&cg_st_, hipStreamNonBlocking) != hipSuccess) {
-      *err = "could not create the batch's streams";
+    bool ok = hipStreamCreateWithFlags(&cg_st_, hipStreamNonBlocking) == hipSuccess;
+    streams_.assign(nthreads_, nullptr);
+    for (auto& st : streams_)
+      ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+      *err = "could not create the engine's streams";
+      destroy_streams();
       return SKIPM_EDEVICE;
     }
-    streams_.assign(nthreads_, nullptr);
-    for (auto& s : streams_)
-      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-        rc = SKIPM_EDEVICE;
-        *err = "could not create the batch's streams";
-      }
-    if (rc == SKIPM_OK) {
-      outstanding_ = n;
-      for (int q = 0; q < n; ++q) tasks_.push_back({q, false});
-      std::vector<std::thread> pool;
-      for (int t = 0; t < nthreads_; ++t) pool.emplace_back([this, t] { worker(t); });
-      rc = execute();
-      {
-        std::lock_guard<std::mutex> g(mu_);
-        stop_ = true;
-      }
-      cv_.notify_all();
-      for (auto& th : pool) th.join();
-      if (rc == SKIPM_OK && fatal_ != SKIPM_OK) rc = fatal_;
-      *err = rc == SKIPM_OK ? "" : (fatal_ != SKIPM_OK ? fatal_msg_ : skipm_last_error());
+    for (int t = 0; t < nthreads_; ++t) pool_.emplace_back([this, t] { worker(t); });
+    exec_ = std::thread([this] { executor(); });
+    started_ = true;
+    return SKIPM_OK;
+  }
+
+  // Queue an LP from its current iterate (thread-safe); e lives until e->done.
+  void add(Entry* e) {
+    memset(e->res, 0, sizeof(*e->res));
+    e->b = BatchLp{};
+    std::lock_guard<std::mutex> g(mu_);
+    ++outstanding_;
+    live_.push_back(e);
+    tasks_.push_back({e, false});
+    cv_.notify_all();
+  }
+
+  // Wait for every queued LP, then end the threads.  After a fatal error the
+  // LPs still in the engine end with that status.
+  void stop() {
+    if (!started_) return;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stop_ = true;
     }
-    for (auto& s : streams_)
-      if (s) (void)hipStreamDestroy(s);
-    (void)hipStreamDestroy(cg_st_);
-    return rc;
+    cv_.notify_all();
+    if (exec_.joinable()) exec_.join();
+    for (auto& th : pool_) th.join();
+    pool_.clear();
+    std::vector<Entry*> left;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      left.swap(live_);
+      outstanding_ = 0;
+    }
+    for (Entry* e : left) {
+      e->res->status = fatal_;
+      e->b.rc = fatal_;
+      e->b.active = false;
+      if (e->done) e->done(e, cg_st_);
+    }
+    destroy_streams();
+    started_ = false;
+  }
+
+  int fatal(std::string* msg) {
+    std::lock_guard<std::mutex> g(mu_);
+    if (msg) *msg = fatal_msg_;
+    return fatal_;
   }
 
  private:
   struct Task {
-    int q;          // position in idx_
+    Entry* e;
     bool after_cg;  // run the end of the iteration first
   };
+
+  void destroy_streams() {
+    for (auto& st : streams_)
+      if (st) (void)hipStreamDestroy(st);
+    streams_.clear();
+    if (cg_st_) (void)hipStreamDestroy(cg_st_);
+    cg_st_ = nullptr;
+  }
+
+  void set_fatal(int rc, const std::string& msg) {
+    if (fatal_ == SKIPM_OK) {
+      fatal_ = rc;
+      fatal_msg_ = msg;
+    }
+  }
 
   void worker(int t) {
     (void)hipSetDevice(dev_);
@@ -148,124 +200,146 @@ class Engine {
       Task task;
       {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [&] { return stop_ || !tasks_.empty(); });
-        if (tasks_.empty()) return;
+        cv_.wait(lk, [&] {
+          return fatal_ != SKIPM_OK || !tasks_.empty() || (stop_ && outstanding_ == 0);
+        });
+        if (fatal_ != SKIPM_OK || tasks_.empty()) return;
         task = tasks_.front();
         tasks_.pop_front();
       }
-      skipm_lp_s* lp = lps_[idx_[task.q]];
-      skipm_result* res = &res_[idx_[task.q]];
-      BatchLp* b = &st_[task.q];
+      Entry* e = task.e;
       if (task.after_cg) {
-        batch_phase_b(lp, res, b, s);
+        batch_phase_b(e->lp, e->res, &e->b, s);
         (void)hipStreamSynchronize(s);
       }
-      if (b->active) {
-        batch_phase_a(lp, res, b, s);
+      if (e->b.active) {
+        batch_phase_a(e->lp, e->res, &e->b, s);
         (void)hipStreamSynchronize(s);
       }
-      std::lock_guard<std::mutex> g(mu_);
-      if (b->rc != SKIPM_OK && fatal_ == SKIPM_OK) {
-        fatal_ = b->rc;
-        fatal_msg_ = b->err;
+      bool finished = false;
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        if (e->b.rc != SKIPM_OK) set_fatal(e->b.rc, e->b.err);
+        if (!e->b.active) {
+          finished = true;
+          live_.erase(std::find(live_.begin(), live_.end(), e));
+        } else if (e->b.grouped) {
+          ready_.push_back(e);
+        } else {
+          tasks_.push_back({e, true});  // its CG ran in one workgroup
+        }
       }
-      if (!b->active) {
+      if (finished && e->done) e->done(e, s);
+      if (finished) {
+        std::lock_guard<std::mutex> g(mu_);
         --outstanding_;
-      } else if (b->grouped) {
-        ready_.push_back(task.q);
-      } else {
-        tasks_.push_back({task.q, true});  // its CG ran in one workgroup
       }
       cv_.notify_all();
     }
   }
 
   // The executor: the grouped CG of the LPs that are ready, chunk by chunk.
-  int execute() {
-    std::vector<int> in_cg;        // positions in idx_
-    std::vector<int64_t> kstart;   // their next CG iteration
+  void executor() {
+    (void)hipSetDevice(dev_);
+    std::vector<Entry*> in_cg;    // LPs in the grouped CG
+    std::vector<int64_t> kstart;  // their next CG iteration
     for (;;) {
-      std::vector<int> fresh;
+      std::vector<Entry*> fresh;
       {
         std::unique_lock<std::mutex> lk(mu_);
         if (in_cg.empty())
-          cv_.wait(lk, [&] { return !ready_.empty() || outstanding_ == 0 || fatal_ != SKIPM_OK; });
-        if (fatal_ != SKIPM_OK) return fatal_;
-        if (in_cg.empty() && ready_.empty() && outstanding_ == 0) return SKIPM_OK;
+          cv_.wait(lk, [&] {
+            return !ready_.empty() || fatal_ != SKIPM_OK || (stop_ && outstanding_ == 0);
+          });
+        if (fatal_ != SKIPM_OK) return;
+        if (in_cg.empty() && ready_.empty()) {
+          if (stop_ && outstanding_ == 0) return;
+          continue;
+        }
         fresh.assign(ready_.begin(), ready_.end());
         ready_.clear();
       }
-      if (!fresh.empty()) {
-        for (int q : fresh) SK_TRY(prepare(q));
-        // CG set-up of the newcomers: z_0 = Q^{-1} p, then r, z, d, x and the
-        // stopping threshold
-        SK_TRY(stage(fresh, nullptr, true));
-        for (auto& g : gq_)
-          if (launch_colpass_grouped(g.key, dp(g.args_off), (const int32_t*)dp(g.first_off),
-                                     (int)g.members.size(), g.first.back(), nullptr, 0, cg_st_) != 0)
-            return set_error("grouped CG: no kernel for a shape"), SKIPM_EINVAL;
-        launch_cg_init_grouped((const CgInitArgs*)dp(init_off_), (int)fresh.size(), cg_st_);
-        SK_CHECK_HIP(hipGetLastError());
-        for (int q : fresh) {
-          in_cg.push_back(q);
-          kstart.push_back(0);
-        }
-        SK_CHECK_HIP(hipStreamSynchronize(cg_st_));  // the staging buffer is reused below
-      }
-      if (in_cg.empty()) continue;
-      SK_TRY(stage(in_cg, &kstart, false));
-      const int na = (int)in_cg.size();
-      const int64_t* ks = (const int64_t*)dp(kstart_off_);
-      for (int j = 0; j < kChunk; ++j) {
-        for (auto& g : gn_)
-          if (launch_colpass_grouped(g.key, dp(g.args_off), (const int32_t*)dp(g.first_off),
-                                     (int)g.members.size(), g.first.back(),
-                                     (const int64_t*)dp(g.kst_off), j, cg_st_) != 0)
-            return set_error("grouped CG: no kernel for a shape"), SKIPM_EINVAL;
-        launch_finish_dot_grouped((const FinishDotArgs*)dp(fin_off_), (const int32_t*)dp(ffirst_off_),
-                                  na, ffirst_.back(), ks, j, cg_st_);
-        for (auto& g : gd_)
-          if (launch_colpass_grouped(g.key, dp(g.args_off), (const int32_t*)dp(g.first_off),
-                                     (int)g.members.size(), g.first.back(),
-                                     (const int64_t*)dp(g.kst_off), j, cg_st_) != 0)
-            return set_error("grouped CG: no kernel for a shape"), SKIPM_EINVAL;
-      }
-      launch_cg_flags((int32_t* const*)dp(isp_off_), na, (int32_t*)dp(flags_off_), cg_st_);
-      SK_CHECK_HIP(hipGetLastError());
-      SK_CHECK_HIP(hipMemcpyAsync(hflags_, dp(flags_off_), 3 * na * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, cg_st_));
-      SK_CHECK_HIP(hipStreamSynchronize(cg_st_));
-      std::vector<int> keep;
-      std::vector<int64_t> kkeep;
-      std::vector<int> finished;
-      for (int q = 0; q < na; ++q) {
-        const int p = in_cg[q];
-        if (hflags_[3 * q]) {
-          st_[p].its = hflags_[3 * q + 1];
-          st_[p].fail = hflags_[3 * q + 2] ? 1 : 0;
-          finished.push_back(p);
-        } else {
-          keep.push_back(p);
-          kkeep.push_back(kstart[q] + kChunk);
-        }
-      }
-      in_cg.swap(keep);
-      kstart.swap(kkeep);
-      if (!finished.empty()) {
+      const int rc = step(fresh, &in_cg, &kstart);
+      if (rc != SKIPM_OK) {
         std::lock_guard<std::mutex> g(mu_);
-        for (int p : finished) tasks_.push_back({p, true});
+        set_fatal(rc, skipm_last_error());
         cv_.notify_all();
+        return;
       }
     }
   }
 
-  int prepare(int q) {
-    CgPrep& c = prep_[q];
+  // Set up the newcomers' CG, then one chunk of grouped iterations for all
+  // LPs in the CG; those done go back to the workers.
+  int step(const std::vector<Entry*>& fresh, std::vector<Entry*>* in_cg,
+           std::vector<int64_t>* kstart) {
+    if (!fresh.empty()) {
+      for (Entry* e : fresh) SK_TRY(prepare(e));
+      // z_0 = Q^{-1} p, then r, z, d, x and the stopping threshold
+      SK_TRY(stage(fresh, nullptr, true));
+      for (auto& g : gq_)
+        if (launch_colpass_grouped(g.key, dp(g.args_off), (const int32_t*)dp(g.first_off),
+                                   (int)g.members.size(), g.first.back(), nullptr, 0, cg_st_) != 0)
+          return set_error("grouped CG: no kernel for a shape"), SKIPM_EINVAL;
+      launch_cg_init_grouped((const CgInitArgs*)dp(init_off_), (int)fresh.size(), cg_st_);
+      SK_CHECK_HIP(hipGetLastError());
+      for (Entry* e : fresh) {
+        in_cg->push_back(e);
+        kstart->push_back(0);
+      }
+      SK_CHECK_HIP(hipStreamSynchronize(cg_st_));  // the staging buffer is reused below
+    }
+    if (in_cg->empty()) return SKIPM_OK;
+    SK_TRY(stage(*in_cg, kstart, false));
+    const int na = (int)in_cg->size();
+    const int64_t* ks = (const int64_t*)dp(kstart_off_);
+    for (int j = 0; j < kChunk; ++j) {
+      for (auto* G : {&gn_, &gd_}) {
+        if (G == &gd_)
+          launch_finish_dot_grouped((const FinishDotArgs*)dp(fin_off_),
+                                    (const int32_t*)dp(ffirst_off_), na, ffirst_.back(), ks, j,
+                                    cg_st_);
+        for (auto& g : *G)
+          if (launch_colpass_grouped(g.key, dp(g.args_off), (const int32_t*)dp(g.first_off),
+                                     (int)g.members.size(), g.first.back(),
+                                     (const int64_t*)dp(g.kst_off), j, cg_st_) != 0)
+            return set_error("grouped CG: no kernel for a shape"), SKIPM_EINVAL;
+      }
+    }
+    launch_cg_flags((int32_t* const*)dp(isp_off_), na, (int32_t*)dp(flags_off_), cg_st_);
+    SK_CHECK_HIP(hipGetLastError());
+    SK_CHECK_HIP(hipMemcpyAsync(hflags_, dp(flags_off_), 3 * na * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, cg_st_));
+    SK_CHECK_HIP(hipStreamSynchronize(cg_st_));
+    std::vector<Entry*> keep, finished;
+    std::vector<int64_t> kkeep;
+    for (int q = 0; q < na; ++q) {
+      Entry* e = (*in_cg)[q];
+      if (hflags_[3 * q]) {
+        e->b.its = hflags_[3 * q + 1];
+        e->b.fail = hflags_[3 * q + 2] ? 1 : 0;
+        finished.push_back(e);
+      } else {
+        keep.push_back(e);
+        kkeep.push_back((*kstart)[q] + kChunk);
+      }
+    }
+    in_cg->swap(keep);
+    kstart->swap(kkeep);
+    if (!finished.empty()) {
+      std::lock_guard<std::mutex> g(mu_);
+      for (Entry* e : finished) tasks_.push_back({e, true});
+      cv_.notify_all();
+    }
+    return SKIPM_OK;
+  }
+
+  int prepare(Entry* e) {
+    CgPrep& c = e->prep;
     if (c.ready) return SKIPM_OK;
-    skipm_lp_s* lp = lps_[idx_[q]];
     ColPass nrm[2], cls[2], qin;
     CgCloseArgs close;
-    batch_cg_passes(lp, nrm, c.fin, cls, &qin, &c.init, &close);
+    batch_cg_passes(e->lp, nrm, c.fin, cls, &qin, &c.init, &close);
     c.a_n.assign(2 * ab_, 0);
     c.a_c.assign(2 * ab_, 0);
     c.a_q.assign(ab_, 0);
@@ -278,8 +352,8 @@ class Engine {
     c.nb_q = colpass_prepare(qin, &c.a_q[0], &c.kd);
     if (c.nb_n < 0 || c.nb_c < 0 || c.nb_q < 0 || !(kk == c.kd))
       return set_error("grouped CG: pass not covered"), SKIPM_EINVAL;
-    c.fnb = finish_nblk(lp->m);
-    c.is = lp->is;
+    c.fnb = finish_nblk(e->lp->m);
+    c.is = e->lp->is;
     c.ready = true;
     return SKIPM_OK;
   }
@@ -287,15 +361,15 @@ class Engine {
   void* dp(size_t o) { return (void*)(dbuf_ + o); }
 
   // Work lists and arguments of the LPs `list` on the device (on cg_st_): the
-  // CG set-up passes (init) or the three passes of an iteration with their
-  // iteration offsets.  Callers have synchronised cg_st_ since its last use
-  // of the staging buffers.
-  int stage(const std::vector<int>& list, const std::vector<int64_t>* kstart, bool init) {
+  // CG set-up pass (init) or the three passes of an iteration with each LP's
+  // iteration offset.  Callers have synchronised cg_st_ since its last use of
+  // the staging buffers.
+  int stage(const std::vector<Entry*>& list, const std::vector<int64_t>* kstart, bool init) {
     const int na = (int)list.size();
     std::vector<ColKey> kn(na), kd(na);
     std::vector<int> bn(na), bc(na), bq(na);
     for (int q = 0; q < na; ++q) {
-      const CgPrep& c = prep_[list[q]];
+      const CgPrep& c = list[q]->prep;
       kn[q] = c.kn;
       kd[q] = c.kd;
       bn[q] = c.nb_n;
@@ -309,7 +383,6 @@ class Engine {
       off += bytes;
       return o;
     };
-    std::vector<int64_t> kst_n, kst_d;
     if (init) {
       gq_ = group_by(kd, bq);
       for (auto& g : gq_) {
@@ -327,7 +400,7 @@ class Engine {
           g.kst_off = take(g.members.size() * sizeof(int64_t));
         }
       ffirst_.assign(na + 1, 0);
-      for (int q = 0; q < na; ++q) ffirst_[q + 1] = ffirst_[q] + prep_[list[q]].fnb;
+      for (int q = 0; q < na; ++q) ffirst_[q + 1] = ffirst_[q] + list[q]->prep.fnb;
       fin_off_ = take(2 * na * sizeof(FinishDotArgs));
       ffirst_off_ = take((na + 1) * sizeof(int32_t));
       kstart_off_ = take(na * sizeof(int64_t));
@@ -339,17 +412,17 @@ class Engine {
     if (init) {
       for (auto& g : gq_) {
         for (size_t q = 0; q < g.members.size(); ++q)
-          put(g.args_off + q * ab_, prep_[list[g.members[q]]].a_q.data(), ab_);
+          put(g.args_off + q * ab_, list[g.members[q]]->prep.a_q.data(), ab_);
         put(g.first_off, g.first.data(), g.first.size() * sizeof(int32_t));
       }
       for (int q = 0; q < na; ++q)
-        put(init_off_ + q * sizeof(CgInitArgs), &prep_[list[q]].init, sizeof(CgInitArgs));
+        put(init_off_ + q * sizeof(CgInitArgs), &list[q]->prep.init, sizeof(CgInitArgs));
     } else {
       for (auto* G : {&gn_, &gd_})
         for (auto& g : *G) {
           const bool product = G == &gn_;
           for (size_t q = 0; q < g.members.size(); ++q) {
-            const CgPrep& c = prep_[list[g.members[q]]];
+            const CgPrep& c = list[g.members[q]]->prep;
             put(g.args_off + 2 * q * ab_, (product ? c.a_n : c.a_c).data(), 2 * ab_);
             const int64_t k0 = (*kstart)[g.members[q]];
             put(g.kst_off + q * sizeof(int64_t), &k0, sizeof(int64_t));
@@ -357,7 +430,7 @@ class Engine {
           put(g.first_off, g.first.data(), g.first.size() * sizeof(int32_t));
         }
       for (int q = 0; q < na; ++q) {
-        const CgPrep& c = prep_[list[q]];
+        const CgPrep& c = list[q]->prep;
         put(fin_off_ + 2 * q * sizeof(FinishDotArgs), c.fin, 2 * sizeof(FinishDotArgs));
         put(kstart_off_ + q * sizeof(int64_t), &(*kstart)[q], sizeof(int64_t));
         put(isp_off_ + q * sizeof(int32_t*), &c.is, sizeof(int32_t*));
@@ -391,25 +464,24 @@ class Engine {
     return SKIPM_OK;
   }
 
-  skipm_lp_t* lps_;
-  skipm_result* res_;
-  std::vector<int> idx_;
   int nthreads_, dev_;
-  std::vector<BatchLp> st_;
-  std::vector<CgPrep> prep_;
+  bool started_ = false;
   size_t ab_ = 0;
   hipStream_t cg_st_ = nullptr;
   std::vector<hipStream_t> streams_;
-  // shared between the executor and the workers
+  std::vector<std::thread> pool_;
+  std::thread exec_;
+  // shared between the executor, the workers and add()
   std::mutex mu_;
   std::condition_variable cv_;
   std::deque<Task> tasks_;
-  std::deque<int> ready_;
+  std::deque<Entry*> ready_;
+  std::vector<Entry*> live_;
   int outstanding_ = 0;
   bool stop_ = false;
   int fatal_ = SKIPM_OK;
   std::string fatal_msg_;
-  // staged work lists
+  // staged work lists (executor only)
   std::vector<Group> gn_, gd_, gq_;
   std::vector<int32_t> ffirst_;
   size_t fin_off_ = 0, ffirst_off_ = 0, kstart_off_ = 0, init_off_ = 0, isp_off_ = 0,
@@ -448,9 +520,17 @@ int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t wo
   std::thread grouped_thread;
   if (!grouped_idx.empty()) {
     grouped_thread = std::thread([&] {
-      Engine eng(lps, res, grouped_idx, std::max(1, std::min<int>(nw, (int)grouped_idx.size())),
-                 dev);
-      grc = eng.run(&gerr);
+      Engine eng(std::min<int>(nw, (int)grouped_idx.size()), dev);
+      grc = eng.start(&gerr);
+      if (grc != SKIPM_OK) return;
+      std::vector<Entry> entries(grouped_idx.size());
+      for (size_t q = 0; q < grouped_idx.size(); ++q) {
+        entries[q].lp = lps[grouped_idx[q]];
+        entries[q].res = &res[grouped_idx[q]];
+        eng.add(&entries[q]);
+      }
+      eng.stop();  // waits for every LP
+      grc = eng.fatal(&gerr);
     });
   }
   const int nsingle = std::min<int>(nw, (int)single_idx.size());
@@ -515,6 +595,8 @@ struct skipm_server_s {
     double* x_out = nullptr;
     hipEvent_t ready = nullptr;  // recorded on the producer stream at submit
     skipm_request_info info{};
+    skipm_result res{};          // filled by the engine while the request runs
+    Entry entry;                 // the request's place in the grouped engine
   };
   int device = 0;
   int64_t budget = 0;
@@ -529,6 +611,7 @@ struct skipm_server_s {
   std::deque<Req*> queue;            // FIFO of admitted-later requests
   std::map<uint64_t, Req*> reqs;     // every request by ticket
   std::vector<std::thread> workers;
+  Engine* engine = nullptr;          // the grouped CG of the dense requests in flight
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -542,33 +625,44 @@ struct skipm_server_s {
     int32_t rc = SKIPM_OK;
     int64_t device_bytes = 0;
   };
-  void run(Req* r, hipStream_t st, Outcome* out);
   void worker_main();
+  void finish(Req* r, skipm_lp_t lp, const Outcome& oc0, hipStream_t st);
 };
 
-// Runs one request.  The outcome goes to *out (a copy private to this
-// worker); the caller publishes it into r->info under the lock, so srv_poll
-// never sees a half-written result.
-void skipm_server_s::run(Req* r, hipStream_t st, Outcome* out) {
-  int rc = SKIPM_OK;
-  if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess) rc = SKIPM_EDEVICE;
-  skipm_lp_t lp = nullptr;
-  if (rc == SKIPM_OK) rc = lp_create(&lp, &r->prob, &r->prm, st);
-  if (rc == SKIPM_OK) {
-    rc = lp_solve(lp, &out->res, st);
-    if (rc == SKIPM_ENOTCONV || rc == SKIPM_ESTALL || rc == SKIPM_ERANK || rc == SKIPM_ENAN)
-      rc = SKIPM_OK;  // an outcome of the LP, in res.status
-    if (rc == SKIPM_OK && r->x_out) rc = lp_get_iterate(lp, r->x_out, nullptr, nullptr, st);
+// The end of a request: copy x out, count the device bytes, free the LP, then
+// publish the outcome into r->info under the lock (srv_poll never sees a
+// half-written result) and release its slot and footprint.
+void skipm_server_s::finish(Req* r, skipm_lp_t lp, const Outcome& oc0, hipStream_t st) {
+  Outcome oc = oc0;
+  if (lp) {
+    if (oc.rc == SKIPM_OK && r->x_out) oc.rc = lp_get_iterate(lp, r->x_out, nullptr, nullptr, st);
     int64_t held = 0;
     lp_device_bytes(lp, &held);
-    out->device_bytes = held;
-  } else {
-    out->res.status = rc;
+    oc.device_bytes = held;
+    lp_destroy(lp);
   }
-  if (lp) lp_destroy(lp);
-  out->rc = rc;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    r->info.res = oc.res;
+    r->info.rc = oc.rc;
+    r->info.device_bytes = oc.device_bytes;
+    in_use -= r->info.footprint;
+    --running;
+    ++completed;
+    r->info.t_done = now();
+    r->info.state = SKIPM_REQ_DONE;
+    if (r->ready) {
+      (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
+    }
+  }
+  work_cv.notify_all();
+  done_cv.notify_all();
 }
 
+// A slot: admit the request at the head of the queue once it fits, create its
+// LP; a dense LP with FP64 CG products joins the grouped engine (and the slot
+// is free for the next admission at once), any other is solved here.
 void skipm_server_s::worker_main() {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
@@ -586,28 +680,34 @@ void skipm_server_s::worker_main() {
     r->info.t_start = now();
     lk.unlock();
     Outcome oc;
-    if (have_stream) {
-      run(r, st, &oc);
-    } else {
-      oc.rc = SKIPM_EDEVICE;
-      oc.res.status = SKIPM_EDEVICE;
+    skipm_lp_t lp = nullptr;
+    int rc = have_stream ? SKIPM_OK : SKIPM_EDEVICE;
+    if (rc == SKIPM_OK && r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess)
+      rc = SKIPM_EDEVICE;
+    if (rc == SKIPM_OK) rc = lp_create(&lp, &r->prob, &r->prm, st);
+    if (rc != SKIPM_OK) {
+      oc.rc = rc;
+      oc.res.status = rc;
+      finish(r, nullptr, oc, st);
+      continue;
     }
-    lk.lock();
-    r->info.res = oc.res;
-    r->info.rc = oc.rc;
-    r->info.device_bytes = oc.device_bytes;
-    in_use -= r->info.footprint;
-    --running;
-    ++completed;
-    r->info.t_done = now();
-    r->info.state = SKIPM_REQ_DONE;
-    if (r->ready) {
-      (void)hipEventDestroy(r->ready);
-      r->ready = nullptr;
+    if (engine && batch_groupable(lp)) {
+      r->entry.lp = lp;
+      r->entry.res = &r->res;
+      r->entry.done = [this, r](Entry* e, hipStream_t s) {
+        Outcome o;
+        o.res = *e->res;
+        o.rc = e->b.rc;
+        finish(r, e->lp, o, s);
+      };
+      engine->add(&r->entry);
+      continue;
     }
-    lk.unlock();
-    work_cv.notify_all();
-    done_cv.notify_all();
+    rc = lp_solve(lp, &oc.res, st);
+    if (rc == SKIPM_ENOTCONV || rc == SKIPM_ESTALL || rc == SKIPM_ERANK || rc == SKIPM_ENAN)
+      rc = SKIPM_OK;  // an outcome of the LP, in res.status
+    oc.rc = rc;
+    finish(r, lp, oc, st);
   }
   if (have_stream) (void)hipStreamDestroy(st);
 }
@@ -626,6 +726,13 @@ int srv_create(skipm_server_t* out, int64_t hbm_budget, int32_t slots) {
   }
   s->budget = hbm_budget;
   s->slots = slots;
+  s->engine = new Engine(std::min(slots, 16), s->device);
+  std::string err;
+  if (s->engine->start(&err) != SKIPM_OK) {
+    delete s->engine;
+    delete s;
+    return set_error(err), SKIPM_EDEVICE;
+  }
   for (int i = 0; i < slots; ++i) s->workers.emplace_back([s] { s->worker_main(); });
   *out = s;
   return SKIPM_OK;
@@ -715,6 +822,11 @@ int srv_destroy(skipm_server_t srv) {
   }
   srv->work_cv.notify_all();
   for (auto& th : srv->workers) th.join();
+  if (srv->engine) {
+    srv->engine->stop();  // the dense requests still in the grouped engine
+    delete srv->engine;
+    srv->engine = nullptr;
+  }
   for (auto& kv : srv->reqs) {
     if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete kv.second;
