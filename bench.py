@@ -31,7 +31,7 @@ INFINITY_CACHE_BYTES = 256 << 20
 # FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 1.9999, the factor a
 # 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
 # current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
-MEASURED_TRAFFIC = {(1, "mixed"): 202_016_083, (1, "fp64"): 406_259_962}
+MEASURED_TRAFFIC = {(1, "mixed"): 202_012_349, (1, "fp64"): 406_341_296}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 
@@ -83,10 +83,13 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=25.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
-    ap.add_argument("--probe", choices=["matvec", "copy"], default=None,
+    ap.add_argument("--probe", choices=["matvec", "copy", "hbm", "cold"], default=None,
                     help="profiling helpers: 'matvec' runs one IPM step then only the fused "
                          "normal matvec; 'copy' runs a plain device copy of known size (the "
-                         "calibration for HBM byte counters)")
+                         "calibration for HBM byte counters); 'hbm' the low-precision product "
+                         "over a copy larger than the Infinity Cache; 'cold' alternates 512 MB "
+                         "of unrelated traffic (writes, then reads only) with single products, "
+                         "then products back to back")
     return ap.parse_args()
 
 
@@ -104,6 +107,11 @@ def run_probe(args):
         return
     import paper_2003_08072_amd as sk
     from lpgen import config_lp
+    if args.probe == "hbm":
+        pr = "mixed" if args.precision not in ("mixed", "bf16") else args.precision
+        r = hbm_product(sk, torch, pr, reps=args.matvec_reps)
+        print(json.dumps({"probe": "hbm", **r}), flush=True)
+        return
     lp = config_lp(args.config)
     prec = {"mixed": sk.SKIPM_PREC_MIXED, "bf16": sk.SKIPM_PREC_BF16}.get(args.precision,
                                                                         sk.SKIPM_PREC_FP64)
@@ -111,6 +119,18 @@ def run_probe(args):
                eps_gap=lp.eps_gap, precision=prec) as h:
         h.step()
         u = torch.randn(lp.m, dtype=torch.float64, device="cuda")
+        if args.probe == "cold":
+            # five products after a 512 MB in-place add (dirty lines), five after
+            # a 512 MB sum (clean lines)
+            flush = torch.zeros(512 << 20, dtype=torch.uint8, device="cuda")
+            for _ in range(5):
+                flush.add_(1)
+                h.normal_matvec(u, reps=1)
+            for _ in range(5):
+                flush.view(torch.float32).sum()
+                h.normal_matvec(u, reps=1)
+            torch.cuda.synchronize()
+            del flush
         h.normal_matvec(u, reps=args.matvec_reps)
         torch.cuda.synchronize()
     print(json.dumps({"probe": "matvec", "config": args.config, "precision": args.precision,
@@ -221,14 +241,22 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
     mv_ms = h.normal_matvec_timed(u, reps=args.matvec_reps)
     mv_bytes = matvec_bytes(lp, precision)
     # cold: one product right after 512 MB of unrelated traffic (twice the
-    # 256 MB Infinity Cache), so A cannot be served from the memory-side cache
+    # 256 MB Infinity Cache), so A cannot be served from the memory-side cache.
+    # The traffic either writes (an in-place add: the cache is left full of
+    # dirty lines that the product's reads must write back) or only reads (a
+    # sum: clean lines)
     flush = torch.zeros(512 << 20, dtype=torch.uint8, device="cuda")
-    cold = []
+    cold, cold_clean = [], []
     for _ in range(5):
         flush.add_(1)
         cold.append(h.normal_matvec_timed(u, reps=1))
-    del flush
+    flush_f = flush.view(torch.float32)
+    for _ in range(5):
+        flush_f.sum()
+        cold_clean.append(h.normal_matvec_timed(u, reps=1))
+    del flush, flush_f
     cold_ms = percentile(cold, 50)
+    cold_clean_ms = percentile(cold_clean, 50)
     h.close()
     return dict(
         precision=precision, s=s_nnz, ok=bool(ok), status=int(res.status), solves_per_s=args.steps / wall,
@@ -246,7 +274,9 @@ def run_mode(sk, torch, lp, precision, s_nnz, args, sketch=None):
         sketch_ms=ks_ms, sketch_samples=ks_n,
         matvec_gbs=mv_bytes / (kt_ms * 1e-3) / 1e9 if kt_n else None,
         matvec_b2b_ms=mv_ms, matvec_b2b_gbs=mv_bytes / (mv_ms * 1e-3) / 1e9,
-        matvec_cold_ms=cold_ms, matvec_cold_gbs=mv_bytes / (cold_ms * 1e-3) / 1e9)
+        matvec_cold_ms=cold_ms, matvec_cold_gbs=mv_bytes / (cold_ms * 1e-3) / 1e9,
+        matvec_cold_clean_ms=cold_clean_ms,
+        matvec_cold_clean_gbs=mv_bytes / (cold_clean_ms * 1e-3) / 1e9)
 
 
 def hbm_product(sk, torch, precision, m=500, reps=50):
@@ -747,6 +777,7 @@ def main():
                      "bytes_per_launch": mv["matvec_bytes"],
                      "back_to_back_gbs": mv["matvec_b2b_gbs"],
                      "cold_gbs": mv["matvec_cold_gbs"],
+                     "cold_clean_gbs": mv["matvec_cold_clean_gbs"],
                      # the product's working set against the 256 MiB Infinity Cache
                      # (memory-side cache in front of HBM): at or under it, part of
                      # the bytes can be served from the cache

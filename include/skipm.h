@@ -228,9 +228,12 @@ int sketch_hash(uint64_t seed, int64_t k, int32_t s, int64_t n, int32_t w,
                 int32_t* bucket, int8_t* sign, hipStream_t stream);
 
 /* The sketch B = A diag(d) W_k (Alg. 1 step 1 with D = diag(d)), W_k the embedding
- * of sketch_hash(prm.seed, k, prm.s, n, prm.w).  d: n (device).  B: device
- * buffer of m*w FP64, column-major with leading dimension m. */
-int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, double* B, hipStream_t stream);
+ * of sketch_hash(prm.seed, k, prm.s, n, prm.w) (or W_G of Sec. 5 with
+ * SKIPM_SKETCH_GAUSSIAN).  d: n (device).  B: device buffer of m*w values of
+ * out_dtype (SKIPM_F64, or SKIPM_F32: the FP64 sketch rounded to nearest),
+ * column-major with leading dimension m.  Another out_dtype: SKIPM_EINVAL. */
+int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, void* B, int32_t out_dtype,
+                 hipStream_t stream);
 
 /* Alg. 1 as used in Alg. 2 step (c): with D^2 = diag(d2), build Q from the
  * sketch with salt k and solve A D^2 A^T dy = p by CG preconditioned with Q,

@@ -107,7 +107,7 @@ SIGNATURES = {
     "lp_get_residuals": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "sketch_hash": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _VP, _VP,
                               _VP]),
-    "sketch_apply": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP]),
+    "sketch_apply": (C.c_int, [_VP, _VP, C.c_int64, _VP, C.c_int32, _VP]),
     "pcg_solve": (C.c_int, [_VP, _VP, _VP, C.c_int64, _VP, C.c_double, C.c_int32,
                             C.POINTER(PcgInfo), _VP]),
     "normal_matvec": (C.c_int, [_VP, _VP, _VP, C.c_int32, _VP]),
@@ -361,12 +361,14 @@ class LP:
                                           _stream(self.stream)), "lp_get_residuals")
         return rp, rd, p, g
 
-    def sketch(self, d, k):
-        """B = A diag(d) W_k as an (m, w) float64 tensor."""
+    def sketch(self, d, k, out_dtype="f64"):
+        """B = A diag(d) W_k as an (m, w) tensor of float64 ("f64") or float32 ("f32")."""
         import torch
         dd = _as_device(d, torch.float64).contiguous()
-        B = torch.empty(self.w, self.m, dtype=torch.float64, device="cuda")  # column-major m x w
+        tdt = {"f64": torch.float64, "f32": torch.float32}[out_dtype]
+        B = torch.empty(self.w, self.m, dtype=tdt, device="cuda")  # column-major m x w
         _check(self._lib.sketch_apply(self.handle, _ptr(dd), int(k), _ptr(B),
+                                      SKIPM_F64 if out_dtype == "f64" else SKIPM_F32,
                                       _stream(self.stream)), "sketch_apply")
         return B.t()
 

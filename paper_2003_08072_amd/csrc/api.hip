@@ -73,9 +73,10 @@ int validate_params(const skipm_params& p, int64_t m, int64_t n) {
   return SKIPM_OK;
 }
 
+constexpr size_t kScalarBlockBytes = S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t);
+
 int sync_read(skipm_lp_s* lp, hipStream_t st) {
-  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st));
+  SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, kScalarBlockBytes, hipMemcpyDeviceToHost, st));
   SK_CHECK_HIP(hipStreamSynchronize(st));
   return SKIPM_OK;
 }
@@ -242,6 +243,7 @@ int qinv_apply(skipm_lp_s* lp, const double* u, double* out, const int32_t* done
 }
 
 constexpr int kKtPairs = 64;
+static_assert(kKtPairs <= 64, "one bit per event pair in kt_used");
 
 // Takes an event pair for a timing sample of the product of CG iteration
 // `iter` when sampling is on; returns the pair index or -1.
@@ -252,19 +254,27 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 
 int kt_take(skipm_lp_s* lp, int iter) {
   if (lp->kt_every <= 0 || iter % lp->kt_every != 0) return -1;
-  const int q = (int)lp->kt_iter.size();
-  if (q >= kKtPairs) return -1;
+  if (lp->kt_used == ~0ull) return -1;
+  const int q = __builtin_ctzll(~lp->kt_used);
+  lp->kt_used |= 1ull << q;
   lp->kt_iter.push_back(iter);
   lp->kt_tier.push_back(lp->fmt == SKIPM_CSR ? SKIPM_TIER_FP64 : lp->tier);
+  lp->kt_pair.push_back(q);
   return q;
+}
+
+void kt_drop_last(skipm_lp_s* lp) {
+  lp->kt_used &= ~(1ull << lp->kt_pair.back());
+  lp->kt_iter.pop_back();
+  lp->kt_tier.pop_back();
+  lp->kt_pair.pop_back();
 }
 
 // Sparse product (three kernels): events recorded on the stream around them.
 int kt_begin(skipm_lp_s* lp, int iter, hipStream_t st) {
   const int q = kt_take(lp, iter);
   if (q >= 0 && hipEventRecord(lp->kt_ev[2 * q], st) != hipSuccess) {
-    lp->kt_iter.pop_back();
-    lp->kt_tier.pop_back();
+    kt_drop_last(lp);
     return -1;
   }
   return q;
@@ -274,22 +284,34 @@ void kt_end(skipm_lp_s* lp, int q, hipStream_t st) {
   if (q >= 0) (void)hipEventRecord(lp->kt_ev[2 * q + 1], st);  // a failed stamp drops the sample
 }
 
-// After a host synchronisation: keep the samples of products that ran (CG
-// iteration index below the number of iterations the CG executed; later ones
-// were skipped by the done flag).
-void kt_harvest(skipm_lp_s* lp, int executed) {
+// At a CG check: `executed` CG iterations have run by the snapshot the host
+// read.  Samples of earlier iterations are taken; later ones stay pending
+// (their products may still be queued) unless the CG is over (`final`), when
+// they were skipped by the done flag and are dropped.
+void kt_harvest(skipm_lp_s* lp, int executed, bool final) {
+  size_t keep = 0;
   for (size_t q = 0; q < lp->kt_iter.size(); ++q) {
-    if (lp->kt_iter[q] >= executed) continue;
+    const int pair = lp->kt_pair[q];
+    if (lp->kt_iter[q] >= executed && !final) {
+      lp->kt_iter[keep] = lp->kt_iter[q];
+      lp->kt_tier[keep] = lp->kt_tier[q];
+      lp->kt_pair[keep] = pair;
+      ++keep;
+      continue;
+    }
     float ms = 0;
-    if (hipEventElapsedTime(&ms, lp->kt_ev[2 * q], lp->kt_ev[2 * q + 1]) == hipSuccess) {
+    if (lp->kt_iter[q] < executed &&
+        hipEventElapsedTime(&ms, lp->kt_ev[2 * pair], lp->kt_ev[2 * pair + 1]) == hipSuccess) {
       lp->kt_sum_ms += ms;
       ++lp->kt_count;
       lp->kt_tier_ms[lp->kt_tier[q]] += ms;
       ++lp->kt_tier_n[lp->kt_tier[q]];
     }
+    lp->kt_used &= ~(1ull << pair);
   }
-  lp->kt_iter.clear();
-  lp->kt_tier.clear();
+  lp->kt_iter.resize(keep);
+  lp->kt_tier.resize(keep);
+  lp->kt_pair.resize(keep);
 }
 
 // The passes of a fused dense CG iteration of parity p (d_k lives in cd for
@@ -445,7 +467,44 @@ int pcg_small(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int m
   return 1;
 }
 
+// CG iterations are enqueued in chunks, each followed by an asynchronous copy
+// of the scalar block into one of two pinned snapshots.  While the host waits
+// for one snapshot, the next chunk is already queued, so the device does not
+// wait for the host's check; what it costs is the chunk queued behind the one
+// in which CG stops (its passes read the done flag and return).  So chunks
+// shrink towards the stop: the stopping quantity (r^T z, or r^T r) falls by a
+// factor c_prev / c_k over the last k - k_prev iterations, and at that rate
+// reaches c_stop after about (k - k_prev) log(c_k / c_stop) / log(c_prev / c_k)
+// more; the next chunk is half of what that leaves beyond the queued
+// iterations, between 1 and kCgChunkMax.  (CG converges faster towards the
+// end, so the recent rate, halved, rarely overshoots.)
+constexpr int kCgChunkDefault = 4, kCgChunkMax = 16;
+
+struct CgProgress {
+  int k = 0;       // CG iteration of the last snapshot read
+  double c = -1;   // its stopping quantity (negative: none yet)
+};
+
+int next_cg_chunk(const double* snap, int enq, CgProgress* last) {
+  const int32_t* hi = (const int32_t*)(snap + S_NSLOTS);
+  const int k = hi[I_CG_ITERS];
+  const bool resid = hi[I_CG_RESID] != 0;
+  const double ck = resid ? snap[S_V_RR] : snap[S_CG_RZ];
+  const double cs = snap[S_CG_TOL2];
+  const CgProgress prev = last->c < 0 ? CgProgress{0, resid ? snap[S_V_GG] : snap[S_CG_RZ0]}
+                                      : *last;
+  last->k = k;
+  last->c = ck;
+  if (!(k > prev.k && cs > 0 && ck > cs && prev.c > ck)) return kCgChunkDefault;
+  const double need = (k - prev.k) * log(ck / cs) / log(prev.c / ck);
+  const double half = 0.5 * (need - (enq - k));  // half of what lies beyond the queue
+  if (!(half < kCgChunkMax)) return kCgChunkMax;
+  return std::max(1, (int)half);
+}
+
 // CG on A D^2 A^T dy = rhs preconditioned by Q^{-1}; returns iterations in *its.
+// The snapshot the host stops on is the final state: passes after the stop
+// change nothing.
 int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max_it,
             int first_chunk, int* its, int* fact_fail, hipStream_t st) {
   {
@@ -456,28 +515,56 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   SK_TRY(qinv_apply(lp, rhs, lp->cw, nullptr, st));
   launch_cg_init(lp->m, rhs, lp->cw, lp->cr, lp->cz, lp->cd, nullptr, xsol, nullptr, 0, lp->sc,
                  lp->is, tol, max_it, 0, st);
-  int enq = 0;
-  int chunk = std::max(1, std::min(first_chunk, max_it));
   *fact_fail = 0;
-  for (;;) {
-    for (int q = 0; q < chunk && enq < max_it; ++q, ++enq)
-      SK_TRY(pcg_iteration(lp, xsol, enq, st));
-    if (enq >= max_it)  // close the capped run (the next iteration's opening pass would)
+  int enq = 0, slot = 0;
+  int queue[2], nq = 0;  // snapshots in flight, oldest first
+  bool capped[2] = {false, false};
+  auto enqueue = [&](int n) -> int {
+    for (int q = 0; q < n && enq < max_it; ++q, ++enq) SK_TRY(pcg_iteration(lp, xsol, enq, st));
+    capped[slot] = enq >= max_it;
+    if (capped[slot])  // close the capped run (the next iteration's opening pass would)
       launch_cg_close(lp->cgred + lp->cg_nf, lp->cg_nd, enq, lp->sc, lp->is, st);
-    SK_TRY(sync_read(lp, st));
-    const int32_t* hi = host_ints(lp);
-    kt_harvest(lp, hi[I_FACT_FAIL] ? 0 : hi[I_CG_ITERS]);
-    if (hi[I_FACT_FAIL]) {
-      *fact_fail = 1;
+    SK_CHECK_HIP(hipMemcpyAsync(lp->hsnap[slot], lp->sc, kScalarBlockBytes,
+                                hipMemcpyDeviceToHost, st));
+    SK_CHECK_HIP(hipEventRecord(lp->snap_ev[slot], st));
+    queue[nq++] = slot;
+    slot ^= 1;
+    return SKIPM_OK;
+  };
+  SK_TRY(enqueue(std::max(1, std::min(first_chunk, max_it))));
+  int next = std::min(kCgChunkDefault, std::max(1, first_chunk));
+  CgProgress progress;
+  for (;;) {
+    if (nq < 2 && enq < max_it) {
+      SK_TRY(enqueue(next));
+    }
+    const int look = queue[0];
+    queue[0] = queue[1];
+    --nq;
+    SK_CHECK_HIP(hipEventSynchronize(lp->snap_ev[look]));
+    const double* snap = lp->hsnap[look];
+    const int32_t* hi = (const int32_t*)(snap + S_NSLOTS);
+    const bool fail = hi[I_FACT_FAIL] != 0;
+    const bool stop = fail || hi[I_CG_DONE] || capped[look];
+    kt_harvest(lp, fail ? 0 : hi[I_CG_ITERS], stop);
+    if (stop) {
+      memcpy(lp->hsc, snap, kScalarBlockBytes);
+      *fact_fail = fail ? 1 : 0;
       *its = hi[I_CG_ITERS];
       return SKIPM_OK;
     }
-    if (hi[I_CG_DONE] || enq >= max_it) {
-      *its = hi[I_CG_ITERS];
-      return SKIPM_OK;
-    }
-    chunk = 4;
+    next = next_cg_chunk(snap, enq, &progress);
   }
+}
+
+// First chunk of a CG run: two thirds of the previous normal-equation solve's
+// iteration count, since a short first chunk costs only overlapped checks
+// while a long one enqueues passes past the stop (the counts of successive IPM
+// iterations often fall by a quarter or more).  Refinement steps after the
+// first correct only the rounding of A's copy and take few iterations: they
+// start with two.
+int first_cg_chunk(const skipm_lp_s* lp, int outer) {
+  return outer == 0 ? std::max(2, lp->prev_cg * 2 / 3) : 2;
 }
 
 // FP64 residual of the normal equations, rt = rhs - A D^2 A^T x (one FP64 pass
@@ -533,7 +620,7 @@ int pcg_refined(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int
     const double rel_target = rho0 > 0 && rho > 0 ? tol * rho0 / rho : tol;
     const double inner_tol = std::min(0.5, rel_target);
     int inner = 0;
-    const int first = std::max(2, outer == 0 ? lp->prev_cg - 1 : lp->prev_cg / 3);
+    const int first = first_cg_chunk(lp, outer);
     SK_TRY(pcg_run(lp, lp->rt, lp->dyc, tol > 0 ? inner_tol : 0.0, budget, first, &inner,
                    fact_fail, st));
     if (*fact_fail) return SKIPM_OK;
@@ -593,8 +680,7 @@ int sketch_solve(skipm_lp_s* lp, const double* dscale, int is_d2, int64_t salt,
     if (lp->tier != SKIPM_TIER_FP64) {
       SK_TRY(pcg_refined(lp, rhs, xsol, tol, max_it, its, &fail, st));
     } else {
-      const int first = std::max(2, lp->prev_cg - 1);
-      SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first, its, &fail, st));
+      SK_TRY(pcg_run(lp, rhs, xsol, tol, max_it, first_cg_chunk(lp, 0), its, &fail, st));
     }
     if (!fail) {
       rc = SKIPM_OK;
@@ -1312,6 +1398,8 @@ int lp_kernel_timing(skipm_lp_t lp, int32_t every) {
   lp->kt_every = every;
   lp->kt_iter.clear();
   lp->kt_tier.clear();
+  lp->kt_pair.clear();
+  lp->kt_used = 0;
   lp->kt_sum_ms = 0;
   lp->kt_count = 0;
   for (int t = 0; t < 3; ++t) {
@@ -1362,7 +1450,10 @@ int lp_destroy(skipm_lp_t lp) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : lp->ks_ev)
     if (e) (void)hipEventDestroy(e);
-  if (lp->hsc) (void)hipHostFree(lp->hsc);
+  for (hipEvent_t e : lp->snap_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (double* h : {lp->hsc, lp->hsnap[0], lp->hsnap[1]})
+    if (h) (void)hipHostFree(h);
   delete lp;
   return SKIPM_OK;
 }
@@ -1604,10 +1695,17 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->sc, S_NSLOTS + (I_NINTS + 1) / 2);
   lp->is = (int32_t*)(lp->sc + S_NSLOTS);
 #undef ALLOC
-  if (hipHostMalloc((void**)&lp->hsc, S_NSLOTS * sizeof(double) + I_NINTS * sizeof(int32_t)) !=
-      hipSuccess) {
-    lp_destroy(lp);
-    return set_error("hipHostMalloc failed"), SKIPM_ENOMEM;
+  for (double** h : {&lp->hsc, &lp->hsnap[0], &lp->hsnap[1]}) {
+    if (hipHostMalloc((void**)h, kScalarBlockBytes) != hipSuccess) {
+      lp_destroy(lp);
+      return set_error("hipHostMalloc failed"), SKIPM_ENOMEM;
+    }
+  }
+  for (hipEvent_t& e : lp->snap_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      lp_destroy(lp);
+      return set_error("hipEventCreate failed"), SKIPM_EDEVICE;
+    }
   }
   // zero the vectors whose padding must stay zero, then copy the problem in
   launch_fill_f64(lp->sc, 0.0, S_NSLOTS, st);
@@ -1712,11 +1810,17 @@ int sketch_hash(uint64_t seed, int64_t k, int32_t s, int64_t n, int32_t w, int32
   return SKIPM_OK;
 }
 
-int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, double* B, hipStream_t st) {
+int sketch_apply(skipm_lp_t lp, const double* d, int64_t k, void* B, int32_t out_dtype,
+                 hipStream_t st) {
+  if (out_dtype != SKIPM_F64 && out_dtype != SKIPM_F32)
+    return set_error("out_dtype must be SKIPM_F64 or SKIPM_F32"), SKIPM_EINVAL;
   if (!lp || !d || !B) return set_error("null argument"), SKIPM_EINVAL;
   SK_CHECK_HIP(hipSetDevice(lp->device));
   SK_TRY(sketch_into(lp, d, 0, k, lp->B, st));
-  launch_pad_copy_f64(B, lp->m, lp->B, lp->lda, lp->m, lp->w, st);
+  if (out_dtype == SKIPM_F64)
+    launch_pad_copy_f64((double*)B, lp->m, lp->B, lp->lda, lp->m, lp->w, st);
+  else
+    launch_pad_copy_f64_to_f32((float*)B, lp->m, lp->B, lp->lda, lp->m, lp->w, st);
   SK_CHECK_HIP(hipGetLastError());
   SK_CHECK_HIP(hipStreamSynchronize(st));
   return SKIPM_OK;

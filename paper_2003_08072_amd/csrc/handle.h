@@ -65,6 +65,10 @@ struct skipm_lp_s {
   double* sc = nullptr;
   int32_t* is = nullptr;
   double* hsc = nullptr;  // pinned: S_NSLOTS doubles then I_NINTS ints
+  // two more pinned copies of the scalar block, filled alternately by the CG's
+  // chunk checks (the host reads one while the next chunk runs)
+  double* hsnap[2] = {nullptr, nullptr};
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
   int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_A16 = 1, nblk_B = 1, nblk_vec = 1;
   int64_t k = 0;
   int64_t hashed_k = -1;
@@ -92,8 +96,10 @@ struct skipm_lp_s {
   // event pairs around every kt_every-th product, harvested at the CG's host checks
   int kt_every = 0;
   std::vector<hipEvent_t> kt_ev;  // 2 * kKtPairs events
-  std::vector<int> kt_iter;       // CG iteration of each pending pair
+  std::vector<int> kt_iter;       // CG iteration of each pending sample
   std::vector<int> kt_tier;       // precision tier of the product it brackets
+  std::vector<int> kt_pair;       // its event pair
+  uint64_t kt_used = 0;           // event pairs held by pending samples (bit per pair)
   double kt_sum_ms = 0;
   int64_t kt_count = 0;
   double kt_tier_ms[3] = {0, 0, 0};  // the same, per SKIPM_TIER_*

@@ -68,6 +68,10 @@ def test_argument_validation_without_device():
         assert lib.lp_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(p), None) == \
             sk.SKIPM_EINVAL, bad
     assert lib.sketch_hash(0, 0, 3, 10, 10, None, None, None) == sk.SKIPM_EINVAL
+    assert lib.sketch_apply(None, None, 0, None, 7, None) == sk.SKIPM_EINVAL
+    assert b"out_dtype" in lib.skipm_last_error()
+    assert lib.sketch_apply(None, None, 0, None, sk.SKIPM_F32, None) == sk.SKIPM_EINVAL
+    assert b"null" in lib.skipm_last_error()
 
 
 def _c_layouts():

@@ -127,6 +127,19 @@ def test_sketch_apply(torch, sk, m, n, w, s, dtype):
     assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
 
 
+def test_sketch_apply_f32_output(torch, sk):
+    """out_dtype SKIPM_F32: the FP64 sketch rounded to nearest, element by element."""
+    say("sketch to FP32, m=61 n=2000 w=244 s=2")
+    rng = np.random.default_rng(404)
+    lp = dense_planted(61, 2000, rng=rng)
+    d = rng.uniform(0.01, 10.0, 2000)
+    with sk.LP(lp.A, lp.b, lp.c, w=244, s=2, seed=9) as h:
+        B64 = h.sketch(d, 3).cpu().numpy()
+        B32 = h.sketch(d, 3, out_dtype="f32").cpu().numpy()
+    assert B32.dtype == np.float32
+    assert np.array_equal(B32, B64.astype(np.float32))
+
+
 # ---------------------------------------------------------------------------
 # a3/a4: preconditioned CG
 # ---------------------------------------------------------------------------
@@ -674,6 +687,19 @@ def test_sketch_at_full_size(torch, sk, cfg1):
     assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
 
 
+def test_sketch_apply_f32_output(torch, sk):
+    """out_dtype SKIPM_F32: the FP64 sketch rounded to nearest, element by element."""
+    say("sketch to FP32, m=61 n=2000 w=244 s=2")
+    rng = np.random.default_rng(404)
+    lp = dense_planted(61, 2000, rng=rng)
+    d = rng.uniform(0.01, 10.0, 2000)
+    with sk.LP(lp.A, lp.b, lp.c, w=244, s=2, seed=9) as h:
+        B64 = h.sketch(d, 3).cpu().numpy()
+        B32 = h.sketch(d, 3, out_dtype="f32").cpu().numpy()
+    assert B32.dtype == np.float32
+    assert np.array_equal(B32, B64.astype(np.float32))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_normal_product_at_full_size(torch, sk, cfg1, prec):
     """The fused product A D^2 A^T u at the bench's shape and launch
@@ -842,6 +868,19 @@ def test_csr_sketch_at_full_size(torch, sk, cfg2):
     bound = np.asarray((abs(AD) @ abs(W)).todense())
     kmax = int(np.diff(W.tocsc().indptr).max())
     assert np.all(np.abs(B - Bref) <= (kmax + 2) * EPS * bound + 1e-300)
+
+
+def test_sketch_apply_f32_output(torch, sk):
+    """out_dtype SKIPM_F32: the FP64 sketch rounded to nearest, element by element."""
+    say("sketch to FP32, m=61 n=2000 w=244 s=2")
+    rng = np.random.default_rng(404)
+    lp = dense_planted(61, 2000, rng=rng)
+    d = rng.uniform(0.01, 10.0, 2000)
+    with sk.LP(lp.A, lp.b, lp.c, w=244, s=2, seed=9) as h:
+        B64 = h.sketch(d, 3).cpu().numpy()
+        B32 = h.sketch(d, 3, out_dtype="f32").cpu().numpy()
+    assert B32.dtype == np.float32
+    assert np.array_equal(B32, B64.astype(np.float32))
 
 
 def test_csr_normal_product_at_full_size(torch, sk, cfg2):
