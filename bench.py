@@ -149,15 +149,16 @@ def matvec_bytes(lp, precision, tier=None):
 
     Dense: A once (m n values in the precision the CG reads: the tier's copy),
     D^2 once (n FP64 values), u in and the product out (m FP64 each).  CSR:
-    the column pass reads the CSC copy (row indices, values, column pointers)
-    and D^2 and writes one coefficient per column; the row pass reads the CSR
-    copy (column indices, values, row pointers) and the coefficients once."""
+    one read of the non-zeros (index and value each), of the column pointers
+    and of D^2.  (The one-pass kernel reads the non-zeros twice, once per
+    copy, and writes and re-reads one m-vector of partial sums per column
+    block: traffic above these bytes.)"""
     tier = PREC_START_TIER[precision] if tier is None else tier
     pa = min(TIER_BYTES[tier], 4 if lp.a_dtype == "f32" else 8)
     if lp.fmt == "dense":
         return lp.m * lp.n * pa + lp.n * 8 + 2 * lp.m * 8
     nnz = int(lp.A.nnz)
-    return 2 * nnz * (4 + pa) + (lp.n + 1) * 4 + (lp.m + 1) * 4 + 3 * lp.n * 8
+    return nnz * (4 + pa) + (lp.n + 1) * 4 + lp.n * 8
 
 
 def percentile(xs, q):
@@ -643,7 +644,7 @@ def run_svm(sk, torch, args):
                    "frac": (r["matvec_gbs"] / HBM_PEAK_GBS) if r["matvec_gbs"] else None,
                    "traffic": None,
                    "kernel": "k_colpass (fused normal matvec A D^2 A^T u)"
-                   if lp.fmt == "dense" else "k_csc_dot + k_csr_seg + k_csr_fold",
+                   if lp.fmt == "dense" else "k_sb_normal + k_finish_dot",
                    "avg_ms": r["matvec_ms"], "samples": r["matvec_samples"],
                    "bytes_per_launch": r["matvec_bytes"]}
         if sketch == "gaussian" and r["sketch_samples"]:
@@ -771,7 +772,7 @@ def main():
                      "unit": "GB/s", "frac": mv["matvec_gbs"] / HBM_PEAK_GBS,
                      "traffic": MEASURED_TRAFFIC.get((args.config, head["precision"])),
                      "kernel": ("k_colpass (fused normal matvec A D^2 A^T u)" if lp.fmt == "dense"
-                                else "k_csc_dot + k_csr_seg + k_csr_fold (sparse normal matvec)"),
+                                else "k_sb_normal + k_finish_dot (sparse normal matvec)"),
                      "avg_ms": mv["matvec_ms"], "samples": mv["matvec_samples"],
                      "timing": timing,
                      "bytes_per_launch": mv["matvec_bytes"],

@@ -170,12 +170,9 @@ int prologue_sparse(skipm_lp_s* lp, hipStream_t st) {
 int normal_sparse(skipm_lp_s* lp, const double* u, double scale, const double* add, double beta,
                   double* out, const int32_t* done, hipStream_t st) {
   const SparseA& A = lp->sp;
-  if (launch_csc_dot(A, COL_NORMAL, u, nullptr, nullptr, nullptr, nullptr, lp->d2, lp->cf1,
-                     nullptr, nullptr, nullptr, nullptr, nullptr, lp->sc, done, lp->nblk_csc,
-                     st) != 0)
+  if (launch_sb_normal(A, u, lp->d2, lp->part, lp->mp, done, st) != 0)
     return set_error("m too large for the sparse path"), SKIPM_EINVAL;
-  launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, done, st);
-  launch_csr_fold(A, lp->segsum, 0, scale, add, beta, out, done, st);
+  launch_finish(lp->part, lp->mp, 0, (int)A.nbk, lp->m, scale, add, beta, out, done, st);
   return SKIPM_OK;
 }
 
@@ -401,12 +398,11 @@ int pcg_iteration(skipm_lp_s* lp, double* xsol, int iter, hipStream_t st) {
     cg.is = lp->is;
     const SparseA& A = lp->sp;
     const int q = kt_begin(lp, iter, st);
-    if (launch_csc_dot(A, COL_NORMAL, lp->cd, nullptr, nullptr, nullptr, nullptr, lp->d2, lp->cf1,
-                       nullptr, nullptr, nullptr, nullptr, nullptr, lp->sc, done, lp->nblk_csc,
-                       st, &cg) != 0)
+    if (launch_sb_normal(A, lp->cd, lp->d2, lp->part, lp->mp, done, st, &cg) != 0)
       return set_error("m too large for the sparse path"), SKIPM_EINVAL;
-    launch_csr_segsum(A, lp->cf1, nullptr, lp->segsum, done, st);
-    launch_csr_fold(A, lp->segsum, 0, 1.0, nullptr, 0.0, lp->cq, done, st, dk, pdq);
+    if (launch_finish_dot(lp->part, lp->mp, (int)A.nbk, lp->m, dk, lp->cq, pdq, done, st) !=
+        lp->cg_nf)
+      return set_error("sparse CG: finish shape mismatch"), SKIPM_EINVAL;
     kt_end(lp, q, st);
   } else {
     // Three launches per iteration: the product pass opens the iteration (stop
@@ -1326,11 +1322,19 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
     add(8 * n);
     add(8 * n);
     add(16 * nseg);
+    {  // column blocks: descriptors, both keyed copies
+      const int64_t nb = sb_max_blocks(n, nnz), sl = sb_max_slots(n, nnz);
+      add(16 * nb);
+      add(4 * sl);
+      add(4 * sl);
+      add(8 * ((sl * esz + 7) / 8));
+      add(8 * ((sl * esz + 7) / 8));
+    }
     nblk_csc = csc_dot_nblk(n);
   }
   for (int i = 0; i < 8; ++i) add(8 * n);    // c x s d2 r_d dx ds v
   for (int i = 0; i < 19; ++i) add(8 * mp);  // m-vectors
-  add(8 * ((csr ? csr_fold_nblk(m) : finish_nblk(m)) +
+  add(8 * (finish_nblk(m) +
            2 * (int64_t)colpass_nblk_dot(mp, m, SKIPM_F64)));  // CG partials
   add(8 * w);
   add(8 * w);
@@ -1364,6 +1368,7 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   pe = std::max<int64_t>(pe, (int64_t)nblk_A32 * mp);
   pe = std::max<int64_t>(pe, (int64_t)nblk_A16 * mp);
   pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
+  if (csr) pe = std::max<int64_t>(pe, sb_max_blocks(n, prob->nnz) * mp);
   add(8 * pe);
   add(8 * 8 * (int64_t)std::max(std::max(std::max(nblk_Ap, nblk_vec), nblk_csc), 64));
   add(8 * S_NSLOTS);
@@ -1610,6 +1615,34 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     ALLOC(lp->cf2, n);
     ALLOC(lp->segsum, 2 * (int64_t)hnseg);
     lp->nblk_csc = csc_dot_nblk(n);
+    // column blocks of the one-pass normal product
+    {
+      std::vector<int32_t> hd;
+      const int64_t slots = sb_partition(S, &hd, st);
+      const int64_t nbk = (int64_t)hd.size() / 4;
+      if (slots < 0 || nbk < 1 || nbk > sb_max_blocks(n, nnz) || slots > sb_max_slots(n, nnz)) {
+        lp_destroy(lp);
+        return set_error("sparse block partition failed"), SKIPM_EDEVICE;
+      }
+      S.nbk = nbk;
+      int32_t* bdesc;
+      uint32_t *ck, *rk;
+      double *cv, *rv;
+      ALLOC(bdesc, 4 * nbk);
+      ALLOC(ck, slots);
+      ALLOC(rk, slots);
+      ALLOC(cv, (slots * (int64_t)esz + 7) / 8);
+      ALLOC(rv, (slots * (int64_t)esz + 7) / 8);
+      SK_CHECK_HIP(hipMemcpyAsync(bdesc, hd.data(), 4 * nbk * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, st));
+      sb_fill(&S, bdesc, ck, cv, rk, rv, bad, st);
+      SK_CHECK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      SK_CHECK_HIP(hipStreamSynchronize(st));
+      if (hbad) {
+        lp_destroy(lp);
+        return set_error("sparse block exceeds its bounds"), SKIPM_EDEVICE;
+      }
+    }
   }
   if (lp->mixed && lp->a_dtype == SKIPM_F64) ALLOC(lp->A32, lda * n);
   if (bf16) ALLOC(lp->A16, lp->lda16 * n);
@@ -1631,7 +1664,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->cz, mp);
   ALLOC(lp->cd, mp);
   ALLOC(lp->cd2, mp);
-  lp->cg_nf = csr ? csr_fold_nblk(m) : finish_nblk(m);
+  lp->cg_nf = finish_nblk(m);
   {
     // one-workgroup CG for small dense LPs; SKIPM_CG_SMALL_BYTES overrides the
     // size limit of A's CG copy (0 turns it off)
@@ -1686,6 +1719,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A32 * mp);
     pe = std::max<int64_t>(pe, (int64_t)lp->nblk_A16 * mp);
     pe = std::max<int64_t>(pe, (int64_t)colpass_nblk(mp, m, SKIPM_F64, SKIPM_F64, COL_AXPY) * mp);
+    if (csr) pe = std::max<int64_t>(pe, lp->sp.nbk * mp);
     ALLOC(lp->part, pe);
   }
   ALLOC(lp->red,

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 #include <string>
@@ -303,8 +305,34 @@ struct SparseA {
   const int32_t* segptr = nullptr;
   const int32_t* seg_start = nullptr;
   const int32_t* seg_end = nullptr;
+  // column blocks of the one-pass normal product: bdesc[4 b ..] = (first
+  // column, columns, non-zeros, first slot) of block b; its slots of two keyed
+  // copies of its non-zeros: column order (ck = local column << 16 | row, cv)
+  // and (row, column) order (rk = row << 16 | local column, rv); bits 12 and
+  // 13 of a key mark its column's (row's) first and last non-zero
+  int64_t nbk = 0;
+  const int32_t* bdesc = nullptr;
+  const uint32_t* ck = nullptr;
+  const void* cv = nullptr;
+  const uint32_t* rk = nullptr;
+  const void* rv = nullptr;
 };
 constexpr int kSeg = 512;
+// One-pass sparse normal product (column blocks, LDS coefficients).
+// sb_partition cuts the columns into blocks and lays out their slots (host
+// vector of 4 nbk block descriptors; returns the slot count, or -1 on a HIP
+// error); sb_fill (A->nbk set, bdesc on the device) writes both keyed copies
+// and records them in A; bad |= 4 if a block broke its bounds.
+int64_t sb_partition(const SparseA& A, std::vector<int32_t>* bdesc, hipStream_t st);
+void sb_fill(SparseA* A, const int32_t* bdesc, uint32_t* ck, void* cv, uint32_t* rk, void* rv,
+             int32_t* bad, hipStream_t st);
+int64_t sb_max_blocks(int64_t n, int64_t nnz);  // upper bounds: block count,
+int64_t sb_max_slots(int64_t n, int64_t nnz);   // slots of each keyed copy
+// part[b][i] (b < A.nbk, leading dimension ldp >= m) = sum over block b's
+// columns j of a_ij c_j (a_j^T u) (c null: c_j = 1).  With cg, the pass opens
+// a CG iteration as the dense product pass does (u is then d_0 at k = 0).
+int launch_sb_normal(const SparseA& A, const double* u, const double* c, double* part,
+                     int64_t ldp, const int32_t* done, hipStream_t st, const CgFuse* cg = nullptr);
 void launch_csr_check(const int32_t* rowptr, const int32_t* colidx, int64_t m, int64_t n,
                       int64_t nnz, int32_t* bad, hipStream_t st);
 void launch_build_csc(const int32_t* rowptr, const int32_t* colidx, const void* val, int vdt,

@@ -883,9 +883,67 @@ def test_sketch_apply_f32_output(torch, sk):
     assert np.array_equal(B32, B64.astype(np.float32))
 
 
+def _csr_case(m, n, dens, ones, dense_col, empty_rows, seed):
+    """Random CSR matrix with optional all-ones row 0, an empty column 7, a
+    dense column 11 and empty rows 3 and 5."""
+    rng = np.random.default_rng(seed)
+    A = sp.random(m, n, density=dens, format="lil", random_state=rng,
+                  data_rvs=rng.standard_normal)
+    if ones:
+        A[0, :] = 1.0
+    A[:, 7] = 0.0
+    if dense_col:
+        A[:, 11] = rng.standard_normal((m, 1))
+    if empty_rows:
+        A[3, :] = 0.0
+        A[5, :] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    return A
+
+
+@pytest.mark.parametrize("m,n,dens,ones,dense_col,empty_rows,vdt", [
+    (50, 30000, 0.001, True, True, False, "f32"),   # long all-ones row across many threads
+    (300, 12000, 0.3, False, True, False, "f64"),   # blocks cut by the non-zero bound
+    (37, 5000, 0.0, True, False, False, "f32"),     # the ones row alone
+    (2048, 3000, 0.01, True, True, False, "f64"),   # largest m
+    (5, 20000, 0.5, True, True, False, "f32"),      # few rows, long runs per row
+    (64, 9000, 0.02, False, False, True, "f64"),    # empty rows
+])
+def test_csr_block_product(torch, sk, m, n, dens, ones, dense_col, empty_rows, vdt):
+    """The one-pass sparse product (column blocks, coefficients in LDS, rows
+    joined by the segmented scan) against the oracle's normal matrix, element
+    by element, and bitwise equal on a second call.  D^2 = x / s comes from the
+    prologue of one IPM step (rank-deficient cases end that step with an
+    error after the prologue; the product does not need the rest)."""
+    A = _csr_case(m, n, dens, ones, dense_col, empty_rows, seed=m + n)
+    if vdt == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+    say(f"csr block product m={m} n={n} nnz={A.nnz} {vdt}")
+    rng = np.random.default_rng(n)
+    x, s = rng.uniform(0.1, 10.0, n), rng.uniform(0.1, 10.0, n)
+    b = A @ x
+    c = A.T @ rng.standard_normal(m) + s
+    u = rng.standard_normal(m)
+    with sk.LP(A, b, c, a_dtype=vdt, s=1, seed=3) as h:
+        h.set_iterate(x, np.zeros(m), s)
+        with contextlib.suppress(sk.SkipmError):
+            h.step()
+        q1 = h.normal_matvec(u).cpu().numpy()
+        q2 = h.normal_matvec(u).cpu().numpy()
+    d2 = x / s
+    ref = O.normal_matrix(A, d2) @ u
+    absA = abs(A)
+    bound = absA @ (d2 * (absA.T @ np.abs(u)))
+    kmax = max(int(np.diff(A.indptr).max()), int(np.diff(A.tocsc().indptr).max()))
+    assert np.all(np.abs(q1 - ref) <= 2 * (kmax + 2) * EPS * bound + 1e-300)
+    assert np.array_equal(q1, q2)
+
+
 def test_csr_normal_product_at_full_size(torch, sk, cfg2):
-    """The sparse product (column pass over the CSC copy, row pass over the CSR
-    segments, fold) at config 2's shape against the oracle's normal matrix."""
+    """The sparse product (one pass over column blocks of the CSC copy and
+    their row-ordered copies, then the block partials' finish) at config 2's
+    shape against the oracle's normal matrix."""
     lp, x, s = cfg2
     say("csr normal product at full size")
     rng = np.random.default_rng(202)
