@@ -1340,12 +1340,7 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
   add(8 * w);
   add(8 * w);
   add(8 * lda * w);  // B
-  {
-    const int64_t T = mp / 64, ntiles = T * (T + 1) / 2;
-    int64_t ks = std::max<int64_t>(1, std::min<int64_t>(16, 320 / ntiles));
-    ks = std::min<int64_t>(ks, std::max<int64_t>(1, w / 64));
-    add(8 * ks * mp * mp);
-  }
+  add(8 * (int64_t)gram_ksplit(mp, w) * mp * mp);
   add(8 * mp * mp);
   add(8 * mp * mp);
   add(8 * mp * mp);  // scratch of the triangular inverse
@@ -1689,13 +1684,7 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
   ALLOC(lp->tw2, w);
   ALLOC(lp->tq, w);
   ALLOC(lp->B, lda * w);
-  {
-    const int T = (int)(mp / 64);
-    const int ntiles = T * (T + 1) / 2;
-    int ks = (int)std::max<int64_t>(1, std::min<int64_t>(16, 320 / ntiles));
-    ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, w / 64));
-    lp->ksplit = ks;
-  }
+  lp->ksplit = gram_ksplit(mp, w);
   ALLOC(lp->Gpart, (int64_t)lp->ksplit * mp * mp);
   ALLOC(lp->G, mp * mp);
   ALLOC(lp->Xb, mp * mp);

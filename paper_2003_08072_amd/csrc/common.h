@@ -362,6 +362,7 @@ void launch_sketch_csc(const SparseA& A, int s, const double* dscale, int is_d2,
                        double* B, int64_t ldb, hipStream_t st);
 
 // Gram matrix and its inverse (blocked Cholesky, triangular inverse, X^T X)
+int gram_ksplit(int64_t mp, int64_t w);  // column splits of the Gram (launch_gram)
 void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart,
                  int ksplit, int64_t mp, hipStream_t st);
 void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, double* G,

@@ -14,102 +14,119 @@ namespace skipm {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, 64x64 tiles of the lower
-// triangle, mirrored to the upper triangle.  G is mp x mp, column-major.
+// Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, 128 x 128 tiles of the
+// lower triangle, mirrored to the upper triangle.  G is mp x mp, column-major.
 //
 // On the FP64 matrix cores: v_mfma_f64_16x16x4 takes, in lane l, A[l%16][l/16]
 // of a 16x4 block and B[l/16][l%16] of a 4x16 block, and accumulates
 // D[l/16 + 4r][l%16] in element r of the lane's four-double accumulator.  The
-// four waves of a workgroup own 16 rows of the 64x64 tile each (four 16x16
-// blocks); 16 columns of B for both row ranges are staged in LDS per step.
+// four waves of a workgroup own a 64 x 64 quarter of the tile each (4 x 4
+// blocks of 16 x 16).  Per stage of 16 columns of B, the tile's two 128-row
+// panels go through LDS (two buffers: the next stage's loads are in flight in
+// registers while this stage's 64 MFMAs per wave run; one barrier per stage).
+// Every entry is a sum over the split's columns in increasing order.
 // ---------------------------------------------------------------------------
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef double dacc4 __attribute__((ext_vector_type(4)));
+constexpr int kRT = 128;      // output tile
+constexpr int kRK = 16;       // columns of B per stage
+constexpr int kRP = kRT + 2;  // LDS row pitch (16-byte aligned rows)
 
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int64_t ldb,
                                               int64_t m, int64_t w, double* __restrict__ Gpart,
                                               int64_t mp, int64_t cols_per_split) {
-  __shared__ double Ai[16][64 + 1];
-  __shared__ double Ak[16][64 + 1];
-  // decode the lower-triangle tile pair (ti >= tk)
+  __shared__ double Ai[2][kRK][kRP];
+  __shared__ double Aj[2][kRK][kRP];
+  // decode the lower-triangle tile pair (ti >= tj)
   int t = blockIdx.x, ti = 0;
   while (t > ti) {
     t -= ti + 1;
     ++ti;
   }
-  const int tk = t;
+  const int tj = t;
   const int ks = blockIdx.y;
-  const int64_t i0 = (int64_t)ti * 64, k0 = (int64_t)tk * 64;
+  const int64_t i0 = (int64_t)ti * kRT, j0 = (int64_t)tj * kRT;
   const int64_t cb = (int64_t)ks * cols_per_split;
   const int64_t ce = cb + cols_per_split < w ? cb + cols_per_split : w;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int th = threadIdx.x, lane = th & 63, wv = th >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  dacc4 acc[4];
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) acc[jb] = (dacc4)0.0;
-  // The 16 columns of step c are loaded into registers two steps ahead (the
-  // sets for c + 16 and c + 32 are in flight while step c's MFMAs run); a
-  // thread's four entries per panel, zero outside B.  Three register sets in
-  // a fixed rotation, so every index is static.
-  auto fetch = [&](double (&vi)[4], double (&vk)[4], const int64_t c) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = threadIdx.x + 256 * q;
-      const int cc = idx >> 6, rr = idx & 63;
-      const int64_t col = c + cc;
-      vi[q] = 0;
-      vk[q] = 0;
-      if (col < ce) {
-        if (i0 + rr < m) vi[q] = B[col * ldb + i0 + rr];
-        if (k0 + rr < m) vk[q] = B[col * ldb + k0 + rr];
+  const int wr = wv >> 1, wc = wv & 1;
+  // load mapping: 4 x (one column kk of the stage, rows 2 rp and 2 rp + 1) per panel
+  const int a_kk = th >> 6, a_rp = th & 63;
+  dvec2 ri[4], rj[4];
+  auto pair = [&](const int64_t r, const int64_t c) {
+    dvec2 v = (dvec2)0.0;
+    if (c < ce) {
+      const double* p = B + c * ldb + r;
+      if (r + 1 < m) {
+        v = *(const dvec2*)p;
+      } else if (r < m) {
+        v.x = p[0];
       }
     }
+    return v;
   };
-  auto step = [&](const double (&vi)[4], const double (&vk)[4]) {
+  auto fetch = [&](const int64_t c0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = threadIdx.x + 256 * q;
-      const int cc = idx >> 6, rr = idx & 63;
-      Ai[cc][rr] = vi[q];
-      Ak[cc][rr] = vk[q];
+      const int64_t c = c0 + a_kk + 4 * q;
+      ri[q] = pair(i0 + 2 * a_rp, c);
+      rj[q] = pair(j0 + 2 * a_rp, c);
     }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const double a = Ai[4 * s + lk][16 * wv + li];
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        const double b = Ak[4 * s + lk][16 * jb + li];
-        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
-      }
-    }
-    __syncthreads();
   };
-  double ai[4], ak[4], bi[4], bk[4], ci[4], ck[4];
-  fetch(ai, ak, cb);
-  fetch(bi, bk, cb + 16);
-  for (int64_t c = cb; c < ce; c += 48) {
-    fetch(ci, ck, c + 32);
-    step(ai, ak);
-    if (c + 16 >= ce) break;
-    fetch(ai, ak, c + 48);
-    step(bi, bk);
-    if (c + 32 >= ce) break;
-    fetch(bi, bk, c + 64);
-    step(ci, ck);
+  auto stash = [&](const int b) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *(dvec2*)&Ai[b][a_kk + 4 * q][2 * a_rp] = ri[q];
+      *(dvec2*)&Aj[b][a_kk + 4 * q][2 * a_rp] = rj[q];
+    }
+  };
+  dacc4 acc[4][4];
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = (dacc4)0.0;
+  const int64_t nst = ce > cb ? (ce - cb + kRK - 1) / kRK : 0;
+  if (nst > 0) {
+    fetch(cb);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    const int b = (int)(st & 1);
+    if (st + 1 < nst) fetch(cb + (st + 1) * kRK);
+#pragma unroll
+    for (int s4 = 0; s4 < kRK / 4; ++s4) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) fa[ib] = Ai[b][4 * s4 + lk][64 * wr + 16 * ib + li];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) fb[jb] = Aj[b][4 * s4 + lk][64 * wc + 16 * jb + li];
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[ib], fb[jb], acc[ib][jb], 0, 0, 0);
+    }
+    if (st + 1 < nst) stash(b ^ 1);
+    __syncthreads();
   }
   // element (i, k) of the tile, mirrored; on a diagonal tile only i >= k is
   // written (with its mirror), so every entry has exactly one writer
   double* G = Gpart + (int64_t)ks * mp * mp;
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb)
+  for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t i = i0 + 16 * wv + lk + 4 * r, k = k0 + 16 * jb + li;
-      if (ti != tk || i >= k) {
-        G[i + k * mp] = acc[jb][r];
-        G[k + i * mp] = acc[jb][r];
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 64 * wr + 16 * ib + lk + 4 * r;
+        const int64_t k = j0 + 64 * wc + 16 * jb + li;
+        if (i < mp && k < mp && (ti != tj || i >= k)) {
+          G[i + k * mp] = acc[ib][jb][r];
+          G[k + i * mp] = acc[ib][jb][r];
+        }
       }
-    }
 }
 
 // G = sum of the split partials on the m x m block; identity on the padding.
@@ -482,9 +499,19 @@ __global__ __launch_bounds__(1024) void k_shift_trace(double* __restrict__ G, in
 
 }  // namespace
 
+// Splits of the Gram along the columns of B: about two workgroups per CU,
+// slices of at least 64 columns, and at most 64 MiB of partials.
+int gram_ksplit(int64_t mp, int64_t w) {
+  const int64_t T = (mp + kRT - 1) / kRT, ntiles = T * (T + 1) / 2;
+  int64_t ks = std::min<int64_t>(16, 512 / ntiles);
+  ks = std::min<int64_t>(ks, w / 64);
+  ks = std::min<int64_t>(ks, (int64_t)(64ll << 20) / (8 * mp * mp));
+  return (int)std::max<int64_t>(1, ks);
+}
+
 void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart, int ksplit,
                  int64_t mp, hipStream_t st) {
-  const int T = (int)(mp / 64);
+  const int T = (int)((mp + kRT - 1) / kRT);
   const int ntiles = T * (T + 1) / 2;
   int64_t cps = (w + ksplit - 1) / ksplit;
   cps = (cps + 15) / 16 * 16;

@@ -41,6 +41,12 @@ constexpr uint32_t kSbLow = 0xfffu;  // local column (rk) or row (ck) bits
 
 __host__ __device__ inline int sb_k(int64_t N) { return (int)((N + kSbThreads - 1) / kSbThreads); }
 
+// LDS slot of coefficient lc: one pad double after every eight, so that lanes
+// reading or writing coefficients 4 or 8 apart (a thread's run over short
+// columns, or over one long row) fall in different banks
+__device__ __forceinline__ int cpad(int lc) { return lc + (lc >> 3); }
+constexpr int kSbCoefLds = kSbCols + kSbCols / 8;
+
 // One workgroup per block.  Column order: the CSC order.  Row order: the
 // non-zeros keyed (row << 16 | local column) << 32 | CSC offset, bitonic-sorted
 // in LDS (keys are distinct).  Logical position j of an order goes to slot
@@ -157,11 +163,16 @@ __device__ __forceinline__ double seg_scan(int f, double s, int* wf, double* ws)
 // and ends inside the run is stored at out[segment] directly; the run's first
 // and last segments may go on in the neighbouring runs and are joined by the
 // segmented scan over the threads: the thread holding a segment's last
-// non-zero stores the scanned sum of all its pieces.  Every thread of the
-// workgroup calls it (barriers inside).
+// non-zero stores the scanned sum of all its pieces (PAD: at out[cpad(segment)]).
+// Every thread of the workgroup calls it (barriers inside).
+template <bool PAD>
 __device__ __forceinline__ void run_sums(const uint32_t (&key)[kSbK], const double (&term)[kSbK],
                                          int n, double* out, double* s_S, int* wf, double* ws) {
   const int tid = threadIdx.x;
+  auto at = [](uint32_t kk) {
+    const int i = (int)(kk >> 16);
+    return PAD ? cpad(i) : i;
+  };
   int runs = 0, hi = -1, ti = -1;
   double hs = 0, acc = 0;
   bool first_flag = false, last_flag = false;
@@ -177,8 +188,8 @@ __device__ __forceinline__ void run_sums(const uint32_t (&key)[kSbK], const doub
         } else if (runs > 1) {
           out[ti] = acc;  // started and ended inside this run
         }
-        if (runs == 0) hi = (int)(kk >> 16);
-        ti = (int)(kk >> 16);
+        if (runs == 0) hi = at(kk);
+        ti = at(kk);
         acc = term[k];
         ++runs;
       } else {
@@ -200,7 +211,7 @@ __device__ __forceinline__ void run_sums(const uint32_t (&key)[kSbK], const doub
 template <typename TV>
 __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   extern __shared__ double dyn[];  // u (m rows), then the block's partial q (m rows)
-  __shared__ double coef[kSbCols];
+  __shared__ double coef[kSbCoefLds];
   __shared__ double sred[2];
   __shared__ double s_S[kSbThreads];
   __shared__ int wf[kSbThreads / 64];
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
 #pragma unroll
   for (int q = 0; q < kCp; ++q) {
     const int lc = tid + kSbThreads * q;
-    if (lc < ncol) coef[lc] = 0.0;  // columns with no non-zero keep t_j = 0
+    if (lc < ncol) coef[cpad(lc)] = 0.0;  // columns with no non-zero keep t_j = 0
   }
   __syncthreads();
 
@@ -342,13 +353,13 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
     double term[kSbK];
 #pragma unroll
     for (int k = 0; k < kSbK; ++k) term[k] = (double)cvt[k] * us[ckt[k] & kSbLow];
-    run_sums(ckt, term, n_mine, coef, s_S, wf, ws);
+    run_sums<true>(ckt, term, n_mine, coef, s_S, wf, ws);
   }
   if (a.c) {  // coef_j = c_j t_j
 #pragma unroll
     for (int q = 0; q < kCp; ++q) {
       const int lc = tid + kSbThreads * q;
-      if (lc < ncol) coef[lc] = spre[q] * coef[lc];
+      if (lc < ncol) coef[cpad(lc)] = spre[q] * coef[cpad(lc)];
     }
     __syncthreads();
   }
@@ -356,8 +367,8 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   {
     double term[kSbK];
 #pragma unroll
-    for (int k = 0; k < kSbK; ++k) term[k] = (double)rvt[k] * coef[rkt[k] & kSbLow];
-    run_sums(rkt, term, n_mine, qs, s_S, wf, ws);
+    for (int k = 0; k < kSbK; ++k) term[k] = (double)rvt[k] * coef[cpad((int)(rkt[k] & kSbLow))];
+    run_sums<false>(rkt, term, n_mine, qs, s_S, wf, ws);
   }
   double* out = a.part + (int64_t)blockIdx.x * a.ldp;
   for (int64_t i = tid; i < m; i += kSbThreads) out[i] = qs[i];
