@@ -127,33 +127,54 @@ struct SbArgs {
   CgFuse cg;  // inside CG: open the iteration (stop test, beta, d_k)
 };
 
+// One DPP step of the segmented scan: (F, S) combined with the pair of the
+// source lane that `ctrl` selects (the identity (0, 0) where it selects none).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_dpp(int& F, double& S) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(S), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(S), CTRL, ROWS, 0xf, true);
+  const int Fp = __builtin_amdgcn_update_dpp(0, F, CTRL, ROWS, 0xf, true);
+  const double Sp = __hiloint2double(hi, lo);
+  if (!F) S = Sp + S;
+  F |= Fp;
+}
+
 // Inclusive segmented scan of (start flag f, value s) over the workgroup's
 // threads in thread order: S_t = s_t if f_t, else S_{t-1} + s_t.  Within a wave
-// by shuffles, then the waves' totals in wave order; the order of additions
-// depends only on the flags, so the result is reproducible.
+// by DPP (shifts by 1, 2, 4, 8 inside rows of 16 lanes, then row 15's pair to
+// the next row and lane 31's to the upper half), then the waves' totals in wave
+// order; the order of additions depends only on the flags, so the result is
+// reproducible.
 __device__ __forceinline__ double seg_scan(int f, double s, int* wf, double* ws) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int F = f;
   double S = s;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double Sp = __shfl_up(S, off, 64);
-    const int Fp = __shfl_up(F, off, 64);
-    if (lane >= off) {
-      if (!F) S = Sp + S;
-      F |= Fp;
-    }
-  }
+  seg_dpp<0x111, 0xf>(F, S);  // row_shr:1
+  seg_dpp<0x112, 0xf>(F, S);  // row_shr:2
+  seg_dpp<0x114, 0xf>(F, S);  // row_shr:4
+  seg_dpp<0x118, 0xf>(F, S);  // row_shr:8
+  seg_dpp<0x142, 0xa>(F, S);  // row_bcast:15 into rows 1 and 3
+  seg_dpp<0x143, 0xc>(F, S);  // row_bcast:31 into rows 2 and 3
   if (lane == 63) {
     wf[wid] = F;
     ws[wid] = S;
   }
   __syncthreads();
-  if (!F && wid > 0) {  // no start in this wave up to this lane: carry in
-    double cs = ws[0];
-    for (int w = 1; w < wid; ++w) cs = wf[w] ? ws[w] : cs + ws[w];
-    S = cs + S;
+  // the waves' totals scanned the same way by the first 16 lanes of wave 0;
+  // wave w then takes the scan up to wave w - 1
+  constexpr int kW = kSbThreads / 64;
+  static_assert(kW <= 16, "one DPP row holds the wave totals");
+  if (wid == 0) {
+    int Fw = lane < kW ? wf[lane] : 1;
+    double Sw = lane < kW ? ws[lane] : 0.0;
+    seg_dpp<0x111, 0xf>(Fw, Sw);
+    seg_dpp<0x112, 0xf>(Fw, Sw);
+    seg_dpp<0x114, 0xf>(Fw, Sw);
+    seg_dpp<0x118, 0xf>(Fw, Sw);
+    if (lane + 1 < kW) ws[kW + lane + 1] = Sw;
   }
+  __syncthreads();
+  if (!F && wid > 0) S = ws[kW + wid] + S;
   return S;
 }
 
@@ -215,7 +236,7 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   __shared__ double sred[2];
   __shared__ double s_S[kSbThreads];
   __shared__ int wf[kSbThreads / 64];
-  __shared__ double ws[kSbThreads / 64];
+  __shared__ double ws[2 * (kSbThreads / 64)];  // wave totals, then their scan
   const int64_t m = a.m;
   double* us = dyn;
   double* qs = dyn + ((m + 1) & ~1ll);
