@@ -503,7 +503,12 @@ def serve_trace(sk, torch, args, trace, lps, scale=1.0):
             time.sleep(delay)
         tickets.append(srv.submit(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed,
                                   s=args.s, eps_gap=lp.eps_gap, max_outer=1000))
-    done = [srv.wait(t)[0] for t in tickets]
+    done = []
+    for i, t in enumerate(tickets):
+        done.append(srv.wait(t)[0])
+        if (i + 1) % 20 == 0 or i + 1 == len(tickets):
+            print(f"[bench] {i + 1}/{len(tickets)} requests done, "
+                  f"{time.perf_counter() - start:.1f} s", file=sys.stderr, flush=True)
     stats = srv.stats()
     srv.close()
     lat = [d.latency * 1000.0 for d in done]

@@ -473,7 +473,10 @@ int pcg_small(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int m
 // reaches c_stop after about (k - k_prev) log(c_k / c_stop) / log(c_prev / c_k)
 // more; the next chunk is half of what that leaves beyond the queued
 // iterations, between 1 and kCgChunkMax.  (CG converges faster towards the
-// end, so the recent rate, halved, rarely overshoots.)
+// end, so the recent rate, halved, rarely overshoots.)  LPs solved next to
+// others (the batch and the request server) keep one snapshot in flight: the
+// host checks each chunk with the stream idle, as the others' work fills the
+// device meanwhile.
 constexpr int kCgChunkDefault = 4, kCgChunkMax = 16;
 
 struct CgProgress {
@@ -515,6 +518,9 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   int enq = 0, slot = 0;
   int queue[2], nq = 0;  // snapshots in flight, oldest first
   bool capped[2] = {false, false};
+  // snapshots in flight: two overlap the check with the next chunk; one checks
+  // each chunk with the stream idle (a plain stream synchronisation)
+  const int depth = lp->overlap_checks ? 2 : 1;
   auto enqueue = [&](int n) -> int {
     for (int q = 0; q < n && enq < max_it; ++q, ++enq) SK_TRY(pcg_iteration(lp, xsol, enq, st));
     capped[slot] = enq >= max_it;
@@ -522,7 +528,7 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
       launch_cg_close(lp->cgred + lp->cg_nf, lp->cg_nd, enq, lp->sc, lp->is, st);
     SK_CHECK_HIP(hipMemcpyAsync(lp->hsnap[slot], lp->sc, kScalarBlockBytes,
                                 hipMemcpyDeviceToHost, st));
-    SK_CHECK_HIP(hipEventRecord(lp->snap_ev[slot], st));
+    if (depth == 2) SK_CHECK_HIP(hipEventRecord(lp->snap_ev[slot], st));
     queue[nq++] = slot;
     slot ^= 1;
     return SKIPM_OK;
@@ -531,13 +537,17 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
   int next = std::min(kCgChunkDefault, std::max(1, first_chunk));
   CgProgress progress;
   for (;;) {
-    if (nq < 2 && enq < max_it) {
+    if (nq < depth && enq < max_it) {
       SK_TRY(enqueue(next));
     }
     const int look = queue[0];
     queue[0] = queue[1];
     --nq;
-    SK_CHECK_HIP(hipEventSynchronize(lp->snap_ev[look]));
+    if (depth == 2) {
+      SK_CHECK_HIP(hipEventSynchronize(lp->snap_ev[look]));
+    } else {
+      SK_CHECK_HIP(hipStreamSynchronize(st));
+    }
     const double* snap = lp->hsnap[look];
     const int32_t* hi = (const int32_t*)(snap + S_NSLOTS);
     const bool fail = hi[I_FACT_FAIL] != 0;

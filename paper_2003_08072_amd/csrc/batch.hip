@@ -507,6 +507,20 @@ int lp_solve_batch(skipm_lp_t* lps, int32_t count, skipm_result* res, int32_t wo
   SK_CHECK_HIP(hipDeviceSynchronize());
   int dev = 0;
   SK_CHECK_HIP(hipGetDevice(&dev));
+  // several LPs share the device: CG chunks are checked with their stream idle
+  // (the flag is restored on return)
+  std::vector<char> overlap(count);
+  for (int i = 0; i < count; ++i) {
+    overlap[i] = lps[i]->overlap_checks;
+    lps[i]->overlap_checks = false;
+  }
+  struct Restore {
+    skipm_lp_t* lps;
+    const std::vector<char>& v;
+    ~Restore() {
+      for (size_t i = 0; i < v.size(); ++i) lps[i]->overlap_checks = v[i] != 0;
+    }
+  } restore{lps, overlap};
   // dense FP64-product LPs of this device go through the grouped engine; the
   // others (CSR, low-precision products) the single-LP way (threads below)
   std::vector<int> grouped_idx, single_idx;
@@ -685,6 +699,7 @@ void skipm_server_s::worker_main() {
     if (rc == SKIPM_OK && r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess)
       rc = SKIPM_EDEVICE;
     if (rc == SKIPM_OK) rc = lp_create(&lp, &r->prob, &r->prm, st);
+    if (rc == SKIPM_OK) lp->overlap_checks = false;  // other requests share the device
     if (rc != SKIPM_OK) {
       oc.rc = rc;
       oc.res.status = rc;

@@ -69,6 +69,10 @@ struct skipm_lp_s {
   // chunk checks (the host reads one while the next chunk runs)
   double* hsnap[2] = {nullptr, nullptr};
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
+  // false: each chunk is checked with the stream idle (no chunk queued behind
+  // the check); set for LPs that the batch and the request server solve on
+  // their own threads, where other LPs keep the device busy meanwhile
+  bool overlap_checks = true;
   int nblk_A = 1, nblk_Ap = 1, nblk_A32 = 1, nblk_A16 = 1, nblk_B = 1, nblk_vec = 1;
   int64_t k = 0;
   int64_t hashed_k = -1;
