@@ -224,6 +224,19 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
       pre1[q] = pv[(int64_t)pc * pst + (cg_open ? 1 : 0)];  // unused unless cg_open
     }
   }
+  // the scalars the opening test (or the closing step) reads, requested with
+  // the partials: the stopping threshold, the cap and r^T z of the previous
+  // iteration (of this one when closing), all written by earlier launches
+  double pf_tol2 = 0, pf_rzh = 0;
+  int pf_resid = 0, pf_max = 0;
+  if (cg_open) {
+    pf_tol2 = a.cg.sc[S_CG_TOL2];
+    pf_rzh = a.cg.sc[S_CG_RZH0 + (int)((a.cg.k - 1) & 1)];
+    pf_resid = a.cg.is[I_CG_RESID];
+    pf_max = a.cg.is[I_CG_MAX];
+  } else if (cg_close) {
+    pf_rzh = a.cg.sc[S_CG_RZH0 + (int)(a.cg.k & 1)];
+  }
   // the done flag of a finished CG is read only now, so that its latency
   // overlaps that of the loads above (all in bounds)
   if (a.done && *a.done) return;
@@ -232,6 +245,7 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
   // early, and the wait for those loads would come before the flag's load)
 #pragma unroll
   for (int q = 0; q < kPre; ++q) asm volatile("" : "+v"(pre0[q]), "+v"(pre1[q]));
+  asm volatile("" : "+v"(pf_tol2), "+v"(pf_rzh), "+v"(pf_resid), "+v"(pf_max));
   if (cg_dir) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -273,9 +287,9 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
     int32_t* is = a.cg.is;
     if (MODE == COL_NORMAL && k > 0) {
       const double rz = cgs[0], rr = cgs[1];
-      const double crit = is[I_CG_RESID] ? rr : rz;
-      const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
-      cg_beta = a.cg.inner == SKIPM_INNER_CG ? rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)] : 0.0;
+      const double crit = pf_resid ? rr : rz;
+      const bool stop = k >= pf_max || crit <= pf_tol2 || !(rz > 0);
+      cg_beta = a.cg.inner == SKIPM_INNER_CG ? rz / pf_rzh : 0.0;
       if (bid == 0 && threadIdx.x == 0) {
         sc[S_CG_RZ] = rz;
         sc[S_V_RR] = rr;
@@ -290,7 +304,7 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
         if (bid == 0 && threadIdx.x == 0) is[I_CG_DONE] = 1;
         return;
       }
-      cg_alpha = a.cg.inner == SKIPM_INNER_RICHARDSON ? 1.0 : sc[S_CG_RZH0 + (int)(k & 1)] / dq;
+      cg_alpha = a.cg.inner == SKIPM_INNER_RICHARDSON ? 1.0 : pf_rzh / dq;
     }
   }
   double cg_pz = 0, cg_pr = 0;

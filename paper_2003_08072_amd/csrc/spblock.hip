@@ -274,6 +274,15 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
       pre1[q] = a.cg.prz[2 * (int64_t)pc + 1];
     }
   }
+  // the scalars of the opening test, written by earlier launches
+  double pf_tol2 = 0, pf_rzh = 0;
+  int pf_resid = 0, pf_max = 0;
+  if (cg_open) {
+    pf_tol2 = a.cg.sc[S_CG_TOL2];
+    pf_rzh = a.cg.sc[S_CG_RZH0 + (int)((a.cg.k - 1) & 1)];
+    pf_resid = a.cg.is[I_CG_RESID];
+    pf_max = a.cg.is[I_CG_MAX];
+  }
   if (done0) return;
   const int N = bd.z;
   const int K = sb_k(N);
@@ -332,10 +341,9 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
     double* sc = a.cg.sc;
     int32_t* is = a.cg.is;
     const double rz = sred[0], rr = sred[1];
-    const double crit = is[I_CG_RESID] ? rr : rz;
-    const bool stop = k >= is[I_CG_MAX] || crit <= sc[S_CG_TOL2] || !(rz > 0);
-    const double beta =
-        a.cg.inner == SKIPM_INNER_CG ? rz / sc[S_CG_RZH0 + (int)((k - 1) & 1)] : 0.0;
+    const double crit = pf_resid ? rr : rz;
+    const bool stop = k >= pf_max || crit <= pf_tol2 || !(rz > 0);
+    const double beta = a.cg.inner == SKIPM_INNER_CG ? rz / pf_rzh : 0.0;
     __syncthreads();
     if (blockIdx.x == 0 && tid == 0) {
       sc[S_CG_RZ] = rz;
