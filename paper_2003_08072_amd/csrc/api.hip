@@ -1332,13 +1332,18 @@ int lp_footprint(const skipm_problem* prob, const skipm_params* prm, int64_t* ou
     add(8 * n);
     add(8 * n);
     add(16 * nseg);
-    {  // column blocks: descriptors, both keyed copies
+    {  // column blocks: descriptors, the column-order copy, the row order
+      // (FP64 values: a second keyed copy; FP32: 16-bit references)
       const int64_t nb = sb_max_blocks(n, nnz), sl = sb_max_slots(n, nnz);
       add(16 * nb);
       add(4 * sl);
-      add(4 * sl);
       add(8 * ((sl * esz + 7) / 8));
-      add(8 * ((sl * esz + 7) / 8));
+      if (f64) {
+        add(4 * sl);
+        add(8 * ((sl * esz + 7) / 8));
+      } else {
+        add(8 * ((sl * 2 + 7) / 8));
+      }
     }
     nblk_csc = csc_dot_nblk(n);
   }
@@ -1631,16 +1636,23 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
       }
       S.nbk = nbk;
       int32_t* bdesc;
-      uint32_t *ck, *rk;
-      double *cv, *rv;
+      uint32_t* ck;
+      uint32_t* rk = nullptr;
+      double* cv;
+      double* rv = nullptr;
+      uint16_t* rp = nullptr;
       ALLOC(bdesc, 4 * nbk);
       ALLOC(ck, slots);
-      ALLOC(rk, slots);
       ALLOC(cv, (slots * (int64_t)esz + 7) / 8);
-      ALLOC(rv, (slots * (int64_t)esz + 7) / 8);
+      if (S.vdt == SKIPM_F64) {
+        ALLOC(rk, slots);
+        ALLOC(rv, (slots * (int64_t)esz + 7) / 8);
+      } else {
+        ALLOC(rp, slots);
+      }
       SK_CHECK_HIP(hipMemcpyAsync(bdesc, hd.data(), 4 * nbk * sizeof(int32_t),
                                   hipMemcpyHostToDevice, st));
-      sb_fill(&S, bdesc, ck, cv, rk, rv, bad, st);
+      sb_fill(&S, bdesc, ck, cv, rk, rv, rp, bad, st);
       SK_CHECK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       SK_CHECK_HIP(hipStreamSynchronize(st));
       if (hbad) {

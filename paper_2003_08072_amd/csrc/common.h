@@ -306,26 +306,31 @@ struct SparseA {
   const int32_t* seg_start = nullptr;
   const int32_t* seg_end = nullptr;
   // column blocks of the one-pass normal product: bdesc[4 b ..] = (first
-  // column, columns, non-zeros, first slot) of block b; its slots of two keyed
-  // copies of its non-zeros: column order (ck = local column << 16 | row, cv)
-  // and (row, column) order (rk = row << 16 | local column, rv); bits 12 and
-  // 13 of a key mark its column's (row's) first and last non-zero
+  // column, columns, non-zeros, first slot) of block b; its slots of the
+  // keyed copy of its non-zeros in column order (ck = local column << 16 |
+  // row, cv), and their (row, column) order: FP64 values as a second keyed
+  // copy (rk = row << 16 | local column, rv), FP32 values as 16-bit references
+  // (rp: the block-local slot of the column-order entry, bits 13 and 14 marking
+  // the row's first and last non-zero).  Bits 12 and 13 of a key mark its
+  // column's (row's) first and last non-zero.
   int64_t nbk = 0;
   const int32_t* bdesc = nullptr;
   const uint32_t* ck = nullptr;
   const void* cv = nullptr;
   const uint32_t* rk = nullptr;
   const void* rv = nullptr;
+  const uint16_t* rp = nullptr;
 };
 constexpr int kSeg = 512;
 // One-pass sparse normal product (column blocks, LDS coefficients).
 // sb_partition cuts the columns into blocks and lays out their slots (host
 // vector of 4 nbk block descriptors; returns the slot count, or -1 on a HIP
-// error); sb_fill (A->nbk set, bdesc on the device) writes both keyed copies
-// and records them in A; bad |= 4 if a block broke its bounds.
+// error); sb_fill (A->nbk set, bdesc on the device) writes the column-order
+// copy and the row order (rk, rv for FP64 values, rp for FP32; the others
+// null) and records them in A; bad |= 4 if a block broke its bounds.
 int64_t sb_partition(const SparseA& A, std::vector<int32_t>* bdesc, hipStream_t st);
 void sb_fill(SparseA* A, const int32_t* bdesc, uint32_t* ck, void* cv, uint32_t* rk, void* rv,
-             int32_t* bad, hipStream_t st);
+             uint16_t* rp, int32_t* bad, hipStream_t st);
 int64_t sb_max_blocks(int64_t n, int64_t nnz);  // upper bounds: block count,
 int64_t sb_max_slots(int64_t n, int64_t nnz);   // slots of each keyed copy
 // part[b][i] (b < A.nbk, leading dimension ldp >= m) = sum over block b's

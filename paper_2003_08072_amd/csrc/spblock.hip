@@ -2,21 +2,25 @@
 //
 // A's columns are cut into blocks of consecutive columns (at most kSbCols
 // columns and kSbEntries non-zeros each).  Each block's non-zeros are kept
-// twice more, in column order (ck = local column << 16 | row, cv: the value)
-// and in (row, column) order (rk = row << 16 | local column, rv: the value);
-// each key also marks the first and last non-zero of its column (of its row).
-// In both copies thread t of the block's workgroup (1024 threads) owns the
+// once more in column order (ck = local column << 16 | row, cv: the value),
+// and their (row, column) order is kept as well: with FP64 values as a second
+// keyed copy (rk = row << 16 | local column, rv: the value), with FP32 values
+// as 16-bit references to the column-order entries (rp, 2 bytes instead of
+// 8 per non-zero; the workgroup reads the entries back from LDS).  Each key
+// (reference) also marks the first and last non-zero of its column (row).
+// In each order thread t of the block's workgroup (1024 threads) owns the
 // K = ceil(N / 1024) consecutive non-zeros t K ... t K + K - 1 of the order,
 // stored so that the k-th of them sits at slot k * 1024 + t of the block's
 // region: a load of slot row k by all threads is coalesced, and each thread
 // still walks a contiguous run.  One workgroup per block:
 //   1. u (or, when the pass opens a CG iteration, d_k = z_k + beta_k d_{k-1})
-//      into LDS, and all of the block's keys and values into registers;
+//      into LDS, and all of the block's keys and values into registers (FP32:
+//      the column-order entries also into LDS, by block-local slot);
 //   2. column phase: each thread sums a_ij u_i along its run; columns inside
 //      the run are complete, columns cut by run boundaries are joined by one
 //      segmented scan over the threads; coef_j = c_j t_j into LDS;
-//   3. row phase: the same over the row-ordered copy with terms a_ij coef_j,
-//      giving the block's q in LDS;
+//   3. row phase: the same over the row order with terms a_ij coef_j, giving
+//      the block's q in LDS;
 //   4. q goes to part[block]; the finish adds the partials of all blocks in
 //      block order.
 // coef never leaves LDS, so no value is gathered from global memory at a random
@@ -38,6 +42,10 @@ constexpr int kSbCap = kSbEntries - (int)kMaxM;  // see sb_partition
 constexpr int kSbRows = (int)kMaxM;
 constexpr uint32_t kSbFirst = 1u << 12, kSbLast = 1u << 13;  // key flags
 constexpr uint32_t kSbLow = 0xfffu;  // local column (rk) or row (ck) bits
+// row-order references (FP32 values): block-local slot, row's first / last
+constexpr uint16_t kRpSlot = 0x1fff, kRpFirst = 1u << 13, kRpLast = 1u << 14;
+template <typename TV>
+constexpr bool sb_refs() { return sizeof(TV) == 4; }
 
 __host__ __device__ inline int sb_k(int64_t N) { return (int)((N + kSbThreads - 1) / kSbThreads); }
 
@@ -50,7 +58,8 @@ constexpr int kSbCoefLds = kSbCols + kSbCols / 8;
 // One workgroup per block.  Column order: the CSC order.  Row order: the
 // non-zeros keyed (row << 16 | local column) << 32 | CSC offset, bitonic-sorted
 // in LDS (keys are distinct).  Logical position j of an order goes to slot
-// (j % K) * 1024 + j / K of the block's region.
+// (j % K) * 1024 + j / K of the block's region; a reference (FP32 values)
+// names the block-local slot of the entry's column-order position.
 template <typename TV>
 __global__ __launch_bounds__(1024) void k_sb_sort(const int32_t* __restrict__ colptr,
                                                   const int32_t* __restrict__ rowidx,
@@ -58,6 +67,7 @@ __global__ __launch_bounds__(1024) void k_sb_sort(const int32_t* __restrict__ co
                                                   const int4* __restrict__ bdesc,
                                                   uint32_t* __restrict__ ck, TV* __restrict__ cv,
                                                   uint32_t* __restrict__ rk, TV* __restrict__ rv,
+                                                  uint16_t* __restrict__ rp,
                                                   int32_t* __restrict__ bad) {
   __shared__ uint64_t sk[kSbEntries];
   const int4 bd = bdesc[blockIdx.x];  // first column, columns, non-zeros, first slot
@@ -107,8 +117,14 @@ __global__ __launch_bounds__(1024) void k_sb_sort(const int32_t* __restrict__ co
     const uint32_t row = key >> 16;
     const bool first = q == 0 || (uint32_t)(sk[q - 1] >> 48) != row;
     const bool last = q == N - 1 || (uint32_t)(sk[q + 1] >> 48) != row;
-    rk[slot(q)] = key | (first ? kSbFirst : 0u) | (last ? kSbLast : 0u);
-    rv[slot(q)] = cval[P0 + (int64_t)(v & 0xffffffffull)];
+    const int jc = (int)(v & 0xffffffffull);
+    if constexpr (sb_refs<TV>()) {
+      rp[slot(q)] = (uint16_t)(((jc % K) * kSbThreads + jc / K) | (first ? kRpFirst : 0) |
+                               (last ? kRpLast : 0));
+    } else {
+      rk[slot(q)] = key | (first ? kSbFirst : 0u) | (last ? kSbLast : 0u);
+      rv[slot(q)] = cval[P0 + jc];
+    }
   }
 }
 
@@ -118,6 +134,7 @@ struct SbArgs {
   const void* cv;
   const uint32_t* rk;
   const void* rv;
+  const uint16_t* rp;
   int64_t m;
   const double* u;
   const double* c;  // coef_j = c_j t_j (null: coef_j = t_j)
@@ -237,6 +254,11 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   __shared__ double s_S[kSbThreads];
   __shared__ int wf[kSbThreads / 64];
   __shared__ double ws[2 * (kSbThreads / 64)];  // wave totals, then their scan
+  // FP32 values: the column-order entries by block-local slot, read back in
+  // row order through the references
+  constexpr bool kRefs = sb_refs<TV>();
+  __shared__ uint32_t skey[kRefs ? kSbEntries : 1];
+  __shared__ TV sval[kRefs ? kSbEntries : 1];
   const int64_t m = a.m;
   double* us = dyn;
   double* qs = dyn + ((m + 1) & ~1ll);
@@ -291,18 +313,24 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   const TV* __restrict__ rvp = (const TV*)a.rv;
   uint32_t ckt[kSbK], rkt[kSbK];
   TV cvt[kSbK], rvt[kSbK];
+  uint16_t rpt[kSbK];
 #pragma unroll
   for (int k = 0; k < kSbK; ++k) {
     ckt[k] = 0;
     rkt[k] = 0;
     cvt[k] = 0;
     rvt[k] = 0;
+    rpt[k] = 0;
     if (k < n_mine) {
       const int64_t p = O + (int64_t)k * kSbThreads + tid;
       ckt[k] = a.ck[p];
       cvt[k] = cvp[p];
-      rkt[k] = a.rk[p];
-      rvt[k] = rvp[p];
+      if constexpr (kRefs) {
+        rpt[k] = a.rp[p];
+      } else {
+        rkt[k] = a.rk[p];
+        rvt[k] = rvp[p];
+      }
     }
   }
   constexpr int kCp = kSbCols / kSbThreads;
@@ -375,6 +403,14 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
     const int lc = tid + kSbThreads * q;
     if (lc < ncol) coef[cpad(lc)] = 0.0;  // columns with no non-zero keep t_j = 0
   }
+  if constexpr (kRefs) {
+#pragma unroll
+    for (int k = 0; k < kSbK; ++k)
+      if (k < n_mine) {
+        skey[k * kSbThreads + tid] = ckt[k];
+        sval[k * kSbThreads + tid] = cvt[k];
+      }
+  }
   __syncthreads();
 
   // column phase: t_j
@@ -395,8 +431,23 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
   // row phase: q_i
   {
     double term[kSbK];
+    if constexpr (kRefs) {
 #pragma unroll
-    for (int k = 0; k < kSbK; ++k) term[k] = (double)rvt[k] * coef[cpad((int)(rkt[k] & kSbLow))];
+      for (int k = 0; k < kSbK; ++k) {
+        term[k] = 0.0;
+        if (k < n_mine) {
+          const int e = rpt[k] & kRpSlot;
+          const uint32_t key = skey[e];  // local column << 16 | row
+          rkt[k] = ((key & kSbLow) << 16) | ((rpt[k] & kRpFirst) ? kSbFirst : 0u) |
+                   ((rpt[k] & kRpLast) ? kSbLast : 0u);
+          term[k] = (double)sval[e] * coef[cpad((int)(key >> 16))];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kSbK; ++k)
+        term[k] = (double)rvt[k] * coef[cpad((int)(rkt[k] & kSbLow))];
+    }
     run_sums<false>(rkt, term, n_mine, qs, s_S, wf, ws);
   }
   double* out = a.part + (int64_t)blockIdx.x * a.ldp;
@@ -451,20 +502,22 @@ int64_t sb_partition(const SparseA& A, std::vector<int32_t>* bdesc, hipStream_t 
 }
 
 void sb_fill(SparseA* A, const int32_t* bdesc, uint32_t* ck, void* cv, uint32_t* rk, void* rv,
-             int32_t* bad, hipStream_t st) {
+             uint16_t* rp, int32_t* bad, hipStream_t st) {
   const int4* bd = (const int4*)bdesc;
   if (A->vdt == SKIPM_F64)
     hipLaunchKernelGGL(k_sb_sort<double>, dim3((unsigned)A->nbk), dim3(1024), 0, st, A->colptr,
                        A->rowidx, (const double*)A->cval, bd, ck, (double*)cv, rk, (double*)rv,
-                       bad);
+                       rp, bad);
   else
     hipLaunchKernelGGL(k_sb_sort<float>, dim3((unsigned)A->nbk), dim3(1024), 0, st, A->colptr,
-                       A->rowidx, (const float*)A->cval, bd, ck, (float*)cv, rk, (float*)rv, bad);
+                       A->rowidx, (const float*)A->cval, bd, ck, (float*)cv, rk, (float*)rv, rp,
+                       bad);
   A->bdesc = bdesc;
   A->ck = ck;
   A->cv = cv;
   A->rk = rk;
   A->rv = rv;
+  A->rp = rp;
 }
 
 int launch_sb_normal(const SparseA& A, const double* u, const double* c, double* part,
@@ -477,6 +530,7 @@ int launch_sb_normal(const SparseA& A, const double* u, const double* c, double*
   a.cv = A.cv;
   a.rk = A.rk;
   a.rv = A.rv;
+  a.rp = A.rp;
   a.m = A.m;
   a.u = u;
   a.c = c;
