@@ -27,11 +27,13 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # dense FP64 MFMA
 INFINITY_CACHE_BYTES = 256 << 20
 
-# HBM bytes per launch of the fused normal matvec on config 1, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes (FETCH_SIZE scaled by 1.9999, the factor a
-# 1 GiB device copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the
-# current k_colpass; profiles/hbm_traffic_colpass_normal_cfg1.md has the runs.
-MEASURED_TRAFFIC = {(1, "mixed"): 202_012_349, (1, "fp64"): 406_341_296}
+# HBM bytes per launch of the normal product from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (FETCH_SIZE scaled by 1.99995, the factor a 1 GiB device
+# copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the current kernels:
+# config 1, k_colpass (profiles/hbm_traffic_colpass_normal_cfg1.md); config 2,
+# k_sb_normal and its finish (profiles/hbm_traffic_sb_normal_cfg2.md).
+MEASURED_TRAFFIC = {(1, "mixed"): 202_021_588, (1, "fp64"): 406_322_525,
+                    (2, "fp64"): 32_359_752}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
 
@@ -150,10 +152,13 @@ def matvec_bytes(lp, precision, tier=None):
     Dense: A once (m n values in the precision the CG reads: the tier's copy),
     D^2 once (n FP64 values), u in and the product out (m FP64 each).  CSR:
     one read of the non-zeros (index and value each), of the column pointers
-    and of D^2.  (The one-pass kernel reads the non-zeros twice, once per
-    copy, and writes and re-reads one m-vector of partial sums per column
-    block: traffic above these bytes.)"""
-    tier = PREC_START_TIER[precision] if tier is None else tier
+    and of D^2.  (The one-pass kernel reads each non-zero's column-order entry
+    and, for its row order, a 2-byte reference (FP32 values) or a second keyed
+    copy (FP64 values), and writes and re-reads one m-vector of partial sums
+    per column block: traffic above these bytes.)  A CSR product reads the
+    values as stored, whatever the precision mode."""
+    if tier is None:
+        tier = PREC_START_TIER.get(precision, 0)
     pa = min(TIER_BYTES[tier], 4 if lp.a_dtype == "f32" else 8)
     if lp.fmt == "dense":
         return lp.m * lp.n * pa + lp.n * 8 + 2 * lp.m * 8
