@@ -371,6 +371,7 @@ ColPass cg_close_args(skipm_lp_s* lp, double* xsol, int p) {
   pq.cg.pdq = lp->cgred;
   pq.cg.nf = lp->cg_nf;
   pq.cg.prz_out = lp->cgred + lp->cg_nf;
+  pq.nt = lp->fmt == SKIPM_CSR;
   return pq;
 }
 

@@ -795,7 +795,7 @@ void launch_one(const Args& a, int nblk, hipStream_t st, hipEvent_t e0, hipEvent
 
 // the passes over A that may take non-temporal loads (STREAM)
 constexpr bool stream_mode(int mode) {
-  return mode == COL_NORMAL || mode == COL_PROLOGUE || mode == COL_EPILOGUE;
+  return mode == COL_NORMAL || mode == COL_PROLOGUE || mode == COL_EPILOGUE || mode == COL_DOT;
 }
 
 template <typename TA, typename TC, int MODE>

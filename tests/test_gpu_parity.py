@@ -909,6 +909,10 @@ def _csr_case(m, n, dens, ones, dense_col, empty_rows, seed):
     (2048, 3000, 0.01, True, True, False, "f64"),   # largest m
     (5, 20000, 0.5, True, True, False, "f32"),      # few rows, long runs per row
     (64, 9000, 0.02, False, False, True, "f64"),    # empty rows
+    # FP32 values keep the row order as 2-byte references into LDS
+    (2048, 3000, 0.01, True, True, False, "f32"),   # largest m: the most LDS
+    (300, 12000, 0.3, False, True, False, "f32"),   # blocks cut by the non-zero bound
+    (64, 9000, 0.02, False, False, True, "f32"),    # empty rows
 ])
 def test_csr_block_product(torch, sk, m, n, dens, ones, dense_col, empty_rows, vdt):
     """The one-pass sparse product (column blocks, coefficients in LDS, rows
