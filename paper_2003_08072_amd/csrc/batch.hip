@@ -128,14 +128,21 @@ class Engine {
   }
 
   // Queue an LP from its current iterate (thread-safe); e lives until e->done.
-  void add(Entry* e) {
+  // Returns the engine's fatal status instead (nothing queued) once an error
+  // has stopped it.
+  int add(Entry* e) {
     memset(e->res, 0, sizeof(*e->res));
     e->b = BatchLp{};
     std::lock_guard<std::mutex> g(mu_);
+    if (fatal_ != SKIPM_OK) {
+      e->res->status = fatal_;
+      return fatal_;
+    }
     ++outstanding_;
     live_.push_back(e);
     tasks_.push_back({e, false});
     cv_.notify_all();
+    return SKIPM_OK;
   }
 
   // Wait for every queued LP, then end the threads.  After a fatal error the
@@ -193,6 +200,30 @@ class Engine {
     }
   }
 
+  // Called by each engine thread as it ends.  After an error the threads end
+  // with LPs still queued or in the CG; the last thread out (no other thread
+  // can then hold an LP) ends those LPs with the error, so that their owners
+  // (a waiting request of the server) learn of it instead of waiting on.
+  void thread_exit(hipStream_t s) {
+    std::vector<Entry*> left;
+    int rc = SKIPM_OK;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      if (++exited_ < nthreads_ + 1 || fatal_ == SKIPM_OK) return;
+      rc = fatal_;
+      left.swap(live_);
+      tasks_.clear();
+      ready_.clear();
+      outstanding_ = 0;
+    }
+    for (Entry* e : left) {
+      e->res->status = rc;
+      e->b.rc = rc;
+      e->b.active = false;
+      if (e->done) e->done(e, s);
+    }
+  }
+
   void worker(int t) {
     (void)hipSetDevice(dev_);
     hipStream_t s = streams_[t];
@@ -203,7 +234,7 @@ class Engine {
         cv_.wait(lk, [&] {
           return fatal_ != SKIPM_OK || !tasks_.empty() || (stop_ && outstanding_ == 0);
         });
-        if (fatal_ != SKIPM_OK || tasks_.empty()) return;
+        if (fatal_ != SKIPM_OK || tasks_.empty()) break;
         task = tasks_.front();
         tasks_.pop_front();
       }
@@ -236,6 +267,7 @@ class Engine {
       }
       cv_.notify_all();
     }
+    thread_exit(s);
   }
 
   // The executor: the grouped CG of the LPs that are ready, chunk by chunk.
@@ -251,9 +283,9 @@ class Engine {
           cv_.wait(lk, [&] {
             return !ready_.empty() || fatal_ != SKIPM_OK || (stop_ && outstanding_ == 0);
           });
-        if (fatal_ != SKIPM_OK) return;
+        if (fatal_ != SKIPM_OK) break;
         if (in_cg.empty() && ready_.empty()) {
-          if (stop_ && outstanding_ == 0) return;
+          if (stop_ && outstanding_ == 0) break;
           continue;
         }
         fresh.assign(ready_.begin(), ready_.end());
@@ -264,9 +296,12 @@ class Engine {
         std::lock_guard<std::mutex> g(mu_);
         set_fatal(rc, skipm_last_error());
         cv_.notify_all();
-        return;
+        break;
       }
     }
+    // an error leaves this thread's LPs with the last thread out
+    (void)hipStreamSynchronize(cg_st_);
+    thread_exit(cg_st_);
   }
 
   // Set up the newcomers' CG, then one chunk of grouped iterations for all
@@ -478,6 +513,7 @@ class Engine {
   std::deque<Entry*> ready_;
   std::vector<Entry*> live_;
   int outstanding_ = 0;
+  int exited_ = 0;  // engine threads that have ended
   bool stop_ = false;
   int fatal_ = SKIPM_OK;
   std::string fatal_msg_;
@@ -715,8 +751,9 @@ void skipm_server_s::worker_main() {
         o.rc = e->b.rc;
         finish(r, e->lp, o, s);
       };
-      engine->add(&r->entry);
-      continue;
+      if (engine->add(&r->entry) == SKIPM_OK) continue;
+      // the engine stopped on an error: this request (its LP untouched) is
+      // solved on the slot
     }
     rc = lp_solve(lp, &oc.res, st);
     if (rc == SKIPM_ENOTCONV || rc == SKIPM_ESTALL || rc == SKIPM_ERANK || rc == SKIPM_ENAN)
