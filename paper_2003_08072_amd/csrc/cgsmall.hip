@@ -30,9 +30,7 @@ constexpr int kNW = kNT / 64;
 
 template <int G>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  return lane_group_sum<G>(v);
 }
 
 // Sum over the workgroup in a fixed order (butterfly per wave, waves in

@@ -64,11 +64,9 @@ __device__ __forceinline__ double widen(unsigned short b) {
   return (double)__uint_as_float((unsigned)b << 16);
 }
 
-template <int G, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  return lane_group_sum<G>(v);
 }
 
 struct Args {
