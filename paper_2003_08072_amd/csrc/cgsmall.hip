@@ -33,15 +33,12 @@ __device__ __forceinline__ double gsum(double v) {
   return lane_group_sum<G>(v);
 }
 
-// Sum over the workgroup in a fixed order (butterfly per wave, waves in
+// Sum over the workgroup in a fixed order (fixed sum per wave, waves in
 // order); every thread returns the total.
 __device__ __forceinline__ void block_sum2(double& a, double& b, double (*red)[2], int lane,
                                            int wid) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    a += __shfl_xor(a, off, 64);
-    b += __shfl_xor(b, off, 64);
-  }
+  a = lane_group_sum<64>(a);
+  b = lane_group_sum<64>(b);
   __syncthreads();  // red may still be read from the previous use
   if (lane == 0) {
     red[wid][0] = a;

@@ -17,7 +17,7 @@
 // Layout: a group of G lanes owns one column at a time; lane l of the group
 // holds rows (r*G + l)*V .. +V-1 for r < R, read as one 16-byte vector per r,
 // so a group reads a column with fully coalesced 16-byte-per-lane loads.  The
-// column's dot is a butterfly over the G lanes.  Each workgroup streams a
+// column's dot is summed over the G lanes by DPP moves.  Each workgroup streams a
 // contiguous range of columns (next column prefetched into registers), keeps
 // its accumulators in registers, folds its waves together through LDS in a
 // fixed order and writes one partial vector; launch_finish sums the partials
@@ -258,7 +258,7 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
   if (cg && (MODE == COL_NORMAL || MODE == COL_DOT)) {
     const int64_t k = a.cg.k;
     if (wid == 0) {
-      // sum over p = lane, lane + 64, ... in that order, then a butterfly
+      // sum over p = lane, lane + 64, ... in that order, then over the wave
       double s0 = 0, s1 = 0;
 #pragma unroll
       for (int q = 0; q < kPre; ++q) {
@@ -270,11 +270,8 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
         s0 += pv[(int64_t)p * pst];
         if (cg_open) s1 += pv[(int64_t)p * pst + 1];
       }
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        s0 += __shfl_xor(s0, off, 64);
-        s1 += __shfl_xor(s1, off, 64);
-      }
+      s0 = lane_group_sum<64>(s0);
+      s1 = lane_group_sum<64>(s1);
       if (lane == 0) {
         cgs[0] = s0;
         cgs[1] = s1;
@@ -427,11 +424,8 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
   }
   if (NACC == 0) {
     if (cg && MODE == COL_DOT) {  // block partials of r^T z, r^T r in a fixed order
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        cg_pz += __shfl_xor(cg_pz, off, 64);
-        cg_pr += __shfl_xor(cg_pr, off, 64);
-      }
+      cg_pz = lane_group_sum<64>(cg_pz);
+      cg_pr = lane_group_sum<64>(cg_pr);
       if (lane == 0) {
         sred[wid][0] = cg_pz;
         sred[wid][1] = cg_pr;

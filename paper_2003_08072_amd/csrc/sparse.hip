@@ -20,11 +20,7 @@ namespace {
 
 constexpr int kMaxRowsLds = (int)kMaxM;
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wsum(double v) { return lane_group_sum<64>(v); }
 
 // rowptr monotone from 0 to nnz, column indices in range and strictly
 // increasing inside each row.  One thread per row.
@@ -191,8 +187,8 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
   }
   // wave 0 of a pass that opens a CG iteration requests the partial sums
   // (up to kPre per lane; any further ones in a loop) before it reads the
-  // done flag, and sums them in the order p = lane, lane + 64, ..., then a
-  // butterfly: the same sums in the same order in every workgroup, hence the
+  // done flag, and sums them in the order p = lane, lane + 64, ..., then over
+  // the wave: the same sums in the same order in every workgroup, hence the
   // same decision
   if (cg_open && threadIdx.x < 64) {
     constexpr int kPre = 4;
@@ -217,11 +213,8 @@ __global__ __launch_bounds__(256) void k_csc_dot(CscArgs a) {
       s0 += a.cg.prz[2 * p];
       s1 += a.cg.prz[2 * p + 1];
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      s0 += __shfl_xor(s0, off, 64);
-      s1 += __shfl_xor(s1, off, 64);
-    }
+    s0 = lane_group_sum<64>(s0);
+    s1 = lane_group_sum<64>(s1);
     if (lane == 0) {
       sred[0][0] = s0;
       sred[0][1] = s1;

@@ -354,11 +354,8 @@ __global__ __launch_bounds__(kSbThreads) void k_sb_normal(SbArgs a) {
         s0 += a.cg.prz[2 * p];
         s1 += a.cg.prz[2 * p + 1];
       }
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        s0 += __shfl_xor(s0, off, 64);
-        s1 += __shfl_xor(s1, off, 64);
-      }
+      s0 = lane_group_sum<64>(s0);
+      s1 = lane_group_sum<64>(s1);
       if (lane == 0) {
         sred[0] = s0;
         sred[1] = s1;

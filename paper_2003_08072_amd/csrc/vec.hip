@@ -1,7 +1,7 @@
 // Vector kernels: fills and copies, the single-workgroup CG state updates, and
 // the n-vector passes of one IPM iteration (correction vector and primal
 // direction, step length, update).  Every reduction runs in a fixed order
-// (per-thread sequential, fixed butterfly inside a wave, waves in index
+// (per-thread sequential, a fixed DPP sum inside a wave, waves in index
 // order, workgroup partials summed in index order), so results are bitwise
 // reproducible run to run.
 #include <math.h>
@@ -15,11 +15,7 @@ namespace {
 constexpr int kVecThreads = 256;
 constexpr int kVecBlocksMax = 1024;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return lane_group_sum<64>(v); }
 
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
@@ -218,11 +214,8 @@ __global__ __launch_bounds__(64) void k_cg_close(const double* __restrict__ prz,
     s0 += prz[2 * p];
     s1 += prz[2 * p + 1];
   }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
-  }
+  s0 = lane_group_sum<64>(s0);
+  s1 = lane_group_sum<64>(s1);
   if (lane == 0) {
     sc[S_CG_RZ] = s0;
     sc[S_V_RR] = s1;
@@ -242,11 +235,8 @@ __global__ __launch_bounds__(64) void k_cg_close_grouped(const CgCloseArgs* __re
     s0 += g.prz[2 * p];
     s1 += g.prz[2 * p + 1];
   }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
-  }
+  s0 = lane_group_sum<64>(s0);
+  s1 = lane_group_sum<64>(s1);
   if (lane == 0) {
     g.sc[S_CG_RZ] = s0;
     g.sc[S_V_RR] = s1;
