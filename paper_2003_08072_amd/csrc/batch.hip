@@ -39,9 +39,9 @@ int default_workers(int count) { return std::max(1, std::min(count, 8)); }
 //     retries, epilogue, correction vector, step), then straight into the
 //     start of its next iteration;
 //   - one executor runs the CG of every LP that is ready, in grouped
-//     launches: per CG iteration one launch per pass and lane-group shape
-//     (product pass, finish, Q^{-1} pass), whose work list is the (LP,
-//     workgroup) pairs of its LPs.  Every LP keeps the workgroup count,
+//     launches: per CG iteration one launch per pass (product pass, finish,
+//     Q^{-1} pass) and block size / register class of the LPs' lane-group
+//     shapes, whose work list is the (LP, workgroup) pairs of its LPs.  Every LP keeps the workgroup count,
 //     column ranges, partial sums and CG iteration index of its own launches,
 //     so its arithmetic is that of a lone solve.  LPs join the launches when
 //     their set-up is done and leave them at the host check after their done

@@ -25,6 +25,8 @@
 #include <hip/hip_ext.h>
 #include <string.h>
 
+#include <utility>
+
 #include "common.h"
 
 namespace skipm {
@@ -89,25 +91,43 @@ struct Args {
   const double* sc;
   const int32_t* done;
   CgFuse cg;
+  int shape = 0;  // grouped launches: the matrix's lane-group shape (index into kGShapes)
+};
+
+// LDS of one pass: the wave fold's buffer (with many waves, each wave parks
+// its sums in its own LDS row and the rows are added in one step; otherwise,
+// or when that would take more than 64 KB, the waves add into one row in
+// turn), per-wave scalar sums and the CG's two opening sums.
+template <typename TA, typename TC, int G, int R, int MODE, int NT>
+struct ColLds {
+  static constexpr int V = Vec<TA>::V;
+  static constexpr int NW = NT / 64;
+  static constexpr int NACC = MODE == COL_PROLOGUE ? 2 : (MODE == COL_DOT ? 0 : 1);
+  static constexpr int NACC1 = NACC > 0 ? NACC : 1;
+  static constexpr int LROWS = G * R * V;
+  static constexpr bool kOneStep = NW >= 8 && NW * LROWS * sizeof(TC) <= 65536;
+  static constexpr int kLbuf = kOneStep ? NW * LROWS : NACC1 * LROWS;  // TC entries
+  static constexpr size_t kSred = (size_t)kLbuf * sizeof(TC);          // byte offsets
+  static constexpr size_t kCgs = kSred + (size_t)NW * 4 * sizeof(double);
+  static constexpr size_t kBytes = kCgs + 2 * sizeof(double);
 };
 
 // The pass of workgroup `bid` of one matrix (its column range, its partial):
-// the body of k_colpass, and of k_colpass_grouped for each matrix of a group.
+// the body of k_colpass, and of the grouped kernels for each matrix of a
+// group; `smem` is the caller's LDS of at least ColLds<...>::kBytes.
 template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
-__device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
+__device__ __forceinline__ void colpass_body(const Args& a, const int bid, char* smem) {
+  typedef ColLds<TA, TC, G, R, MODE, NT> L;
   constexpr int V = Vec<TA>::V;
   typedef typename Vec<TA>::type VT;
   constexpr int NGW = 64 / G;
   constexpr int NW = NT / 64;
-  constexpr int NACC = MODE == COL_PROLOGUE ? 2 : (MODE == COL_DOT ? 0 : 1);
-  constexpr int NACC1 = NACC > 0 ? NACC : 1;
-  constexpr int LROWS = G * R * V;
-  // Wave fold of the partial sums: with many waves, each wave parks its sums in
-  // its own LDS row and the rows are added in one step; otherwise (or when
-  // that would take more than 64 KB) the waves add into one row in turn.
-  constexpr bool kOneStep = NW >= 8 && NW * LROWS * sizeof(TC) <= 65536;
-  __shared__ TC lbuf[kOneStep ? NW * LROWS : NACC1 * LROWS];
-  __shared__ double sred[NW][4];
+  constexpr int NACC = L::NACC;
+  constexpr int NACC1 = L::NACC1;
+  constexpr int LROWS = L::LROWS;
+  constexpr bool kOneStep = L::kOneStep;
+  TC* lbuf = (TC*)smem;
+  double(*sred)[4] = (double(*)[4])(smem + L::kSred);
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / G, lg = lane % G;
@@ -253,7 +273,7 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
 
   // fused CG bookkeeping at the start of the pass (every block computes the
   // same sums in the same order, so every block takes the same decision)
-  __shared__ double cgs[2];
+  double* cgs = (double*)(smem + L::kCgs);
   double cg_beta = 0, cg_alpha = 0;
   if (cg && (MODE == COL_NORMAL || MODE == COL_DOT)) {
     const int64_t k = a.cg.k;
@@ -512,32 +532,8 @@ __device__ __forceinline__ void colpass_body(const Args& a, const int bid) {
 
 template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
 __global__ __launch_bounds__(NT) void k_colpass(Args a) {
-  colpass_body<TA, TC, G, R, MODE, NT, STREAM>(a, blockIdx.x);
-}
-
-// The same pass over several matrices of one lane-group shape in one launch
-// (the CG of a batch of LPs): first[i] is the first workgroup of matrix i
-// (first[nmat] the total), each matrix keeps its own workgroup count, column
-// ranges and partials, so its arithmetic is that of its own launch.  Matrix
-// i is at CG iteration kstart[i] + j and takes the arguments of that
-// iteration's parity, args[2 i + (k & 1)]; a pass outside the CG (kstart
-// null) takes args[i].
-template <typename TA, typename TC, int G, int R, int MODE, int NT, bool STREAM>
-__global__ __launch_bounds__(NT) void k_colpass_grouped(const Args* __restrict__ args,
-                                                        const int32_t* __restrict__ first,
-                                                        int nmat,
-                                                        const int64_t* __restrict__ kstart,
-                                                        int j) {
-  int lo = 0, hi = nmat - 1;  // the matrix whose workgroup range holds blockIdx.x
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (first[mid] <= (int)blockIdx.x) lo = mid;
-    else hi = mid - 1;
-  }
-  const int64_t k = kstart ? kstart[lo] + j : 0;
-  Args a = args[kstart ? 2 * lo + (int)(k & 1) : lo];
-  a.cg.k = k;
-  colpass_body<TA, TC, G, R, MODE, NT, STREAM>(a, (int)blockIdx.x - first[lo]);
+  __shared__ __attribute__((aligned(16))) char smem[ColLds<TA, TC, G, R, MODE, NT>::kBytes];
+  colpass_body<TA, TC, G, R, MODE, NT, STREAM>(a, blockIdx.x, smem);
 }
 
 // B[:, b] = sum over the (sorted) items of bucket b of sign * d_j * A[:, j]
@@ -978,29 +974,114 @@ Args to_args(const ColPass& c) {
   return a;
 }
 
+// The lane-group shapes (G, R) of the grouped launches; Args::shape indexes
+// this table.
+constexpr int kGShapes[][2] = {{16, 1}, {16, 2}, {64, 1}, {64, 2},  {64, 3},
+                               {64, 4}, {64, 6}, {64, 8}, {64, 12}, {64, 16}};
+constexpr int kNGShapes = (int)(sizeof(kGShapes) / sizeof(kGShapes[0]));
+
+// Register class of a shape: the shapes of one launch share its register
+// count, the largest that one of them needs, so that shapes of a few
+// registers do not run at the occupancy of those of many.
+constexpr int gshape_cls(int R) { return R <= 2 ? 0 : (R <= 4 ? 1 : (R <= 8 ? 2 : 3)); }
+
+// Shape i runs in the grouped kernel of block size NT (the block size its own
+// launch would take) and register class CLS, for values TA.
+template <typename TA, int MODE, int NT, int CLS>
+constexpr bool gshape_in(int i) {
+  return kGShapes[i][0] * kGShapes[i][1] * Vec<TA>::V <= kMaxM &&
+         threads_for(MODE, kGShapes[i][1], Vec<TA>::V, 8) == NT &&
+         gshape_cls(kGShapes[i][1]) == CLS;
+}
+template <typename TA, int MODE, int NT, int CLS, int I>
+constexpr size_t gshape_lds() {
+  if constexpr (gshape_in<TA, MODE, NT, CLS>(I))
+    return ColLds<TA, double, kGShapes[I][0], kGShapes[I][1], MODE, NT>::kBytes;
+  else
+    return 0;
+}
+template <typename TA, int MODE, int NT, int CLS, int... I>
+constexpr size_t gshapes_lds(std::integer_sequence<int, I...>) {
+  size_t b = 16;
+  ((b = gshape_lds<TA, MODE, NT, CLS, I>() > b ? gshape_lds<TA, MODE, NT, CLS, I>() : b), ...);
+  return b;
+}
+
+// One pass over several matrices in one launch (the CG of a batch of LPs):
+// first[i] is the first workgroup of matrix i (first[nmat] the total), each
+// matrix keeps its own lane-group shape, workgroup count, column ranges and
+// partials, so its arithmetic is that of its own launch; the matrices of
+// every shape whose own launch takes NT threads and that is of register
+// class CLS share the launch, and the workgroup's LDS is the largest that
+// one of them needs.  Matrix i is at CG
+// iteration kstart[i] + j and takes the arguments of that iteration's parity,
+// args[2 i + (k & 1)]; a pass outside the CG (kstart null) takes args[i].
+template <typename TA, int MODE, int NT, int CLS, bool STREAM>
+__global__ __launch_bounds__(NT) void k_colpass_grouped(const Args* __restrict__ args,
+                                                        const int32_t* __restrict__ first,
+                                                        int nmat,
+                                                        const int64_t* __restrict__ kstart,
+                                                        int j) {
+  int lo = 0, hi = nmat - 1;  // the matrix whose workgroup range holds blockIdx.x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t k = kstart ? kstart[lo] + j : 0;
+  Args a = args[kstart ? 2 * lo + (int)(k & 1) : lo];
+  a.cg.k = k;
+  const int bid = (int)blockIdx.x - first[lo];
+  constexpr size_t kLds =
+      gshapes_lds<TA, MODE, NT, CLS>(std::make_integer_sequence<int, kNGShapes>{});
+  __shared__ __attribute__((aligned(16))) char smem[kLds];
+#define SK_GCASE(I)                                                                      \
+  if constexpr (gshape_in<TA, MODE, NT, CLS>(I)) {                                       \
+    if (a.shape == I) {                                                                  \
+      colpass_body<TA, double, kGShapes[I][0], kGShapes[I][1], MODE, NT, STREAM>(a, bid, \
+                                                                                 smem);  \
+      return;                                                                            \
+    }                                                                                    \
+  }
+  SK_GCASE(0) SK_GCASE(1) SK_GCASE(2) SK_GCASE(3) SK_GCASE(4)
+  SK_GCASE(5) SK_GCASE(6) SK_GCASE(7) SK_GCASE(8) SK_GCASE(9)
+#undef SK_GCASE
+}
+
+template <typename TA, int MODE, int NT, int CLS>
+void launch_grouped(const ColKey& k, const Args* args, const int32_t* first, int nmat, int total,
+                    const int64_t* kstart, int kit, hipStream_t st) {
+  if constexpr (stream_mode(MODE)) {
+    if (k.nt) {
+      hipLaunchKernelGGL((k_colpass_grouped<TA, MODE, NT, CLS, true>), dim3(total), dim3(NT), 0,
+                         st, args, first, nmat, kstart, kit);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_colpass_grouped<TA, MODE, NT, CLS, false>), dim3(total), dim3(NT), 0, st,
+                     args, first, nmat, kstart, kit);
+}
+
+template <typename TA, int MODE, int NT>
+int dispatch_cls(const ColKey& k, const Args* args, const int32_t* first, int nmat, int total,
+                 const int64_t* kstart, int kit, hipStream_t st) {
+  switch (k.cls) {
+    case 0: launch_grouped<TA, MODE, NT, 0>(k, args, first, nmat, total, kstart, kit, st); return 0;
+    case 1: launch_grouped<TA, MODE, NT, 1>(k, args, first, nmat, total, kstart, kit, st); return 0;
+    case 2: launch_grouped<TA, MODE, NT, 2>(k, args, first, nmat, total, kstart, kit, st); return 0;
+    case 3: launch_grouped<TA, MODE, NT, 3>(k, args, first, nmat, total, kstart, kit, st); return 0;
+  }
+  return -1;
+}
+
 template <typename TA, int MODE>
 int dispatch_grouped(const ColKey& k, const Args* args, const int32_t* first, int nmat, int total,
                      const int64_t* kstart, int kit, hipStream_t st) {
-#define SK_GCASE(GG, RR)                                                                    \
-  if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                                            \
-    if (k.G == GG && k.R == RR) {                                                           \
-      constexpr int NT = threads_for(MODE, RR, Vec<TA>::V, 8);                              \
-      if constexpr (stream_mode(MODE)) {                                                    \
-        if (k.nt) {                                                                         \
-          hipLaunchKernelGGL((k_colpass_grouped<TA, double, GG, RR, MODE, NT, true>),      \
-                             dim3(total), dim3(NT), 0, st, args, first, nmat, kstart, kit); \
-          return 0;                                                                         \
-        }                                                                                   \
-      }                                                                                     \
-      hipLaunchKernelGGL((k_colpass_grouped<TA, double, GG, RR, MODE, NT, false>), dim3(total), \
-                         dim3(NT), 0, st, args, first, nmat, kstart, kit);                  \
-      return 0;                                                                             \
-    }                                                                                       \
+  switch (k.threads) {
+    case 1024: return dispatch_cls<TA, MODE, 1024>(k, args, first, nmat, total, kstart, kit, st);
+    case 512: return dispatch_cls<TA, MODE, 512>(k, args, first, nmat, total, kstart, kit, st);
+    case 256: return dispatch_cls<TA, MODE, 256>(k, args, first, nmat, total, kstart, kit, st);
   }
-  SK_GCASE(16, 1) SK_GCASE(16, 2)
-  SK_GCASE(64, 1) SK_GCASE(64, 2) SK_GCASE(64, 3) SK_GCASE(64, 4)
-  SK_GCASE(64, 6) SK_GCASE(64, 8) SK_GCASE(64, 12) SK_GCASE(64, 16)
-#undef SK_GCASE
   return -1;
 }
 
@@ -1015,13 +1096,17 @@ int colpass_prepare(ColPass& c, void* args_out, ColKey* key) {
     c.nblk = c.mode == COL_DOT ? colpass_nblk_dot(c.lda, c.n, c.ta)
                                : colpass_nblk(c.lda, c.n, c.ta, c.tc, c.mode);
   const Shape sh = pick_shape(c.lda, vec_width(c.ta));
-  if (sh.G == 0) return -1;
+  int shape = -1;
+  for (int i = 0; i < kNGShapes; ++i)
+    if (kGShapes[i][0] == sh.G && kGShapes[i][1] == sh.R) shape = i;
+  if (shape < 0) return -1;
   key->ta = c.ta;
   key->mode = c.mode;
-  key->G = sh.G;
-  key->R = sh.R;
+  key->threads = threads_for(c.mode, sh.R, vec_width(c.ta), 8);
+  key->cls = gshape_cls(sh.R);
   key->nt = c.mode == COL_NORMAL && c.nt != 0;
-  const Args a = to_args(c);
+  Args a = to_args(c);
+  a.shape = shape;
   memcpy(args_out, &a, sizeof(Args));
   return c.nblk;
 }

@@ -209,17 +209,18 @@ struct ColPass {
 enum { COL_NORMAL = 0, COL_PROLOGUE = 1, COL_EPILOGUE = 2, COL_DOT = 3, COL_AXPY = 4 };
 int launch_colpass(ColPass& a, hipStream_t st);
 
-// Grouped passes: the CG passes of many LPs in one launch per lane-group shape.
-// colpass_prepare fills the kernel arguments of one pass (colpass_args_bytes()
-// bytes, to be copied to the device) and the shape key; returns its
-// workgroup count, or -1 for a pass the grouped kernels do not cover (only
-// COL_NORMAL and COL_DOT over FP64 / FP32 values).  Passes launched together
-// must share the key.
+// Grouped passes: the CG passes of many LPs in one launch per pass, block
+// size and register class; each matrix keeps its own lane-group shape,
+// carried in its argument block.  colpass_prepare fills the kernel arguments of one pass
+// (colpass_args_bytes() bytes, to be copied to the device) and the launch
+// key; returns its workgroup count, or -1 for a pass the grouped kernels do
+// not cover (only COL_NORMAL and COL_DOT over FP64 / FP32 values).  Passes
+// launched together must share the key.
 struct ColKey {
-  int ta = 0, mode = 0, G = 0, R = 0;
+  int ta = 0, mode = 0, threads = 0, cls = 0;
   bool nt = false;
   bool operator==(const ColKey& o) const {
-    return ta == o.ta && mode == o.mode && G == o.G && R == o.R && nt == o.nt;
+    return ta == o.ta && mode == o.mode && threads == o.threads && cls == o.cls && nt == o.nt;
   }
 };
 size_t colpass_args_bytes();
