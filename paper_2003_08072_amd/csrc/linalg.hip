@@ -499,14 +499,29 @@ __global__ __launch_bounds__(1024) void k_shift_trace(double* __restrict__ G, in
 
 }  // namespace
 
-// Splits of the Gram along the columns of B: about two workgroups per CU,
-// slices of at least 64 columns, and at most 64 MiB of partials.
+// Splits of the Gram along the columns of B: at most 16, slices of at least
+// 64 columns, at most 64 MiB of partials; among those, the count with the
+// least estimated time, in columns of one workgroup: rounds of 256
+// workgroups (one per CU: a CU that runs two runs each at about half rate)
+// times the columns per split, plus the finish's read of the partials
+// (about 8 columns' time per 1024 x 1024 partial).  At m = 1000 (36 tiles),
+// 7 splits in one round take 110 us where 8 (288 workgroups) took 146.
 int gram_ksplit(int64_t mp, int64_t w) {
   const int64_t T = (mp + kRT - 1) / kRT, ntiles = T * (T + 1) / 2;
-  int64_t ks = std::min<int64_t>(16, 512 / ntiles);
-  ks = std::min<int64_t>(ks, w / 64);
-  ks = std::min<int64_t>(ks, (int64_t)(64ll << 20) / (8 * mp * mp));
-  return (int)std::max<int64_t>(1, ks);
+  int64_t kmax = std::min<int64_t>(16, w / 64);
+  kmax = std::min<int64_t>(kmax, (int64_t)(64ll << 20) / (8 * mp * mp));
+  int64_t best = 1;
+  double best_cost = HUGE_VAL;
+  for (int64_t ks = 1; ks <= kmax; ++ks) {
+    const int64_t cps = ((w + ks - 1) / ks + 15) / 16 * 16;
+    const int64_t rounds = (ntiles * ks + 255) / 256;
+    const double cost = (double)(rounds * cps) + (double)ks * (double)(mp * mp) / 131072.0;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ks;
+    }
+  }
+  return (int)best;
 }
 
 void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart, int ksplit,
