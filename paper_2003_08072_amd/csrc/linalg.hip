@@ -168,138 +168,50 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Panel step k, one wave of NB lanes per block.  Every block factors G_kk with
-// lane i holding row i in registers (left-looking: column p needs row p's
-// finished entries, taken from lane p by readlane), then keeps L_kk in LDS.
-// Block 0 forms X_kk = L_kk^{-1} (lane c solves column c by forward
-// substitution, reading L_kk by LDS broadcast) and stores it in Xb; block
-// b > 0 solves L_kk y = G_ik[r, :]^T for its rows r (lane r), i.e.
-// L_ik = G_ik L_kk^{-T}, in place.
-template <int NB>
-__global__ __launch_bounds__(NB) void k_chol_panel(double* __restrict__ G, double* __restrict__ Xb,
-                                                   int64_t mp, int k,
-                                                   int32_t* __restrict__ fail) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double rdiag[NB];
-  const int lane = threadIdx.x;
-  const int64_t K0 = (int64_t)k * NB;
-  double a[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) a[j] = G[(K0 + lane) + (K0 + j) * mp];
-  bool bad = false;
-#pragma unroll
-  for (int p = 0; p < NB; ++p) {
-    double s = a[p];
-#pragma unroll
-    for (int q = 0; q < p; ++q) s -= a[q] * readlane_d(a[q], p);
-    double d = readlane_d(s, p);
-    if (!(d > 0.0)) {
-      bad = true;
-      d = 1e-300;
-    }
-    const double lpp = sqrt(d);
-    a[p] = lane > p ? s / lpp : (lane == p ? lpp : 0.0);
-  }
-  if (bad && lane == 0) atomicOr(fail, 1);
-#pragma unroll
-  for (int j = 0; j < NB; ++j) Ls[lane][j] = a[j];
-  __syncthreads();
-  rdiag[lane] = 1.0 / Ls[lane][lane];
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    // column `lane` of L_kk^{-1}
-    double x[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double s = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-      for (int q = 0; q < i; ++q) s -= Ls[i][q] * x[q];
-      x[i] = s * rdiag[i];
-    }
-    __syncthreads();
-    // stage through LDS (transpose) for coalesced stores of the column-major tile
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Ls[i][lane] = x[i];
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Xb[(K0 + lane) + (K0 + c) * mp] = Ls[lane][c];
-    return;
-  }
-  const int64_t I0 = K0 + (int64_t)blockIdx.x * NB;
-  double y[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) y[c] = G[(I0 + lane) + (K0 + c) * mp];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    double s = y[c];
-#pragma unroll
-    for (int q = 0; q < c; ++q) s -= Ls[c][q] * y[q];
-    y[c] = s * rdiag[c];
-  }
-#pragma unroll
-  for (int c = 0; c < NB; ++c) G[(I0 + lane) + (K0 + c) * mp] = y[c];
-}
-
-// C[I, J] (+)= sign * sum_q A[I, q-block] B[J, q-block]^T over a range of q
-// blocks, with NB x NB tiles staged through LDS (16 x 16 threads, TW x TW each).
+// One NB x NB output tile (NB = 32) of a product of tiles staged through LDS,
+// on the FP64 matrix cores: wave w of the workgroup's four owns the 16 x 16
+// quadrant (w >> 1, w & 1) and takes one v_mfma_f64_16x16x4 per four values
+// of the inner index q (in lane l: A[l%16][l/16] of the 16 x 4 block,
+// B[l/16][l%16] of the 4 x 16 block; D[l/16 + 4r][l%16] in element r of the
+// accumulator).  Every entry is a sum over q in increasing order.
 template <int NB>
 struct TileAcc {
-  static constexpr int TW = NB / 16;
-  double acc[TW][TW];
-  __device__ void zero() {
-#pragma unroll
-    for (int p = 0; p < TW; ++p)
-#pragma unroll
-      for (int o = 0; o < TW; ++o) acc[p][o] = 0.0;
+  static_assert(NB == 32, "four waves of 16 x 16 quadrants");
+  dacc4 acc;
+  int i0, j0, li, lk;
+  __device__ TileAcc() {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    i0 = 16 * (w >> 1);
+    j0 = 16 * (w & 1);
+    li = lane & 15;
+    lk = lane >> 4;
+    acc = (dacc4)0.0;
   }
+  __device__ void zero() { acc = (dacc4)0.0; }
   // acc += At * Bt^T   (At, Bt: NB x NB tiles in LDS, row index first)
   __device__ void mma_nt(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (int q = 0; q < NB; ++q) {
-      double a[TW], b[TW];
 #pragma unroll
-      for (int p = 0; p < TW; ++p) {
-        a[p] = At[ty * TW + p][q];
-        b[p] = Bt[tx * TW + p][q];
-      }
-#pragma unroll
-      for (int p = 0; p < TW; ++p)
-#pragma unroll
-        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
-    }
+    for (int q0 = 0; q0 < NB; q0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(At[i0 + li][q0 + lk], Bt[j0 + li][q0 + lk], acc,
+                                                 0, 0, 0);
   }
   // acc += At^T * Bt
   __device__ void mma_tn(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (int q = 0; q < NB; ++q) {
-      double a[TW], b[TW];
 #pragma unroll
-      for (int p = 0; p < TW; ++p) {
-        a[p] = At[q][ty * TW + p];
-        b[p] = Bt[q][tx * TW + p];
-      }
-#pragma unroll
-      for (int p = 0; p < TW; ++p)
-#pragma unroll
-        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
-    }
+    for (int q0 = 0; q0 < NB; q0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(At[q0 + lk][i0 + li], Bt[q0 + lk][j0 + li], acc,
+                                                 0, 0, 0);
   }
   // acc += At * Bt
   __device__ void mma_nn(double (*At)[NB + 1], double (*Bt)[NB + 1]) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (int q = 0; q < NB; ++q) {
-      double a[TW], b[TW];
 #pragma unroll
-      for (int p = 0; p < TW; ++p) {
-        a[p] = At[ty * TW + p][q];
-        b[p] = Bt[q][tx * TW + p];
-      }
-#pragma unroll
-      for (int p = 0; p < TW; ++p)
-#pragma unroll
-        for (int o = 0; o < TW; ++o) acc[p][o] += a[p] * b[o];
-    }
+    for (int q0 = 0; q0 < NB; q0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(At[i0 + li][q0 + lk], Bt[q0 + lk][j0 + li], acc,
+                                                 0, 0, 0);
   }
+  // the tile row and column of element r of the accumulator
+  __device__ int row(int r) const { return i0 + lk + 4 * r; }
+  __device__ int col() const { return j0 + li; }
 };
 
 template <int NB>
@@ -311,33 +223,179 @@ __device__ void load_tile(double (*Tt)[NB + 1], const double* __restrict__ M, in
   }
 }
 
-// Trailing update of step k: G_ij -= L_ik L_jk^T for k < j <= i (lower triangle).
+// One NB x NB tile in the registers of a 256-thread workgroup (element
+// threadIdx.x + 256 q at row e % NB, column e / NB, as load_tile), so that
+// the loops over tile products below request kTileAhead tiles' loads at once
+// and wait for their latency once per batch instead of once per tile.
+constexpr int kTileAhead = 8;
 template <int NB>
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int64_t mp, int k) {
-  __shared__ double Ai[NB][NB + 1];
-  __shared__ double Aj[NB][NB + 1];
-  int t = blockIdx.x, di = 0;  // decode (di >= dj) over the trailing blocks
-  while (t > di) {
-    t -= di + 1;
-    ++di;
+struct TileRegs {
+  static constexpr int NE = NB * NB / 256;
+  double v[NE];
+  __device__ void load(const double* __restrict__ M, int64_t ld, int64_t r0, int64_t c0) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      v[q] = M[(r0 + e % NB) + (c0 + e / NB) * ld];
+    }
   }
-  const int bi = k + 1 + di, bj = k + 1 + t;
-  const int64_t K0 = (int64_t)k * NB, I0 = (int64_t)bi * NB, J0 = (int64_t)bj * NB;
-  load_tile<NB>(Ai, G, mp, I0, K0);
-  load_tile<NB>(Aj, G, mp, J0, K0);
+  // rows >= nrows or columns >= ncols of M read as zero
+  __device__ void load_masked(const double* __restrict__ M, int64_t ld, int64_t r0, int64_t c0,
+                              int64_t nrows, int64_t ncols) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int64_t gr = r0 + e % NB, gc = c0 + e / NB;
+      v[q] = (gr < nrows && gc < ncols) ? M[gr + gc * ld] : 0.0;
+    }
+  }
+  __device__ void store(double (*Tt)[NB + 1]) const {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Tt[e % NB][e / NB] = v[q];
+    }
+  }
+};
+
+// Trailing update of step kp on tile (bi, bj), bi >= bj > kp:
+// G_ij -= L_i,kp L_j,kp^T (all 256 threads of the workgroup).
+template <int NB>
+__device__ __forceinline__ void update_tile(double* __restrict__ G, int64_t mp, int kp, int bi,
+                                            int bj, double (*Ai)[NB + 1], double (*Aj)[NB + 1]) {
+  const int64_t P0 = (int64_t)kp * NB, I0 = (int64_t)bi * NB, J0 = (int64_t)bj * NB;
+  load_tile<NB>(Ai, G, mp, I0, P0);
+  load_tile<NB>(Aj, G, mp, J0, P0);
   __syncthreads();
   TileAcc<NB> ta;
-  ta.zero();
   ta.mma_nt(Ai, Aj);
-  constexpr int TW = NB / 16;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int p = 0; p < TW; ++p)
-#pragma unroll
-    for (int o = 0; o < TW; ++o) {
-      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
-      G[gi + gj * mp] -= ta.acc[p][o];
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gi = I0 + ta.row(r), gj = J0 + ta.col();
+    G[gi + gj * mp] -= ta.acc[r];
+  }
+}
+
+// Step k of the blocked factorisation, one launch of 256-thread workgroups.
+// Workgroups 0..rest (rest = T - k - 1) are the panel of column block k: each
+// first applies step k-1's update to the diagonal block and to its own block
+// of the column (the same sums, in the same order, as the tile update below),
+// then wave 0 factors G_kk with lane i holding row i in registers
+// (left-looking: column p needs row p's finished entries, taken from lane p by
+// readlane).  Workgroup 0 forms X_kk = L_kk^{-1} (lane c solves column c by
+// forward substitution, reading L_kk by LDS broadcast) and stores it in Xb;
+// workgroup b > 0 solves L_kk y = G_ik[r, :]^T for its rows r (lane r), i.e.
+// L_ik = G_ik L_kk^{-T}, in place.  The workgroups after those apply step
+// k-1's update to the trailing tiles right of column block k, so the panel
+// and the rest of the previous step's update share one launch.
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ G, double* __restrict__ Xb,
+                                                   int64_t mp, int k, int T,
+                                                   int32_t* __restrict__ fail) {
+  static_assert(NB == 32, "the panel keeps a 32 x 32 block in one wave's registers");
+  __shared__ double Ai[NB][NB + 1];
+  __shared__ double Aj[NB][NB + 1];
+  __shared__ double Dg[NB][NB + 1];
+  __shared__ double Yb[NB][NB + 1];
+  __shared__ double rdiag[NB];
+  const int rest = T - k - 1;
+  if ((int)blockIdx.x > rest) {  // trailing tile (di >= dj) of step k-1's update
+    int t = (int)blockIdx.x - rest - 1, di = 0;
+    while (t > di) {
+      t -= di + 1;
+      ++di;
     }
+    update_tile<NB>(G, mp, k - 1, k + 1 + di, k + 1 + t, Ai, Aj);
+    return;
+  }
+  const int bid = blockIdx.x;
+  const int64_t K0 = (int64_t)k * NB;
+  const int64_t I0 = K0 + (int64_t)bid * NB;  // block b > 0: its rows of column block k
+  load_tile<NB>(Dg, G, mp, K0, K0);
+  if (bid > 0) load_tile<NB>(Yb, G, mp, I0, K0);
+  if (k > 0) {
+    load_tile<NB>(Aj, G, mp, K0, K0 - NB);
+    if (bid > 0) load_tile<NB>(Ai, G, mp, I0, K0 - NB);
+  }
+  __syncthreads();
+  if (k > 0) {
+    TileAcc<NB> td, tb;
+    td.mma_nt(Aj, Aj);
+    if (bid > 0) tb.mma_nt(Ai, Aj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Dg[td.row(r)][td.col()] -= td.acc[r];
+      if (bid > 0) Yb[tb.row(r)][tb.col()] -= tb.acc[r];
+    }
+    __syncthreads();
+  }
+  // wave 0 factors G_kk; its lanes past NB repeat lane NB - 1 and store nothing
+  const int lane = threadIdx.x;
+  const int ln = lane < NB ? lane : NB - 1;
+  if (threadIdx.x < 64) {
+    double a[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[j] = Dg[ln][j];
+    bool bad = false;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      double s = a[p];
+#pragma unroll
+      for (int q = 0; q < p; ++q) s -= a[q] * readlane_d(a[q], p);
+      double d = readlane_d(s, p);
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1e-300;
+      }
+      const double lpp = sqrt(d);
+      a[p] = ln > p ? s / lpp : (ln == p ? lpp : 0.0);
+    }
+    if (bad && lane == 0) atomicOr(fail, 1);
+    // L_kk over the diagonal block (every lane has read its row)
+    if (lane < NB) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) Dg[lane][j] = a[j];
+    }
+  }
+  __syncthreads();
+  if (lane < NB) rdiag[lane] = 1.0 / Dg[lane][lane];
+  __syncthreads();
+  if (bid == 0) {
+    // column `lane` of L_kk^{-1}
+    double x[NB];
+    if (lane < NB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) s -= Dg[i][q] * x[q];
+        x[i] = s * rdiag[i];
+      }
+      // stage through LDS (transpose) for coalesced stores of the column-major tile
+#pragma unroll
+      for (int i = 0; i < NB; ++i) Ai[i][lane] = x[i];
+    }
+    __syncthreads();
+    if (lane < NB) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) Xb[(K0 + lane) + (K0 + c) * mp] = Ai[lane][c];
+    }
+    return;
+  }
+  if (lane < NB) {
+    double y[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) y[c] = Yb[lane][c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double s = y[c];
+#pragma unroll
+      for (int q = 0; q < c; ++q) s -= Dg[c][q] * y[q];
+      y[c] = s * rdiag[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) G[(I0 + lane) + (K0 + c) * mp] = y[c];
+  }
 }
 
 // X = L^{-1} from its diagonal blocks by recursive doubling.  At a level with
@@ -360,22 +418,27 @@ __global__ __launch_bounds__(256) void k_trinv_c(const double* __restrict__ G,
   if (bi >= nbb) return;
   const int64_t R0 = (int64_t)(b0 + bi) * NB, C0 = (int64_t)(a0 + ai) * NB;
   TileAcc<NB> ta;
-  ta.zero();
-  for (int j = ai; j < half; ++j) {
-    const int64_t J0 = (int64_t)(a0 + j) * NB;
-    __syncthreads();
-    load_tile<NB>(At, G, mp, R0, J0);   // L_(b0+bi),(a0+j)
-    load_tile<NB>(Bt, Xb, mp, J0, C0);  // X_(a0+j),(a0+ai)
-    __syncthreads();
-    ta.mma_nn(At, Bt);
+  for (int j0 = ai; j0 < half; j0 += kTileAhead) {
+    TileRegs<NB> ra[kTileAhead], rb[kTileAhead];
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (j0 + d < half) {
+        const int64_t J0 = (int64_t)(a0 + j0 + d) * NB;
+        ra[d].load(G, mp, R0, J0);   // L_(b0+bi),(a0+j)
+        rb[d].load(Xb, mp, J0, C0);  // X_(a0+j),(a0+ai)
+      }
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (j0 + d < half) {
+        __syncthreads();
+        ra[d].store(At);
+        rb[d].store(Bt);
+        __syncthreads();
+        ta.mma_nn(At, Bt);
+      }
   }
-  constexpr int TW = NB / 16;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int p = 0; p < TW; ++p)
-#pragma unroll
-    for (int o = 0; o < TW; ++o)
-      Ct[(R0 + ty * TW + p) + (C0 + tx * TW + o) * mp] = ta.acc[p][o];
+  for (int r = 0; r < 4; ++r) Ct[(R0 + ta.row(r)) + (C0 + ta.col()) * mp] = ta.acc[r];
 }
 
 template <int NB>
@@ -390,22 +453,27 @@ __global__ __launch_bounds__(256) void k_trinv_x(const double* __restrict__ Ct,
   if (bi >= nbb) return;
   const int64_t R0 = (int64_t)(b0 + bi) * NB, C0 = (int64_t)(a0 + ai) * NB;
   TileAcc<NB> ta;
-  ta.zero();
-  for (int j = 0; j <= bi; ++j) {
-    const int64_t J0 = (int64_t)(b0 + j) * NB;
-    __syncthreads();
-    load_tile<NB>(At, Xb, mp, R0, J0);  // X_(b0+bi),(b0+j)
-    load_tile<NB>(Bt, Ct, mp, J0, C0);  // C_(b0+j),(a0+ai)
-    __syncthreads();
-    ta.mma_nn(At, Bt);
+  for (int j0 = 0; j0 <= bi; j0 += kTileAhead) {
+    TileRegs<NB> ra[kTileAhead], rb[kTileAhead];
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (j0 + d <= bi) {
+        const int64_t J0 = (int64_t)(b0 + j0 + d) * NB;
+        ra[d].load(Xb, mp, R0, J0);  // X_(b0+bi),(b0+j)
+        rb[d].load(Ct, mp, J0, C0);  // C_(b0+j),(a0+ai)
+      }
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (j0 + d <= bi) {
+        __syncthreads();
+        ra[d].store(At);
+        rb[d].store(Bt);
+        __syncthreads();
+        ta.mma_nn(At, Bt);
+      }
   }
-  constexpr int TW = NB / 16;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int p = 0; p < TW; ++p)
-#pragma unroll
-    for (int o = 0; o < TW; ++o)
-      Xb[(R0 + ty * TW + p) + (C0 + tx * TW + o) * mp] = -ta.acc[p][o];
+  for (int r = 0; r < 4; ++r) Xb[(R0 + ta.row(r)) + (C0 + ta.col()) * mp] = -ta.acc[r];
 }
 
 // P = X^T X: P_ij = sum_{l >= i} X_li^T X_lj for j <= i, mirrored; written over G.
@@ -422,25 +490,35 @@ __global__ __launch_bounds__(256) void k_xtx(const double* __restrict__ Xb, doub
   const int bj = t;
   const int64_t I0 = (int64_t)bi * NB, J0 = (int64_t)bj * NB;
   TileAcc<NB> ta;
-  ta.zero();
-  for (int l = bi; l < T; ++l) {
-    const int64_t L0 = (int64_t)l * NB;
-    __syncthreads();
-    load_tile<NB>(At, Xb, mp, L0, I0);  // X_li
-    load_tile<NB>(Bt, Xb, mp, L0, J0);  // X_lj
-    __syncthreads();
-    ta.mma_tn(At, Bt);
+  for (int l0 = bi; l0 < T; l0 += kTileAhead) {
+    TileRegs<NB> ra[kTileAhead], rb[kTileAhead];
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (l0 + d < T) {
+        const int64_t L0 = (int64_t)(l0 + d) * NB;
+        ra[d].load(Xb, mp, L0, I0);  // X_li
+        rb[d].load(Xb, mp, L0, J0);  // X_lj
+      }
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (l0 + d < T) {
+        __syncthreads();
+        ra[d].store(At);
+        rb[d].store(Bt);
+        __syncthreads();
+        ta.mma_tn(At, Bt);
+      }
   }
-  constexpr int TW = NB / 16;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  // on a diagonal tile only i >= j is written (with its mirror): one writer
+  // per entry
 #pragma unroll
-  for (int p = 0; p < TW; ++p)
-#pragma unroll
-    for (int o = 0; o < TW; ++o) {
-      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
-      G[gi + gj * mp] = ta.acc[p][o];
-      G[gj + gi * mp] = ta.acc[p][o];
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gi = I0 + ta.row(r), gj = J0 + ta.col();
+    if (bi != bj || gi >= gj) {
+      G[gi + gj * mp] = ta.acc[r];
+      G[gj + gi * mp] = ta.acc[r];
     }
+  }
 }
 
 // Out = X * In for X block-lower-triangular (mp x mp, ld mp; only blocks
@@ -457,28 +535,30 @@ __global__ __launch_bounds__(256) void k_trmm(const double* __restrict__ X, int6
   const int bi = blockIdx.x;
   const int64_t I0 = (int64_t)bi * NB, J0 = (int64_t)blockIdx.y * NB;
   TileAcc<NB> ta;
-  ta.zero();
-  for (int kb = 0; kb <= bi; ++kb) {
-    const int64_t K0 = (int64_t)kb * NB;
-    __syncthreads();
-    load_tile<NB>(At, X, mp, I0, K0);
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-      const int r = e % NB, c = e / NB;
-      const int64_t gr = K0 + r, gc = J0 + c;
-      Bt[r][c] = (gr < nrows && gc < ncols) ? In[gr + gc * ldin] : 0.0;
-    }
-    __syncthreads();
-    ta.mma_nn(At, Bt);
+  for (int k0 = 0; k0 <= bi; k0 += kTileAhead) {
+    TileRegs<NB> ra[kTileAhead], rb[kTileAhead];
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (k0 + d <= bi) {
+        const int64_t K0 = (int64_t)(k0 + d) * NB;
+        ra[d].load(X, mp, I0, K0);
+        rb[d].load_masked(In, ldin, K0, J0, nrows, ncols);
+      }
+#pragma unroll
+    for (int d = 0; d < kTileAhead; ++d)
+      if (k0 + d <= bi) {
+        __syncthreads();
+        ra[d].store(At);
+        rb[d].store(Bt);
+        __syncthreads();
+        ta.mma_nn(At, Bt);
+      }
   }
-  constexpr int TW = NB / 16;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int p = 0; p < TW; ++p)
-#pragma unroll
-    for (int o = 0; o < TW; ++o) {
-      const int64_t gi = I0 + ty * TW + p, gj = J0 + tx * TW + o;
-      if (gi < nrows_out && gj < ncols) Out[gi + gj * ldout] = ta.acc[p][o];
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gi = I0 + ta.row(r), gj = J0 + ta.col();
+    if (gi < nrows_out && gj < ncols) Out[gi + gj * ldout] = ta.acc[r];
+  }
 }
 
 // G_ii += c * trace(G) for i < m (single workgroup): the shift of shifted
@@ -551,10 +631,9 @@ void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int32_t* 
   const int T = (int)(mp / kNb);
   for (int k = 0; k < T; ++k) {
     const int rest = T - k - 1;
-    hipLaunchKernelGGL(k_chol_panel<kNb>, dim3(rest + 1), dim3(kNb), 0, st, G, Xb, mp, k, fail);
-    if (rest > 0)
-      hipLaunchKernelGGL(k_chol_update<kNb>, dim3(rest * (rest + 1) / 2), dim3(256), 0, st, G,
-                         mp, k);
+    const int tiles = k > 0 ? rest * (rest + 1) / 2 : 0;  // step k-1's update right of block k
+    hipLaunchKernelGGL(k_chol_step<kNb>, dim3(rest + 1 + tiles), dim3(256), 0, st, G, Xb, mp, k,
+                       T, fail);
   }
   // X = L^{-1}: log2(T) levels of two launches each
   for (int half = 1; half < T; half *= 2) {
