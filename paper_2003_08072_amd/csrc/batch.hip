@@ -87,6 +87,11 @@ std::vector<Group> group_by(const std::vector<ColKey>& keys, const std::vector<i
 
 constexpr int kChunk = 6;  // CG iterations between host checks of the grouped CG
 
+// bytes of the copy of A that an LP's CG products read
+int64_t cg_bytes(const skipm_lp_s* lp) {
+  return lp->lda * lp->n * (lp->a_dtype == SKIPM_F64 ? 8 : 4);
+}
+
 // One LP in the engine: its handle and result, its loop state, its prepared
 // CG arguments, and what to do when its run has ended (called on a worker
 // thread, with that worker's stream, after the engine has let go of it).
@@ -140,6 +145,7 @@ class Engine {
     }
     ++outstanding_;
     live_.push_back(e);
+    live_bytes_ += cg_bytes(e->lp);
     tasks_.push_back({e, false});
     cv_.notify_all();
     return SKIPM_OK;
@@ -161,6 +167,7 @@ class Engine {
     {
       std::lock_guard<std::mutex> g(mu_);
       left.swap(live_);
+      live_bytes_ = 0;
       outstanding_ = 0;
     }
     for (Entry* e : left) {
@@ -212,6 +219,7 @@ class Engine {
       if (++exited_ < nthreads_ + 1 || fatal_ == SKIPM_OK) return;
       rc = fatal_;
       left.swap(live_);
+      live_bytes_ = 0;
       tasks_.clear();
       ready_.clear();
       outstanding_ = 0;
@@ -254,6 +262,7 @@ class Engine {
         if (!e->b.active) {
           finished = true;
           live_.erase(std::find(live_.begin(), live_.end(), e));
+          live_bytes_ -= cg_bytes(e->lp);
         } else if (e->b.grouped) {
           ready_.push_back(e);
         } else {
@@ -375,6 +384,12 @@ class Engine {
     ColPass nrm[2], cls[2], qin;
     CgCloseArgs close;
     batch_cg_passes(e->lp, nrm, c.fin, cls, &qin, &c.init, &close);
+    {
+      // the grouped products of all LPs in the engine stream more than the
+      // Infinity Cache holds: non-temporal loads (the same sums)
+      std::lock_guard<std::mutex> g(mu_);
+      if (live_bytes_ > kStreamBytes) nrm[0].nt = nrm[1].nt = 1;
+    }
     c.a_n.assign(2 * ab_, 0);
     c.a_c.assign(2 * ab_, 0);
     c.a_q.assign(ab_, 0);
@@ -512,6 +527,7 @@ class Engine {
   std::deque<Task> tasks_;
   std::deque<Entry*> ready_;
   std::vector<Entry*> live_;
+  int64_t live_bytes_ = 0;  // bytes of the CG copies of A of the LPs in live_
   int outstanding_ = 0;
   int exited_ = 0;  // engine threads that have ended
   bool stop_ = false;

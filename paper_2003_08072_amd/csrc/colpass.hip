@@ -742,9 +742,15 @@ struct Shape {
   int G, R;
 };
 
-Shape pick_shape(int64_t lda, int V) {
+// g32: the column passes also take lane groups of 32 lanes with three vectors
+// each for 64V < lda <= 96V rows (at most a quarter of the lanes idle, where
+// 64 lanes with two vectors leave up to half idle: a pass that is bound by
+// the bytes in flight per CU gets up to half as many again); the sketch keeps
+// the 16 / 64-lane shapes.
+Shape pick_shape(int64_t lda, int V, bool g32 = false) {
   if (lda <= 16 * V) return {16, 1};
   if (lda <= 32 * V) return {16, 2};
+  if (g32 && lda > 64 * V && lda <= 96 * V) return {32, 3};
   const int64_t per = 64 * V;
   const int64_t R = (lda + per - 1) / per;
   static const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16};
@@ -761,18 +767,20 @@ Shape pick_shape(int64_t lda, int V) {
 // puts every instantiation that the compiler would have to spill to scratch
 // at the smaller block.  DOT passes write no partial sums, so they use small
 // blocks and many of them.
-constexpr int threads_for(int mode, int R, int V, int tc_bytes) {
+constexpr int threads_for(int mode, int R, int V, int tc_bytes, int G = 64) {
   const int nacc = mode == COL_PROLOGUE ? 2 : (mode == COL_DOT ? 0 : 1);
   const int est = (1 + nacc) * R * V * tc_bytes / 4 + 16 * R + 32 +
                   (mode == COL_PROLOGUE ? 32 : 0) + (V == 4 && tc_bytes == 8 ? 8 : 0) +
                   (V == 8 ? 24 * R : 0);
   if (mode == COL_DOT) return 256;
+  // 32-lane groups: 768 threads when three waves per SIMD fit (<= 168 VGPRs)
+  if (G == 32 && est <= 168) return 768;
   return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
 
 template <typename TA, typename TC, int MODE, int G, int R, bool STREAM>
 void launch_one(const Args& a, int nblk, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  constexpr int NT = threads_for(MODE, R, Vec<TA>::V, (int)sizeof(TC));
+  constexpr int NT = threads_for(MODE, R, Vec<TA>::V, (int)sizeof(TC), G);
   if (e0)  // events stamped by the runtime with the kernel's own start and end
     hipExtLaunchKernelGGL((k_colpass<TA, TC, G, R, MODE, NT, STREAM>), dim3(nblk), dim3(NT), 0,
                           st, e0, e1, 0, a);
@@ -789,7 +797,7 @@ constexpr bool stream_mode(int mode) {
 template <typename TA, typename TC, int MODE>
 int dispatch(const Args& a, int nblk, bool stream, hipStream_t st, hipEvent_t e0 = nullptr,
              hipEvent_t e1 = nullptr) {
-  const Shape sh = pick_shape(a.lda, Vec<TA>::V);
+  const Shape sh = pick_shape(a.lda, Vec<TA>::V, true);
   // shapes that only columns longer than kMaxM would select are not built
 #define SK_CASE(GG, RR)                                                   \
   if constexpr (GG * RR * Vec<TA>::V <= kMaxM) {                          \
@@ -804,7 +812,7 @@ int dispatch(const Args& a, int nblk, bool stream, hipStream_t st, hipEvent_t e0
       return 0;                                                           \
     }                                                                     \
   }
-  SK_CASE(16, 1) SK_CASE(16, 2)
+  SK_CASE(16, 1) SK_CASE(16, 2) SK_CASE(32, 3)
   SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
   SK_CASE(64, 6) SK_CASE(64, 8) SK_CASE(64, 12) SK_CASE(64, 16)
 #undef SK_CASE
@@ -847,7 +855,7 @@ int vec_width(int ta) { return ta == SKIPM_F64 ? 2 : (ta == SKIPM_F32 ? 4 : 8); 
 
 int colpass_nblk_dot(int64_t lda, int64_t n, int ta) {
   const int V = vec_width(ta);
-  const Shape sh = pick_shape(lda, V);
+  const Shape sh = pick_shape(lda, V, true);
   if (sh.G == 0) return 1;
   const int64_t slots = (256 / 64) * (64 / sh.G);
   int64_t nb = (n + slots - 1) / slots;
@@ -858,9 +866,9 @@ int colpass_nblk_dot(int64_t lda, int64_t n, int ta) {
 
 int colpass_nblk(int64_t lda, int64_t n, int ta, int tc, int mode) {
   const int V = vec_width(ta);
-  const Shape sh = pick_shape(lda, V);
+  const Shape sh = pick_shape(lda, V, true);
   if (sh.G == 0) return 1;
-  const int nt = threads_for(mode, sh.R, V, tc == SKIPM_F64 ? 8 : 4);
+  const int nt = threads_for(mode, sh.R, V, tc == SKIPM_F64 ? 8 : 4, sh.G);
   const int64_t slots = (int64_t)(nt / 64) * (64 / sh.G);
   const int target = nt == 256 ? 512 : 256;
   // at least 16 columns per lane group: fewer, longer workgroups for small
@@ -976,8 +984,8 @@ Args to_args(const ColPass& c) {
 
 // The lane-group shapes (G, R) of the grouped launches; Args::shape indexes
 // this table.
-constexpr int kGShapes[][2] = {{16, 1}, {16, 2}, {64, 1}, {64, 2},  {64, 3},
-                               {64, 4}, {64, 6}, {64, 8}, {64, 12}, {64, 16}};
+constexpr int kGShapes[][2] = {{16, 1}, {16, 2}, {64, 1},  {64, 2},  {64, 3}, {64, 4},
+                               {64, 6}, {64, 8}, {64, 12}, {64, 16}, {32, 3}};
 constexpr int kNGShapes = (int)(sizeof(kGShapes) / sizeof(kGShapes[0]));
 
 // Register class of a shape: the shapes of one launch share its register
@@ -990,7 +998,7 @@ constexpr int gshape_cls(int R) { return R <= 2 ? 0 : (R <= 4 ? 1 : (R <= 8 ? 2 
 template <typename TA, int MODE, int NT, int CLS>
 constexpr bool gshape_in(int i) {
   return kGShapes[i][0] * kGShapes[i][1] * Vec<TA>::V <= kMaxM &&
-         threads_for(MODE, kGShapes[i][1], Vec<TA>::V, 8) == NT &&
+         threads_for(MODE, kGShapes[i][1], Vec<TA>::V, 8, kGShapes[i][0]) == NT &&
          gshape_cls(kGShapes[i][1]) == CLS;
 }
 template <typename TA, int MODE, int NT, int CLS, int I>
@@ -1043,8 +1051,8 @@ __global__ __launch_bounds__(NT) void k_colpass_grouped(const Args* __restrict__
       return;                                                                            \
     }                                                                                    \
   }
-  SK_GCASE(0) SK_GCASE(1) SK_GCASE(2) SK_GCASE(3) SK_GCASE(4)
-  SK_GCASE(5) SK_GCASE(6) SK_GCASE(7) SK_GCASE(8) SK_GCASE(9)
+  SK_GCASE(0) SK_GCASE(1) SK_GCASE(2) SK_GCASE(3) SK_GCASE(4) SK_GCASE(5)
+  SK_GCASE(6) SK_GCASE(7) SK_GCASE(8) SK_GCASE(9) SK_GCASE(10)
 #undef SK_GCASE
 }
 
@@ -1079,6 +1087,7 @@ int dispatch_grouped(const ColKey& k, const Args* args, const int32_t* first, in
                      const int64_t* kstart, int kit, hipStream_t st) {
   switch (k.threads) {
     case 1024: return dispatch_cls<TA, MODE, 1024>(k, args, first, nmat, total, kstart, kit, st);
+    case 768: return dispatch_cls<TA, MODE, 768>(k, args, first, nmat, total, kstart, kit, st);
     case 512: return dispatch_cls<TA, MODE, 512>(k, args, first, nmat, total, kstart, kit, st);
     case 256: return dispatch_cls<TA, MODE, 256>(k, args, first, nmat, total, kstart, kit, st);
   }
@@ -1095,14 +1104,14 @@ int colpass_prepare(ColPass& c, void* args_out, ColKey* key) {
   if (c.nblk <= 0)
     c.nblk = c.mode == COL_DOT ? colpass_nblk_dot(c.lda, c.n, c.ta)
                                : colpass_nblk(c.lda, c.n, c.ta, c.tc, c.mode);
-  const Shape sh = pick_shape(c.lda, vec_width(c.ta));
+  const Shape sh = pick_shape(c.lda, vec_width(c.ta), true);
   int shape = -1;
   for (int i = 0; i < kNGShapes; ++i)
     if (kGShapes[i][0] == sh.G && kGShapes[i][1] == sh.R) shape = i;
   if (shape < 0) return -1;
   key->ta = c.ta;
   key->mode = c.mode;
-  key->threads = threads_for(c.mode, sh.R, vec_width(c.ta), 8);
+  key->threads = threads_for(c.mode, sh.R, vec_width(c.ta), 8, sh.G);
   key->cls = gshape_cls(sh.R);
   key->nt = c.mode == COL_NORMAL && c.nt != 0;
   Args a = to_args(c);

@@ -42,13 +42,14 @@ constexpr int kTypeBF16 = 2;
 constexpr int64_t kMaxM = 2048;
 
 // ---------------------------------------------------------------------------
-// Sum of an FP64 value over a lane group of G = 16 (a DPP row) or 64 (the
-// wave) lanes, the same bits in every lane of the group: pairs of lanes
-// (xor 1, xor 2 by quad permutes), then the two halves of each 8-lane half
-// row and of each 16-lane row (mirrors: lane i against 7 - i, 15 - i), each
-// by DPP moves of the two 32-bit halves; for the wave, the four rows' sums
-// read from lanes 0, 16, 32, 48 and added as (r0 + r1) + (r2 + r3).  No LDS
-// permute, so the chain is a few cycles per step.
+// Sum of an FP64 value over a lane group of G = 16 (a DPP row), 32 (half
+// the wave) or 64 (the wave) lanes, the same bits in every lane of the group:
+// pairs of lanes (xor 1, xor 2 by quad permutes), then the two halves of each
+// 8-lane half row and of each 16-lane row (mirrors: lane i against 7 - i,
+// 15 - i), each by DPP moves of the two 32-bit halves; then the four rows'
+// sums read from lanes 0, 16, 32, 48 and added as r0 + r1, r2 + r3 (halves)
+// or (r0 + r1) + (r2 + r3) (the wave).  No LDS permute, so the chain is a few
+// cycles per step.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -62,7 +63,7 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 template <int G>
 __device__ __forceinline__ double lane_group_sum(double v) {
-  static_assert(G == 16 || G == 64, "lane groups of 16 or 64 lanes");
+  static_assert(G == 16 || G == 32 || G == 64, "lane groups of 16, 32 or 64 lanes");
   v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane xor 1
   v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane xor 2
   v += dpp_f64<0x141>(v);  // row_half_mirror
@@ -71,6 +72,10 @@ __device__ __forceinline__ double lane_group_sum(double v) {
     const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
     const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
     v = (r0 + r1) + (r2 + r3);
+  } else if constexpr (G == 32) {
+    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+    v = (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
   }
   return v;
 }
