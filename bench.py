@@ -32,7 +32,7 @@ INFINITY_CACHE_BYTES = 256 << 20
 # copy needs to read 1 GiB; WRITE_SIZE by 1.000), taken on the current kernels:
 # config 1, k_colpass (profiles/hbm_traffic_colpass_normal_cfg1.md); config 2,
 # k_sb_normal and its finish (profiles/hbm_traffic_sb_normal_cfg2.md).
-MEASURED_TRAFFIC = {(1, "mixed"): 202_268_571, (1, "fp64"): 406_716_961,
+MEASURED_TRAFFIC = {(1, "mixed"): 202_316_033, (1, "fp64"): 406_616_092,
                     (2, "fp64"): 32_372_040}
 METRIC = "LP solves/s at rel. gap 1e-6 (mixed vs FP64 PCG); matvec GB/s; p50/p99 latency"
 
