@@ -203,7 +203,7 @@ int hash_items(skipm_lp_s* lp, int64_t salt, hipStream_t st) {
   launch_fill_i32(lp->bcnt, 0, lp->w, st);
   launch_hash(lp->prm.seed, salt, lp->s, lp->n, lp->w, lp->bucket, lp->sign, lp->bcnt, st);
   launch_bucket_scan(lp->bcnt, lp->bptr, lp->bcur, lp->w, st);
-  launch_bucket_scatter(lp->bucket, lp->n * lp->s, lp->bptr, lp->bcur, lp->perm_raw, st);
+  launch_bucket_scatter(lp->bucket, lp->n * lp->s, lp->w, lp->bptr, lp->bcur, lp->perm_raw, st);
   launch_bucket_sort(lp->bptr, lp->perm_raw, lp->perm, lp->w, st);
   SK_CHECK_HIP(hipGetLastError());
   lp->hashed_k = salt;

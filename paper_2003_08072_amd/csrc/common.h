@@ -144,7 +144,8 @@ void launch_hash(uint64_t seed, int64_t k, int s, int64_t n, int w, int32_t* buc
                  int8_t* sign, int32_t* count, hipStream_t st);
 void launch_bucket_scan(const int32_t* count, int32_t* ptr, int32_t* cursor, int w,
                         hipStream_t st);
-void launch_bucket_scatter(const int32_t* bucket, int64_t nitems, const int32_t* ptr,
+// w: the number of buckets (at most 8192 takes the LDS-aggregated kernel)
+void launch_bucket_scatter(const int32_t* bucket, int64_t nitems, int w, const int32_t* ptr,
                            int32_t* cursor, int32_t* perm, hipStream_t st);
 void launch_bucket_sort(const int32_t* ptr, const int32_t* raw, int32_t* perm, int w,
                         hipStream_t st);

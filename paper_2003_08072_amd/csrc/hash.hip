@@ -46,6 +46,38 @@ __global__ __launch_bounds__(256) void k_hash(HashBases hb, int s, int64_t n, in
   }
 }
 
+// Bucket counts without per-item global atomics: workgroup g hashes the
+// items of its own contiguous range, counts them per bucket in LDS, then adds
+// each non-zero count to the global count once (a few workgroups per bucket
+// instead of every item).
+constexpr int kLdsBuckets = 8192;  // w up to this takes the LDS-aggregated kernels
+constexpr int kAggBlocks = 64;     // workgroups of 1024 threads for them
+
+__global__ __launch_bounds__(1024) void k_hash_agg(HashBases hb, int s, int64_t n, int blk,
+                                                   int w, int32_t* __restrict__ bucket,
+                                                   int8_t* __restrict__ sign,
+                                                   int32_t* __restrict__ count) {
+  __shared__ int32_t cnt[kLdsBuckets];
+  for (int b = threadIdx.x; b < w; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const int64_t nitems = n * s;
+  const int64_t per = (nitems + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < nitems ? i0 + per : nitems;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int64_t j = i / s;
+    const int r = (int)(i - j * s);
+    const uint64_t h = mix64(hb.base[r] ^ (uint64_t)j);
+    const int b = r * blk + (int)(((h >> 32) * (uint64_t)blk) >> 32);
+    bucket[i] = b;
+    sign[i] = (h & 1ull) ? (int8_t)-1 : (int8_t)1;
+    atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < w; b += blockDim.x)
+    if (cnt[b]) atomicAdd(&count[b], cnt[b]);
+}
+
 // Exclusive scan of the bucket counts (single workgroup), ptr has w+1 entries.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count,
                                                int32_t* __restrict__ ptr,
@@ -94,6 +126,34 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ buc
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nitems; i += stride) {
     const int b = bucket[i];
     const int pos = ptr[b] + atomicAdd(&cursor[b], 1);
+    out[pos] = (int32_t)i;
+  }
+}
+
+// The scatter with the same item ranges: each workgroup counts its items per
+// bucket in LDS, takes one range of slots per non-empty bucket from the
+// global cursor, and places its items there by LDS cursors.  The order inside
+// a bucket depends on timing; the sort below makes it ascending.
+__global__ __launch_bounds__(1024) void k_scatter_agg(const int32_t* __restrict__ bucket,
+                                                      int64_t nitems, int w,
+                                                      const int32_t* __restrict__ ptr,
+                                                      int32_t* __restrict__ cursor,
+                                                      int32_t* __restrict__ out) {
+  __shared__ int32_t cur[kLdsBuckets];
+  for (int b = threadIdx.x; b < w; b += blockDim.x) cur[b] = 0;
+  __syncthreads();
+  const int64_t per = (nitems + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < nitems ? i0 + per : nitems;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&cur[bucket[i]], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < w; b += blockDim.x) {
+    const int c = cur[b];
+    cur[b] = c ? ptr[b] + atomicAdd(&cursor[b], c) : 0;
+  }
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int pos = atomicAdd(&cur[bucket[i]], 1);
     out[pos] = (int32_t)i;
   }
 }
@@ -155,6 +215,14 @@ void launch_hash(uint64_t seed, int64_t k, int s, int64_t n, int w, int32_t* buc
   for (int r = 0; r < s && r < kMaxS; ++r)
     hb.base[r] = mix64(seed + kGolden * (1ull + (uint64_t)k * (uint64_t)s + (uint64_t)r));
   const int blk = w / s;
+  if (count && w <= kLdsBuckets) {
+    int64_t blocks = (n * s + 1023) / 1024;
+    if (blocks > kAggBlocks) blocks = kAggBlocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_hash_agg, dim3((unsigned)blocks), dim3(1024), 0, st, hb, s, n, blk, w,
+                       bucket, sign, count);
+    return;
+  }
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
@@ -167,8 +235,16 @@ void launch_bucket_scan(const int32_t* count, int32_t* ptr, int32_t* cursor, int
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, ptr, cursor, w);
 }
 
-void launch_bucket_scatter(const int32_t* bucket, int64_t nitems, const int32_t* ptr,
+void launch_bucket_scatter(const int32_t* bucket, int64_t nitems, int w, const int32_t* ptr,
                            int32_t* cursor, int32_t* perm, hipStream_t st) {
+  if (w <= kLdsBuckets) {
+    int64_t blocks = (nitems + 1023) / 1024;
+    if (blocks > kAggBlocks) blocks = kAggBlocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_scatter_agg, dim3((unsigned)blocks), dim3(1024), 0, st, bucket, nitems,
+                       w, ptr, cursor, perm);
+    return;
+  }
   int64_t blocks = (nitems + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
