@@ -416,11 +416,18 @@ __global__ __launch_bounds__(256) void k_csr_fold(const double* __restrict__ seg
 
 // Sketch from CSC: one wave per bucket accumulates B[:, b] in LDS, column by
 // column in item order (the lanes of one step touch distinct rows).  The
-// items' metadata (column, coefficient, column range) is fetched 64 items at
-// a time, one per lane, and the first 64 entries of the next column are
-// requested while the current one is added, so a bucket's columns do not
-// wait out three load latencies each.  The order of the additions is the
-// plain item-by-item order.
+// items' metadata (column, coefficient, column range) and the first kHead
+// entries of each item's column are fetched 64 items at a time, one item per
+// lane, so a block of 64 columns waits out one load latency; the columns are
+// then added one after another from registers (read across lanes), the
+// entries past the first kHead of a longer column by strided loads.  The
+// order of the additions is the plain item-by-item order.
+constexpr int kHead = 4;
+__device__ __forceinline__ float readlane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_val(double v, int l) { return readlane_f64(v, l); }
+
 template <typename TV>
 __global__ __launch_bounds__(256) void k_csc_sketch(const int32_t* __restrict__ colptr,
                                                     const int32_t* __restrict__ rowidx,
@@ -440,9 +447,10 @@ __global__ __launch_bounds__(256) void k_csc_sketch(const int32_t* __restrict__ 
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   const int beg = ptr[bkt], end = ptr[bkt + 1];
+  const int64_t last = nnz > 0 ? nnz - 1 : 0;
   for (int it0 = beg; it0 < end; it0 += 64) {
     const int itl = it0 + lane;
-    long long cb_l = 0, ce_l = 0;
+    int32_t cb_l = 0, ce_l = 0;
     double coef_l = 0.0;
     if (itl < end) {
       const int item = perm[itl];
@@ -452,34 +460,38 @@ __global__ __launch_bounds__(256) void k_csc_sketch(const int32_t* __restrict__ 
       cb_l = colptr[j];
       ce_l = colptr[j + 1];
     }
+    // the first kHead entries of this lane's column (in-bounds indices past its end)
+    int32_t hr[kHead];
+    TV hv[kHead];
+#pragma unroll
+    for (int e = 0; e < kHead; ++e) {
+      const int64_t k = (int64_t)cb_l + e;
+      const int64_t kc = k < ce_l ? k : last;
+      hr[e] = rowidx[kc];
+      hv[e] = cval[kc];
+    }
     const int cnt = end - it0 < 64 ? end - it0 : 64;
-    // entry cb + lane of column q (an in-bounds index when the column is shorter)
-    auto head = [&](int q, int32_t& r, TV& v) -> bool {
-      const int64_t cb = __shfl(cb_l, q), ce = __shfl(ce_l, q);
-      const int64_t k = cb + lane;
-      const bool in = k < ce;
-      const int64_t kc = in ? k : (nnz > 0 ? nnz - 1 : 0);
-      r = rowidx[kc];
-      v = cval[kc];
-      return in;
-    };
-    int32_t r0 = 0;
-    TV v0 = 0;
-    bool in0 = head(0, r0, v0);
     for (int q = 0; q < cnt; ++q) {
-      const int64_t cb = __shfl(cb_l, q), ce = __shfl(ce_l, q);
-      const double coef = __shfl(coef_l, q);
-      int32_t r1 = 0;
-      TV v1 = 0;
-      bool in1 = false;
-      if (q + 1 < cnt) in1 = head(q + 1, r1, v1);
-      if (in0) acc[r0] += coef * (double)v0;
-      for (int64_t k = cb + 64 + lane; k < ce; k += 64) acc[rowidx[k]] += coef * (double)cval[k];
+      const int32_t cb = __builtin_amdgcn_readlane(cb_l, q);
+      const int32_t ce = __builtin_amdgcn_readlane(ce_l, q);
+      const double coef = readlane_f64(coef_l, q);
+      // lane e < kHead adds entry cb + e of column q
+      int32_t r0 = 0;
+      TV v0 = 0;
+#pragma unroll
+      for (int e = 0; e < kHead; ++e) {
+        const int32_t re = __builtin_amdgcn_readlane(hr[e], q);
+        const TV ve = readlane_val(hv[e], q);
+        if (lane == e) {
+          r0 = re;
+          v0 = ve;
+        }
+      }
+      if (lane < kHead && cb + lane < ce) acc[r0] += coef * (double)v0;
+      for (int64_t k = (int64_t)cb + kHead + lane; k < ce; k += 64)
+        acc[rowidx[k]] += coef * (double)cval[k];
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      r0 = r1;
-      v0 = v1;
-      in0 = in1;
     }
   }
   double* out = B + (int64_t)bkt * ldb;
