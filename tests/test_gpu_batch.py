@@ -79,6 +79,31 @@ def test_batch_matches_lone_solves(torch, sk):
         h.close()
 
 
+def test_batch_matches_lone_solves_32_lane_groups(torch, sk):
+    """LPs whose column passes take 32-lane groups (FP32 m in (256, 384], FP64
+    m in (128, 192]) next to 64-lane ones, at the batched workload's gap and
+    column ratio: the grouped launches give each LP its lone solve, bitwise."""
+    shapes = [(300, 9000, "f32"), (160, 4800, "f64"), (384, 7680, "f32"), (200, 4000, "f32")]
+    lps = [dense_planted(m, n, rng=np.random.default_rng(60 + i), a_dtype=dt, eps_gap=1e-6,
+                         seed=300 + i) for i, (m, n, dt) in enumerate(shapes)]
+    say(f"batch of {len(lps)} LPs with 32-lane column groups vs lone solves")
+    hs = [sk.LP(lp.A, lp.b, lp.c, a_dtype=lp.a_dtype, w=lp.w, seed=lp.seed,
+                eps_gap=lp.eps_gap) for lp in lps]
+    lone, xs = [], []
+    for h in hs:
+        lone.append(h.solve())
+        xs.append(h.get_iterate()[0].cpu().numpy())
+        h.reset()
+    torch.cuda.synchronize()
+    batch = sk.solve_batch(hs, workers=4)
+    for lp, h, r1, r2, x1 in zip(lps, hs, lone, batch, xs):
+        check_planted(lp, r2)
+        same(r1, r2)
+        assert np.array_equal(h.get_iterate()[0].cpu().numpy(), x1)
+    for h in hs:
+        h.close()
+
+
 def test_batch_workload_sample(torch, sk):
     idx = list(range(12))
     say("batched workload: LPs 0..11 (dense FP32, m in [20, 400], n = m k)")

@@ -723,6 +723,34 @@ def test_normal_product_at_full_size(torch, sk, cfg1, prec):
     assert np.all(np.abs(q - ref) <= 2 * (lp.m + lp.n) * EPS * bound)
 
 
+@pytest.mark.parametrize("m,prec", [(256, "mixed"), (257, "mixed"), (300, "mixed"),
+                                    (384, "mixed"), (385, "mixed"), (128, "fp64"),
+                                    (129, "fp64"), (192, "fp64"), (193, "fp64")])
+def test_normal_product_lane_group_shapes(torch, sk, m, prec):
+    """The fused product on both sides of each edge of the 32-lane column
+    groups (three 16-byte vectors per lane: 64V < lda <= 96V rows, V = 4 FP32
+    or 2 FP64 values per vector) and the 64-lane groups around them, over a
+    ragged number of columns, against the oracle's normal matrix."""
+    n = 2501
+    lp = dense_planted(m, n, rng=np.random.default_rng(m + 7))
+    rng = np.random.default_rng(m + 8)
+    x = rng.uniform(0.1, 10.0, n)
+    s = rng.uniform(0.1, 10.0, n)
+    y = rng.standard_normal(m)
+    u = rng.standard_normal(m)
+    say(f"normal product m={m} n={n} {prec}")
+    precision = sk.SKIPM_PREC_MIXED if prec == "mixed" else sk.SKIPM_PREC_FP64
+    with sk.LP(lp.A, lp.b, lp.c, w=lp.w, seed=lp.seed, s=2, precision=precision) as h:
+        h.set_iterate(x, y, s)
+        h.step()
+        q = h.normal_matvec(u).cpu().numpy()
+    A = lp.A if prec == "fp64" else lp.A.astype(np.float32).astype(np.float64)
+    d2 = x / s
+    ref = O.normal_matrix(A, d2) @ u
+    bound = np.abs(A) @ (d2 * (np.abs(A).T @ np.abs(u)))
+    assert np.all(np.abs(q - ref) <= 2 * (m + n) * EPS * bound)
+
+
 def test_streamed_fp32_product(torch, sk):
     """The mixed product over an FP32 copy larger than 240 MiB (500 x 130000:
     260 MB) takes the non-temporal instantiation of the pass; element by
