@@ -14,29 +14,36 @@ namespace skipm {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, 128 x 128 tiles of the
-// lower triangle, mirrored to the upper triangle.  G is mp x mp, column-major.
+// Gram: Gpart[ks] = B[:, cols of split ks] B[:, same]^T, RT x RT tiles of the
+// lower triangle (RT = 128, or 64 when mp <= 256), mirrored to the upper
+// triangle.  G is mp x mp, column-major.
 //
 // On the FP64 matrix cores: v_mfma_f64_16x16x4 takes, in lane l, A[l%16][l/16]
 // of a 16x4 block and B[l/16][l%16] of a 4x16 block, and accumulates
 // D[l/16 + 4r][l%16] in element r of the lane's four-double accumulator.  The
-// four waves of a workgroup own a 64 x 64 quarter of the tile each (4 x 4
-// blocks of 16 x 16).  Per stage of 16 columns of B, the tile's two 128-row
-// panels go through LDS (two buffers: the next stage's loads are in flight in
-// registers while this stage's 64 MFMAs per wave run; one barrier per stage).
-// Every entry is a sum over the split's columns in increasing order.
+// four waves of a workgroup own an RT/2 x RT/2 quarter of the tile each
+// (RT/32 x RT/32 blocks of 16 x 16).  Per stage of 16 columns of B, the tile's
+// two RT-row panels go through LDS (two buffers: the next stage's loads are in
+// flight in registers while this stage's MFMAs run; one barrier per stage).
+// Every entry is a sum over the split's columns in increasing order, in the
+// same steps for either tile size.
 // ---------------------------------------------------------------------------
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef double dacc4 __attribute__((ext_vector_type(4)));
-constexpr int kRT = 128;      // output tile
+constexpr int kRT = 128;      // output tile of the split rule
 constexpr int kRK = 16;       // columns of B per stage
-constexpr int kRP = kRT + 2;  // LDS row pitch (16-byte aligned rows)
 
+template <int RT>
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int64_t ldb,
                                               int64_t m, int64_t w, double* __restrict__ Gpart,
                                               int64_t mp, int64_t cols_per_split) {
-  __shared__ double Ai[2][kRK][kRP];
-  __shared__ double Aj[2][kRK][kRP];
+  constexpr int RP = RT + 2;       // LDS row pitch (16-byte aligned rows)
+  constexpr int NBW = RT / 32;     // 16 x 16 blocks per wave and dimension
+  constexpr int TPC = RT / 2;      // threads per panel column (two rows each)
+  constexpr int CPP = 256 / TPC;   // panel columns per pass of the workgroup
+  constexpr int NPASS = kRK / CPP;
+  __shared__ double Ai[2][kRK][RP];
+  __shared__ double Aj[2][kRK][RP];
   // decode the lower-triangle tile pair (ti >= tj)
   int t = blockIdx.x, ti = 0;
   while (t > ti) {
@@ -45,15 +52,15 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
   }
   const int tj = t;
   const int ks = blockIdx.y;
-  const int64_t i0 = (int64_t)ti * kRT, j0 = (int64_t)tj * kRT;
+  const int64_t i0 = (int64_t)ti * RT, j0 = (int64_t)tj * RT;
   const int64_t cb = (int64_t)ks * cols_per_split;
   const int64_t ce = cb + cols_per_split < w ? cb + cols_per_split : w;
   const int th = threadIdx.x, lane = th & 63, wv = th >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = wv >> 1, wc = wv & 1;
-  // load mapping: 4 x (one column kk of the stage, rows 2 rp and 2 rp + 1) per panel
-  const int a_kk = th >> 6, a_rp = th & 63;
-  dvec2 ri[4], rj[4];
+  // load mapping: NPASS x (one column kk of the stage, rows 2 rp and 2 rp + 1) per panel
+  const int a_kk = th / TPC, a_rp = th % TPC;
+  dvec2 ri[NPASS], rj[NPASS];
   auto pair = [&](const int64_t r, const int64_t c) {
     dvec2 v = (dvec2)0.0;
     if (c < ce) {
@@ -68,24 +75,24 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
   };
   auto fetch = [&](const int64_t c0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t c = c0 + a_kk + 4 * q;
+    for (int q = 0; q < NPASS; ++q) {
+      const int64_t c = c0 + a_kk + CPP * q;
       ri[q] = pair(i0 + 2 * a_rp, c);
       rj[q] = pair(j0 + 2 * a_rp, c);
     }
   };
   auto stash = [&](const int b) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *(dvec2*)&Ai[b][a_kk + 4 * q][2 * a_rp] = ri[q];
-      *(dvec2*)&Aj[b][a_kk + 4 * q][2 * a_rp] = rj[q];
+    for (int q = 0; q < NPASS; ++q) {
+      *(dvec2*)&Ai[b][a_kk + CPP * q][2 * a_rp] = ri[q];
+      *(dvec2*)&Aj[b][a_kk + CPP * q][2 * a_rp] = rj[q];
     }
   };
-  dacc4 acc[4][4];
+  dacc4 acc[NBW][NBW];
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib)
+  for (int ib = 0; ib < NBW; ++ib)
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = (dacc4)0.0;
+    for (int jb = 0; jb < NBW; ++jb) acc[ib][jb] = (dacc4)0.0;
   const int64_t nst = ce > cb ? (ce - cb + kRK - 1) / kRK : 0;
   if (nst > 0) {
     fetch(cb);
@@ -97,15 +104,15 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
     if (st + 1 < nst) fetch(cb + (st + 1) * kRK);
 #pragma unroll
     for (int s4 = 0; s4 < kRK / 4; ++s4) {
-      double fa[4], fb[4];
+      double fa[NBW], fb[NBW];
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) fa[ib] = Ai[b][4 * s4 + lk][64 * wr + 16 * ib + li];
+      for (int ib = 0; ib < NBW; ++ib) fa[ib] = Ai[b][4 * s4 + lk][(RT / 2) * wr + 16 * ib + li];
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) fb[jb] = Aj[b][4 * s4 + lk][64 * wc + 16 * jb + li];
+      for (int jb = 0; jb < NBW; ++jb) fb[jb] = Aj[b][4 * s4 + lk][(RT / 2) * wc + 16 * jb + li];
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
+      for (int ib = 0; ib < NBW; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
+        for (int jb = 0; jb < NBW; ++jb)
           acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[ib], fb[jb], acc[ib][jb], 0, 0, 0);
     }
     if (st + 1 < nst) stash(b ^ 1);
@@ -115,13 +122,13 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ B, int6
   // written (with its mirror), so every entry has exactly one writer
   double* G = Gpart + (int64_t)ks * mp * mp;
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib)
+  for (int ib = 0; ib < NBW; ++ib)
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
+    for (int jb = 0; jb < NBW; ++jb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + 64 * wr + 16 * ib + lk + 4 * r;
-        const int64_t k = j0 + 64 * wc + 16 * jb + li;
+        const int64_t i = i0 + (RT / 2) * wr + 16 * ib + lk + 4 * r;
+        const int64_t k = j0 + (RT / 2) * wc + 16 * jb + li;
         if (i < mp && k < mp && (ti != tj || i >= k)) {
           G[i + k * mp] = acc[ib][jb][r];
           G[k + i * mp] = acc[ib][jb][r];
@@ -606,12 +613,17 @@ int gram_ksplit(int64_t mp, int64_t w) {
 
 void launch_gram(const double* B, int64_t ldb, int64_t m, int64_t w, double* Gpart, int ksplit,
                  int64_t mp, hipStream_t st) {
-  const int T = (int)((mp + kRT - 1) / kRT);
-  const int ntiles = T * (T + 1) / 2;
   int64_t cps = (w + ksplit - 1) / ksplit;
   cps = (cps + 15) / 16 * 16;
-  hipLaunchKernelGGL(k_gram, dim3(ntiles, ksplit), dim3(256), 0, st, B, ldb, m, w, Gpart, mp,
-                     cps);
+  if (mp <= 256) {  // 64 x 64 tiles: less padding and more workgroups for small m
+    const int T = (int)((mp + 63) / 64);
+    hipLaunchKernelGGL(k_gram<64>, dim3(T * (T + 1) / 2, ksplit), dim3(256), 0, st, B, ldb, m, w,
+                       Gpart, mp, cps);
+    return;
+  }
+  const int T = (int)((mp + kRT - 1) / kRT);
+  hipLaunchKernelGGL(k_gram<kRT>, dim3(T * (T + 1) / 2, ksplit), dim3(256), 0, st, B, ldb, m, w,
+                     Gpart, mp, cps);
 }
 
 void launch_gram_finish(const double* Gpart, int ksplit, int64_t m, int64_t mp, double* G,
