@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -77,11 +78,49 @@ constexpr size_t kScalarBlockBytes = S_NSLOTS * sizeof(double) + I_NINTS * sizeo
 
 int sync_read(skipm_lp_s* lp, hipStream_t st) {
   SK_CHECK_HIP(hipMemcpyAsync(lp->hsc, lp->sc, kScalarBlockBytes, hipMemcpyDeviceToHost, st));
-  SK_CHECK_HIP(hipStreamSynchronize(st));
-  return SKIPM_OK;
+  return wait_stream(st, lp->rd_ev);
 }
 
 const int32_t* host_ints(const skipm_lp_s* lp) { return (const int32_t*)(lp->hsc + S_NSLOTS); }
+
+}  // namespace
+
+namespace skipm {
+
+// The host's waits on the device (reads of the scalar block, CG checks, the
+// batch's phase ends) sit between short chains of dependent launches: the GPU
+// idles from the awaited work's end until the host has woken up and queued
+// the next launch.  So the host polls the event for a while (at most
+// kSpinUs) before a blocking wait (config 0: 45.3 -> 50.3 solves/s).
+constexpr int kSpinUs = 200;
+
+int poll_event(hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) return SKIPM_OK;
+    if (e != hipErrorNotReady) {
+      set_error(std::string("hipEventQuery: ") + hipGetErrorString(e));
+      return SKIPM_EDEVICE;
+    }
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinUs)) break;
+  }
+  SK_CHECK_HIP(hipEventSynchronize(ev));
+  return SKIPM_OK;
+}
+
+int wait_stream(hipStream_t st, hipEvent_t ev) {
+  if (!ev) {
+    SK_CHECK_HIP(hipStreamSynchronize(st));
+    return SKIPM_OK;
+  }
+  SK_CHECK_HIP(hipEventRecord(ev, st));
+  return poll_event(ev);
+}
+
+}  // namespace skipm
+
+namespace {
 
 int mu_from_iterate(skipm_lp_s* lp, hipStream_t st) {
   launch_xs_sum(lp->n, lp->x, lp->sv, lp->red, lp->nblk_vec, st);
@@ -545,9 +584,9 @@ int pcg_run(skipm_lp_s* lp, const double* rhs, double* xsol, double tol, int max
     queue[0] = queue[1];
     --nq;
     if (depth == 2) {
-      SK_CHECK_HIP(hipEventSynchronize(lp->snap_ev[look]));
+      SK_TRY(poll_event(lp->snap_ev[look]));
     } else {
-      SK_CHECK_HIP(hipStreamSynchronize(st));
+      SK_TRY(wait_stream(st, lp->rd_ev));
     }
     const double* snap = lp->hsnap[look];
     const int32_t* hi = (const int32_t*)(snap + S_NSLOTS);
@@ -1468,6 +1507,7 @@ int lp_destroy(skipm_lp_t lp) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : lp->snap_ev)
     if (e) (void)hipEventDestroy(e);
+  if (lp->rd_ev) (void)hipEventDestroy(lp->rd_ev);
   for (double* h : {lp->hsc, lp->hsnap[0], lp->hsnap[1]})
     if (h) (void)hipHostFree(h);
   delete lp;
@@ -1747,8 +1787,8 @@ int lp_create(skipm_lp_t* out, const skipm_problem* prob, const skipm_params* pr
       return set_error("hipHostMalloc failed"), SKIPM_ENOMEM;
     }
   }
-  for (hipEvent_t& e : lp->snap_ev) {
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+  for (hipEvent_t* e : {&lp->snap_ev[0], &lp->snap_ev[1], &lp->rd_ev}) {
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
       lp_destroy(lp);
       return set_error("hipEventCreate failed"), SKIPM_EDEVICE;
     }

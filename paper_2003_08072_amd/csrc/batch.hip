@@ -118,6 +118,7 @@ class Engine {
     if (hipSetDevice(dev_) != hipSuccess) return *err = "hipSetDevice failed", SKIPM_EDEVICE;
     ab_ = colpass_args_bytes();
     bool ok = hipStreamCreateWithFlags(&cg_st_, hipStreamNonBlocking) == hipSuccess;
+    if (hipEventCreateWithFlags(&cg_ev_, hipEventDisableTiming) != hipSuccess) cg_ev_ = nullptr;
     streams_.assign(nthreads_, nullptr);
     for (auto& st : streams_)
       ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
@@ -198,6 +199,8 @@ class Engine {
     streams_.clear();
     if (cg_st_) (void)hipStreamDestroy(cg_st_);
     cg_st_ = nullptr;
+    if (cg_ev_) (void)hipEventDestroy(cg_ev_);
+    cg_ev_ = nullptr;
   }
 
   void set_fatal(int rc, const std::string& msg) {
@@ -235,6 +238,10 @@ class Engine {
   void worker(int t) {
     (void)hipSetDevice(dev_);
     hipStream_t s = streams_[t];
+    // the end of each phase is awaited by polling this event (a plain stream
+    // synchronisation if it cannot be made)
+    hipEvent_t wev = nullptr;
+    if (hipEventCreateWithFlags(&wev, hipEventDisableTiming) != hipSuccess) wev = nullptr;
     for (;;) {
       Task task;
       {
@@ -249,11 +256,11 @@ class Engine {
       Entry* e = task.e;
       if (task.after_cg) {
         batch_phase_b(e->lp, e->res, &e->b, s);
-        (void)hipStreamSynchronize(s);
+        (void)wait_stream(s, wev);
       }
       if (e->b.active) {
         batch_phase_a(e->lp, e->res, &e->b, s);
-        (void)hipStreamSynchronize(s);
+        (void)wait_stream(s, wev);
       }
       bool finished = false;
       {
@@ -276,6 +283,7 @@ class Engine {
       }
       cv_.notify_all();
     }
+    if (wev) (void)hipEventDestroy(wev);
     thread_exit(s);
   }
 
@@ -354,7 +362,7 @@ class Engine {
     SK_CHECK_HIP(hipGetLastError());
     SK_CHECK_HIP(hipMemcpyAsync(hflags_, dp(flags_off_), 3 * na * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, cg_st_));
-    SK_CHECK_HIP(hipStreamSynchronize(cg_st_));
+    SK_TRY(wait_stream(cg_st_, cg_ev_));
     std::vector<Entry*> keep, finished;
     std::vector<int64_t> kkeep;
     for (int q = 0; q < na; ++q) {
@@ -518,6 +526,7 @@ class Engine {
   bool started_ = false;
   size_t ab_ = 0;
   hipStream_t cg_st_ = nullptr;
+  hipEvent_t cg_ev_ = nullptr;  // the end of each chunk, awaited by polling
   std::vector<hipStream_t> streams_;
   std::vector<std::thread> pool_;
   std::thread exec_;

@@ -69,6 +69,7 @@ struct skipm_lp_s {
   // chunk checks (the host reads one while the next chunk runs)
   double* hsnap[2] = {nullptr, nullptr};
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
+  hipEvent_t rd_ev = nullptr;  // marks the end of a synchronous read of the scalar block
   // false: each chunk is checked with the stream idle (no chunk queued behind
   // the check); set for LPs that the batch and the request server solve on
   // their own threads, where other LPs keep the device busy meanwhile
@@ -116,6 +117,12 @@ struct skipm_lp_s {
 };
 
 namespace skipm {
+
+// Wait for ev (recorded on the awaited stream): polled for a while, then a
+// blocking wait.  wait_stream records ev on st first (a plain stream
+// synchronisation when ev is null).
+int poll_event(hipEvent_t ev);
+int wait_stream(hipStream_t st, hipEvent_t ev);
 
 // ---- one IPM iteration in steps, for the grouped batch engine ----------------
 // Each step is exactly what lp_solve does at that point of an iteration, so an
