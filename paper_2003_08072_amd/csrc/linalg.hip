@@ -405,6 +405,158 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ G, doubl
   }
 }
 
+// The whole inverse at mp = 64 (two 32-column blocks) in one workgroup: the
+// same steps, sums and orders as the launches for any mp (k_chol_step for
+// k = 0 and 1, one level of k_trinv_c / k_trinv_x, k_xtx), with the blocks in
+// LDS between them, so a small LP's factorization is one launch instead of
+// five.  Wave 0 factors the diagonal blocks; the diagonal block's inverse and
+// the solve for the rows below run on waves 0 and 1 side by side.
+__device__ __forceinline__ void chol_factor_block(double (*Dg)[33], double* rdiag,
+                                                  int32_t* __restrict__ fail) {
+  constexpr int NB = 32;
+  const int lane = threadIdx.x;
+  const int ln = lane < NB ? lane : NB - 1;
+  if (threadIdx.x < 64) {
+    double a[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[j] = Dg[ln][j];
+    bool bad = false;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      double s = a[p];
+#pragma unroll
+      for (int q = 0; q < p; ++q) s -= a[q] * readlane_d(a[q], p);
+      double d = readlane_d(s, p);
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1e-300;
+      }
+      const double lpp = sqrt(d);
+      a[p] = ln > p ? s / lpp : (ln == p ? lpp : 0.0);
+    }
+    if (bad && lane == 0) atomicOr(fail, 1);
+    if (lane < NB) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) Dg[lane][j] = a[j];
+    }
+  }
+  __syncthreads();
+  if (lane < NB) rdiag[lane] = 1.0 / Dg[lane][lane];
+  __syncthreads();
+}
+
+// column c of L^{-1} (lane c < 32 of its wave), into X[i][c]
+__device__ __forceinline__ void chol_inverse_block(double (*Dg)[33], const double* rdiag,
+                                                   double (*X)[33], int c) {
+  constexpr int NB = 32;
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < i; ++q) s -= Dg[i][q] * x[q];
+    x[i] = s * rdiag[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) X[i][c] = x[i];
+}
+
+// row r of Y L^{-T} (lane r < 32 of its wave), in place
+__device__ __forceinline__ void chol_solve_row(double (*Dg)[33], const double* rdiag,
+                                               double (*Y)[33], int r) {
+  constexpr int NB = 32;
+  double y[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) y[c] = Y[r][c];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    double s = y[c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) s -= Dg[c][q] * y[q];
+    y[c] = s * rdiag[c];
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) Y[r][c] = y[c];
+}
+
+__global__ __launch_bounds__(256) void k_spd_inverse64(double* __restrict__ G,
+                                                       double* __restrict__ Xb,
+                                                       int32_t* __restrict__ fail) {
+  constexpr int NB = 32;
+  constexpr int64_t mp = 64;
+  __shared__ double D0[NB][NB + 1], D1[NB][NB + 1], Y[NB][NB + 1];
+  __shared__ double X0[NB][NB + 1], X1[NB][NB + 1], T0[NB][NB + 1];
+  __shared__ double rd0[NB], rd1[NB];
+  const int t = threadIdx.x;
+  load_tile<NB>(D0, G, mp, 0, 0);
+  load_tile<NB>(Y, G, mp, NB, 0);
+  load_tile<NB>(D1, G, mp, NB, NB);
+  __syncthreads();
+  // step 0: L00, then X00 (wave 0) and L10 = G10 L00^{-T} (wave 1)
+  chol_factor_block(D0, rd0, fail);
+  if (t < NB) chol_inverse_block(D0, rd0, X0, t);
+  if (t >= 64 && t < 64 + NB) chol_solve_row(D0, rd0, Y, t - 64);
+  __syncthreads();
+  // step 1: G11 - L10 L10^T, L11, X11
+  {
+    TileAcc<NB> td;
+    td.mma_nt(Y, Y);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) D1[td.row(r)][td.col()] -= td.acc[r];
+  }
+  __syncthreads();
+  chol_factor_block(D1, rd1, fail);
+  if (t < NB) chol_inverse_block(D1, rd1, X1, t);
+  __syncthreads();
+  // X10 = -X11 (L10 X00)
+  {
+    TileAcc<NB> tc;
+    tc.mma_nn(Y, X0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T0[tc.row(r)][tc.col()] = tc.acc[r];
+  }
+  __syncthreads();
+  {
+    TileAcc<NB> tx;
+    tx.mma_nn(X1, T0);
+    __syncthreads();  // every wave has read T0
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T0[tx.row(r)][tx.col()] = -tx.acc[r];
+  }
+  __syncthreads();  // T0 = X10
+  // L^{-1} out (the block above the diagonal is not written)
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e % NB, c = e / NB;
+    Xb[r + c * mp] = X0[r][c];
+    Xb[(NB + r) + c * mp] = T0[r][c];
+    Xb[(NB + r) + (NB + c) * mp] = X1[r][c];
+  }
+  // P = X^T X over G: P00 = X00^T X00 + X10^T X10, P10 = X11^T X10, P11 = X11^T X11
+  {
+    TileAcc<NB> p00, p10, p11;
+    p00.mma_tn(X0, X0);
+    p00.mma_tn(T0, T0);
+    p10.mma_tn(X1, T0);
+    p11.mma_tn(X1, X1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = p00.row(r), gj = p00.col();
+      if (gi >= gj) {
+        G[gi + gj * mp] = p00.acc[r];
+        G[gj + gi * mp] = p00.acc[r];
+      }
+      const int64_t hi = NB + p10.row(r), hj = p10.col();
+      G[hi + hj * mp] = p10.acc[r];
+      G[hj + hi * mp] = p10.acc[r];
+      const int64_t ki = NB + p11.row(r), kj = NB + p11.col();
+      if (ki >= kj) {
+        G[ki + kj * mp] = p11.acc[r];
+        G[kj + ki * mp] = p11.acc[r];
+      }
+    }
+  }
+}
+
 // X = L^{-1} from its diagonal blocks by recursive doubling.  At a level with
 // ranges of `half` blocks, pair p joins a = [a0, a0 + half) and the range b that
 // follows it (at most `half` blocks); with X_aa and X_bb already inverses,
@@ -640,6 +792,10 @@ constexpr int kNb = 32;
 
 void launch_spd_inverse(double* G, double* Xb, double* Ct, int64_t mp, int32_t* fail,
                         hipStream_t st) {
+  if (mp == 2 * kNb) {
+    hipLaunchKernelGGL(k_spd_inverse64, dim3(1), dim3(256), 0, st, G, Xb, fail);
+    return;
+  }
   const int T = (int)(mp / kNb);
   for (int k = 0; k < T; ++k) {
     const int rest = T - k - 1;
