@@ -226,10 +226,8 @@ int prologue(skipm_lp_s* lp, hipStream_t st) {
   cp.d2_out = lp->d2;
   SK_TRY(run_colpass(cp, st));
   // r_p = A x - b ; p = b - A (sigma mu / s + d2 r_d)
-  launch_finish(lp->part, 2 * lp->mp, 0, cp.nblk, lp->m, 1.0, lp->b, -1.0, lp->rp,
-                nullptr, st);
-  launch_finish(lp->part, 2 * lp->mp, lp->mp, cp.nblk, lp->m, -1.0, lp->b, 1.0, lp->p,
-                nullptr, st);
+  launch_finish2(lp->part, 2 * lp->mp, cp.nblk, lp->m, 0, 1.0, lp->b, -1.0, lp->rp, lp->mp, -1.0,
+                 lp->b, 1.0, lp->p, st);
   launch_prologue_finalize(lp->m, lp->rp, lp->b, lp->y, lp->red, cp.nblk, lp->sc,
                            lp->origin_pending, st);
   lp->origin_pending = 0;

@@ -623,11 +623,11 @@ __global__ __launch_bounds__(NT) void k_sketch(const TA* __restrict__ A, int64_t
 // Partials are summed over the block axis by 16 block-lanes x 16 rows per
 // workgroup, then the 16 block-lane sums are added in a fixed tree order.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int64_t ldp,
-                                                int64_t off, int nblk, int64_t m, double scale,
-                                                const double* __restrict__ add, double beta,
-                                                double* __restrict__ out,
-                                                const int32_t* __restrict__ done) {
+__device__ __forceinline__ void finish_body(const TP* __restrict__ part, int64_t ldp,
+                                            int64_t off, int nblk, int64_t m, double scale,
+                                            const double* __restrict__ add, double beta,
+                                            double* __restrict__ out,
+                                            const int32_t* __restrict__ done) {
   __shared__ double tile[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + tx;
@@ -660,6 +660,29 @@ __global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int
     if (add) v += beta * add[i];
     out[i] = v;
   }
+}
+
+template <typename TP>
+__global__ __launch_bounds__(256) void k_finish(const TP* __restrict__ part, int64_t ldp,
+                                                int64_t off, int nblk, int64_t m, double scale,
+                                                const double* __restrict__ add, double beta,
+                                                double* __restrict__ out,
+                                                const int32_t* __restrict__ done) {
+  finish_body<TP>(part, ldp, off, nblk, m, scale, add, beta, out, done);
+}
+
+// Two finishes of the same partials in one launch (blockIdx.y picks the set).
+struct FinishSet {
+  int64_t off;
+  double scale;
+  const double* add;
+  double beta;
+  double* out;
+};
+__global__ __launch_bounds__(256) void k_finish2(const double* __restrict__ part, int64_t ldp,
+                                                 int nblk, int64_t m, FinishSet f0, FinishSet f1) {
+  const FinishSet& f = blockIdx.y == 0 ? f0 : f1;
+  finish_body<double>(part, ldp, f.off, nblk, m, f.scale, f.add, f.beta, f.out, nullptr);
 }
 
 // k_finish for the fused CG: out = sum of the partials, and per workgroup the
@@ -1153,6 +1176,15 @@ void launch_finish(const double* part, int64_t ldp, int64_t off, int nblk, int64
   const unsigned blocks = (unsigned)((m + 15) / 16);
   hipLaunchKernelGGL(k_finish<double>, dim3(blocks), dim3(256), 0, st, part, ldp, off, nblk, m,
                      scale, add, beta, out, done);
+}
+
+void launch_finish2(const double* part, int64_t ldp, int nblk, int64_t m, int64_t off0,
+                    double scale0, const double* add0, double beta0, double* out0, int64_t off1,
+                    double scale1, const double* add1, double beta1, double* out1,
+                    hipStream_t st) {
+  const unsigned blocks = (unsigned)((m + 15) / 16);
+  const FinishSet f0{off0, scale0, add0, beta0, out0}, f1{off1, scale1, add1, beta1, out1};
+  hipLaunchKernelGGL(k_finish2, dim3(blocks, 2), dim3(256), 0, st, part, ldp, nblk, m, f0, f1);
 }
 
 }  // namespace skipm

@@ -330,6 +330,11 @@ int colpass_nblk_dot(int64_t lda, int64_t n, int ta);
 void launch_finish(const double* part, int64_t ldp, int64_t off, int nblk, int64_t m,
                    double scale, const double* add, double beta, double* out,
                    const int32_t* done, hipStream_t st);
+// two launch_finish of the same partials (offsets off0 and off1) in one launch
+void launch_finish2(const double* part, int64_t ldp, int nblk, int64_t m, int64_t off0,
+                    double scale0, const double* add0, double beta0, double* out0, int64_t off1,
+                    double scale1, const double* add1, double beta1, double* out1,
+                    hipStream_t st);
 
 // sparse A: CSR for products A v (rows cut into segments of at most kSeg
 // non-zeros), CSC for the column dots and the sketch
