@@ -765,14 +765,16 @@ struct Shape {
   int G, R;
 };
 
-// g32: the column passes also take lane groups of 32 lanes with three vectors
-// each for 64V < lda <= 96V rows (at most a quarter of the lanes idle, where
-// 64 lanes with two vectors leave up to half idle: a pass that is bound by
-// the bytes in flight per CU gets up to half as many again); the sketch keeps
-// the 16 / 64-lane shapes.
+// g32: the column passes also take lane groups of three vectors per lane, of
+// 16 lanes for 32V < lda <= 48V rows and of 32 lanes for 64V < lda <= 96V
+// (at most a third or a quarter of the lanes idle, where 64 lanes with one or
+// two vectors leave up to half idle: a pass that is bound by the bytes in
+// flight per CU gets up to half as many again); the sketch keeps the 16 /
+// 64-lane shapes.
 Shape pick_shape(int64_t lda, int V, bool g32 = false) {
   if (lda <= 16 * V) return {16, 1};
   if (lda <= 32 * V) return {16, 2};
+  if (g32 && lda > 32 * V && lda <= 48 * V) return {16, 3};
   if (g32 && lda > 64 * V && lda <= 96 * V) return {32, 3};
   const int64_t per = 64 * V;
   const int64_t R = (lda + per - 1) / per;
@@ -796,8 +798,9 @@ constexpr int threads_for(int mode, int R, int V, int tc_bytes, int G = 64) {
                   (mode == COL_PROLOGUE ? 32 : 0) + (V == 4 && tc_bytes == 8 ? 8 : 0) +
                   (V == 8 ? 24 * R : 0);
   if (mode == COL_DOT) return 256;
-  // 32-lane groups: 768 threads when three waves per SIMD fit (<= 168 VGPRs)
-  if (G == 32 && est <= 168) return 768;
+  // 16- and 32-lane groups of three vectors: 768 threads when three waves per
+  // SIMD fit (<= 168 VGPRs)
+  if (G < 64 && R == 3 && est <= 168) return 768;
   return est <= 128 ? 1024 : (est <= 256 ? 512 : 256);
 }
 
@@ -835,7 +838,7 @@ int dispatch(const Args& a, int nblk, bool stream, hipStream_t st, hipEvent_t e0
       return 0;                                                           \
     }                                                                     \
   }
-  SK_CASE(16, 1) SK_CASE(16, 2) SK_CASE(32, 3)
+  SK_CASE(16, 1) SK_CASE(16, 2) SK_CASE(16, 3) SK_CASE(32, 3)
   SK_CASE(64, 1) SK_CASE(64, 2) SK_CASE(64, 3) SK_CASE(64, 4)
   SK_CASE(64, 6) SK_CASE(64, 8) SK_CASE(64, 12) SK_CASE(64, 16)
 #undef SK_CASE
@@ -1008,7 +1011,7 @@ Args to_args(const ColPass& c) {
 // The lane-group shapes (G, R) of the grouped launches; Args::shape indexes
 // this table.
 constexpr int kGShapes[][2] = {{16, 1}, {16, 2}, {64, 1},  {64, 2},  {64, 3}, {64, 4},
-                               {64, 6}, {64, 8}, {64, 12}, {64, 16}, {32, 3}};
+                               {64, 6}, {64, 8}, {64, 12}, {64, 16}, {32, 3}, {16, 3}};
 constexpr int kNGShapes = (int)(sizeof(kGShapes) / sizeof(kGShapes[0]));
 
 // Register class of a shape: the shapes of one launch share its register
@@ -1075,7 +1078,7 @@ __global__ __launch_bounds__(NT) void k_colpass_grouped(const Args* __restrict__
     }                                                                                    \
   }
   SK_GCASE(0) SK_GCASE(1) SK_GCASE(2) SK_GCASE(3) SK_GCASE(4) SK_GCASE(5)
-  SK_GCASE(6) SK_GCASE(7) SK_GCASE(8) SK_GCASE(9) SK_GCASE(10)
+  SK_GCASE(6) SK_GCASE(7) SK_GCASE(8) SK_GCASE(9) SK_GCASE(10) SK_GCASE(11)
 #undef SK_GCASE
 }
 

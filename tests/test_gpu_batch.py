@@ -81,9 +81,11 @@ def test_batch_matches_lone_solves(torch, sk):
 
 def test_batch_matches_lone_solves_32_lane_groups(torch, sk):
     """LPs whose column passes take 32-lane groups (FP32 m in (256, 384], FP64
-    m in (128, 192]) next to 64-lane ones, at the batched workload's gap and
+    m in (128, 192]) and 16-lane groups of three vectors (FP32 m in (128, 192],
+    FP64 m in (64, 96]) next to 64-lane ones, at the batched workload's gap and
     column ratio: the grouped launches give each LP its lone solve, bitwise."""
-    shapes = [(300, 9000, "f32"), (160, 4800, "f64"), (384, 7680, "f32"), (200, 4000, "f32")]
+    shapes = [(300, 9000, "f32"), (160, 4800, "f64"), (384, 7680, "f32"), (200, 4000, "f32"),
+              (150, 4500, "f32"), (80, 3200, "f64")]
     lps = [dense_planted(m, n, rng=np.random.default_rng(60 + i), a_dtype=dt, eps_gap=1e-6,
                          seed=300 + i) for i, (m, n, dt) in enumerate(shapes)]
     say(f"batch of {len(lps)} LPs with 32-lane column groups vs lone solves")

@@ -725,12 +725,16 @@ def test_normal_product_at_full_size(torch, sk, cfg1, prec):
 
 @pytest.mark.parametrize("m,prec", [(256, "mixed"), (257, "mixed"), (300, "mixed"),
                                     (384, "mixed"), (385, "mixed"), (128, "fp64"),
-                                    (129, "fp64"), (192, "fp64"), (193, "fp64")])
+                                    (129, "fp64"), (192, "fp64"), (193, "fp64"),
+                                    (128, "mixed"), (129, "mixed"), (192, "mixed"),
+                                    (193, "mixed"), (64, "fp64"), (65, "fp64"), (96, "fp64"),
+                                    (97, "fp64")])
 def test_normal_product_lane_group_shapes(torch, sk, m, prec):
-    """The fused product on both sides of each edge of the 32-lane column
-    groups (three 16-byte vectors per lane: 64V < lda <= 96V rows, V = 4 FP32
-    or 2 FP64 values per vector) and the 64-lane groups around them, over a
-    ragged number of columns, against the oracle's normal matrix."""
+    """The fused product on both sides of each edge of the lane groups with
+    three 16-byte vectors per lane (16 lanes: 32V < lda <= 48V rows; 32 lanes:
+    64V < lda <= 96V; V = 4 FP32 or 2 FP64 values per vector) and the groups
+    around them, over a ragged number of columns, against the oracle's normal
+    matrix."""
     n = 2501
     lp = dense_planted(m, n, rng=np.random.default_rng(m + 7))
     rng = np.random.default_rng(m + 8)
