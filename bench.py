@@ -52,6 +52,9 @@ def parse():
                          "and FP64-residual refinement")
     ap.add_argument("--workers", type=int, default=8,
                     help="config 3: host threads (streams) of lp_solve_batch; config 4: slots")
+    ap.add_argument("--stall-timeout", type=float, default=120.0,
+                    help="config 4: seconds without a finished request before the run "
+                         "reports the requests still out and stops")
     ap.add_argument("--requests", type=int, default=120,
                     help="config 4: requests taken from the head of the arrival trace")
     ap.add_argument("--rate", type=float, default=200.0, help="config 4: arrivals per second")
@@ -508,12 +511,36 @@ def serve_trace(sk, torch, args, trace, lps, scale=1.0):
             time.sleep(delay)
         tickets.append(srv.submit(lp.A, lp.b, lp.c, a_dtype="f32", w=lp.w, seed=lp.seed,
                                   s=args.s, eps_gap=lp.eps_gap, max_outer=1000))
-    done = []
-    for i, t in enumerate(tickets):
-        done.append(srv.wait(t)[0])
-        if (i + 1) % 20 == 0 or i + 1 == len(tickets):
-            print(f"[bench] {i + 1}/{len(tickets)} requests done, "
-                  f"{time.perf_counter() - start:.1f} s", file=sys.stderr, flush=True)
+    # Completions are polled, with a progress line every 20 s and a stall
+    # report: if no request finishes for args.stall_timeout seconds, the
+    # requests still out (state, size, kind, when they started) are printed
+    # and the run ends with an error instead of waiting on.
+    done = [None] * len(tickets)
+    pending = set(range(len(tickets)))
+    last_done = last_line = time.perf_counter()
+    while pending:
+        for i in sorted(pending):
+            if srv.poll(tickets[i]).state == sk.SKIPM_REQ_DONE:
+                done[i] = srv.wait(tickets[i])[0]
+                pending.discard(i)
+                last_done = time.perf_counter()
+        now = time.perf_counter()
+        if now - last_line >= 20.0 or not pending:
+            print(f"[bench] {len(tickets) - len(pending)}/{len(tickets)} requests done, "
+                  f"{now - start:.1f} s", file=sys.stderr, flush=True)
+            last_line = now
+        if pending and now - last_done > args.stall_timeout:
+            for i in sorted(pending):
+                info = srv.poll(tickets[i])
+                state = {sk.SKIPM_REQ_QUEUED: "queued", sk.SKIPM_REQ_RUNNING: "running"}.get(
+                    info.state, str(info.state))
+                print(f"[bench] outstanding request {i}: {state}, {trace[i]['kind']} "
+                      f"{trace[i]['m']} x {trace[i]['n']}, footprint {info.footprint / 1e9:.2f} GB, "
+                      f"started {info.t_start - s_start:.1f} s", file=sys.stderr, flush=True)
+            raise RuntimeError(f"serving trace: no request finished in {args.stall_timeout:g} s "
+                               f"({len(pending)} outstanding)")
+        if pending:
+            time.sleep(0.005)
     stats = srv.stats()
     srv.close()
     lat = [d.latency * 1000.0 for d in done]
